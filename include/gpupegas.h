@@ -1,0 +1,173 @@
+/*
+ * gpupegas.h -- C ABI of the MI355X GPUPEGAS timestep library (libgpupegas.so).
+ *
+ * One simulation ("sim") advances a two-component self-gravitating system on
+ * a uniform periodic-or-outflow 3D grid of cubic cells, following
+ * I. Kulikov, "GPUPEGAS: a new GPU-accelerated hydrodynamical code for
+ * numerical simulation of interacting galaxies" (arXiv:1311.0861):
+ *   - gas: density rho, momentum rho v, total energy rho E, internal energy
+ *     rho eps, with p = (gamma - 1) rho eps (Sec. 2, gas system and EOS);
+ *   - stars/dark matter as Boltzmann moment equations: density n, momentum
+ *     n u, symmetric stress Pi_ij and energy tensor n E_ij = Pi_ij + n u_i u_j
+ *     (Sec. 2, moment system);
+ *   - gravity from Laplace(Phi) = 4 pi G (rho + n) (Sec. 2.3).
+ * One step = Eulerian stage (Sec. 2.1, 2.2: closed-form interface states,
+ * gravity sources) -> Lagrangian FlIC flux stage (Sec. 2.1) -> energy balance
+ * and correctness integrals (Sec. 2.4) -> FFT Poisson with the 27-point symbol
+ * (Sec. 2.3) -> CFL step and diagnostics, all on the GPU; the host only
+ * enqueues work.
+ *
+ * Conventions
+ *   - Every call returns a gp_status; GP_OK is 0, errors are negative.
+ *   - Arrays are dense nx*ny*nz, cell (i,j,k) at index i + nx*(j + ny*k)
+ *     (x fastest).  Cell centres are lo + (i + 1/2) h; h must be equal on the
+ *     three axes (the Poisson symbol has one h).
+ *   - Host pointers (on_device = 0) are copied synchronously.  Device pointers
+ *     (on_device = 1, e.g. a torch tensor's data_ptr()) are read/written in
+ *     stream order on the sim's stream; the library never keeps a caller
+ *     pointer after the call returns.
+ *   - The library owns all device memory of a sim.  A sim is not thread-safe;
+ *     different sims are independent.
+ *   - Device-side failures (non-finite values, rho or n <= 0, p <= 0 or a
+ *     diagonal stress <= 0) are latched on the device and returned by the next
+ *     synchronising call (gp_sync, gp_get_*), never by gp_step itself.
+ */
+#ifndef GPUPEGAS_H
+#define GPUPEGAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GP_OK = 0,
+  GP_E_INVALID = -1,     /* bad argument or configuration                  */
+  GP_E_NOMEM = -2,       /* device allocation failed                       */
+  GP_E_HIP = -3,         /* HIP runtime error (see gp_last_error)          */
+  GP_E_NONFINITE = -4,   /* NaN/Inf appeared in the state                  */
+  GP_E_NONPOSITIVE = -5, /* rho, n, p or a diagonal stress became <= 0     */
+  GP_E_UNSUPPORTED = -6, /* valid request this build does not implement    */
+  GP_E_STATE = -7        /* call out of order (e.g. stages out of sequence) */
+} gp_status;
+
+enum { GP_BC_OUTFLOW = 0, GP_BC_PERIODIC = 1 };
+enum { GP_FP64 = 0, GP_FP32 = 1 };
+
+/* State fields, in this order.  GP_PHI (the potential) is read-only. */
+enum {
+  GP_RHO = 0, GP_MX, GP_MY, GP_MZ, GP_E, GP_EINT,
+  GP_N, GP_QX, GP_QY, GP_QZ,
+  GP_PXX, GP_PXY, GP_PXZ, GP_PYY, GP_PYZ, GP_PZZ,
+  GP_WXX, GP_WXY, GP_WXZ, GP_WYY, GP_WYZ, GP_WZZ,
+  GP_NFIELDS = 22,
+  GP_PHI = 22
+};
+
+/* Stages of one step, for gp_debug_stage, in the order they must run. */
+enum { GP_STAGE_EUL = 0, GP_STAGE_LAG = 1, GP_STAGE_POISSON = 2, GP_STAGE_FINALIZE = 3 };
+
+/* Kernels timed by gp_time_kernels. */
+enum {
+  GP_K_EUL = 0, GP_K_LAG, GP_K_FFT_X_FWD, GP_K_FFT_Y_FWD, GP_K_FFT_Z, GP_K_FFT_Y_INV,
+  GP_K_FFT_X_INV, GP_K_FINALIZE, GP_NKERNELS
+};
+
+typedef struct {
+  int32_t n[3];      /* cells per axis; >= 4.  With G != 0 each must be even and
+                        of the form 2^a 3^b (FFT lengths)                    */
+  int32_t bc[3];     /* GP_BC_OUTFLOW (clamped, zero-gradient) or GP_BC_PERIODIC;
+                        the potential is always periodic                     */
+  double lo[3], hi[3];
+  double gamma;      /* adiabatic index, > 1                                 */
+  double G;          /* gravitational constant; 0 switches gravity off       */
+  double cfl;        /* Courant number C: tau = C h / max signal speed       */
+  double eta;        /* energy-balance threshold; < 0 switches it off        */
+  double fixed_dt;   /* > 0: constant step instead of the CFL step           */
+  double t_end;      /* > 0: the step is clipped so that t never exceeds it  */
+  int32_t precision; /* GP_FP64, or GP_FP32 (rho and n stay FP64; CFL, sums
+                        and the Poisson zero mode stay FP64)                  */
+  int32_t reserved;  /* must be 0                                            */
+} gp_config;
+
+/* One diagnostics record per step (and one for the initial state).  Sums are
+ * h^3-weighted over the grid, accumulated in FP64 in a fixed order. */
+typedef struct {
+  int64_t step;
+  double t;
+  double dt;          /* the step the next update will use                   */
+  double mass_gas, mass_bme;
+  double mom[3];      /* total momentum, gas + stars                          */
+  double e_gas;       /* sum of rho E                                         */
+  double e_bme;       /* sum of tr(n E_ij) / 2                                */
+  double e_pot;       /* (1/2) sum (rho + n) Phi                              */
+  double kappa_gas;   /* Sec. 2.4 integral, measured before energy balance    */
+  double kappa_bme;
+  double outflow_gas; /* cumulative mass that left through outflow faces      */
+  double outflow_bme;
+  double n_sync_gas;  /* cells whose internal energy was re-synchronised      */
+  double n_sync_bme;  /* cells with at least one re-synchronised stress       */
+  uint32_t err;       /* latched device error bits up to this record          */
+  uint32_t pad;
+} gp_diag;
+
+typedef struct gp_sim gp_sim;
+
+/* Create a sim.  hip_stream: a hipStream_t to run on, or NULL for a stream
+ * the sim creates and owns.  On success *out receives the handle, which the
+ * caller releases with gp_destroy.  Returns GP_E_INVALID for a bad config,
+ * GP_E_UNSUPPORTED for FFT lengths the kernels do not handle, GP_E_NOMEM. */
+gp_status gp_create(const gp_config *cfg, void *hip_stream, gp_sim **out);
+gp_status gp_destroy(gp_sim *sim);
+
+/* Copy one state field in (set) or out (get).  dtype GP_FP64 or GP_FP32 is
+ * the caller's element type; values convert to the sim's storage type.
+ * Setting any field invalidates Phi and tau; they are recomputed from the
+ * state by the next gp_step, gp_debug_stage or gp_get_field(GP_PHI). */
+gp_status gp_set_field(gp_sim *sim, int32_t field, const void *src, int32_t dtype,
+                       int32_t on_device);
+gp_status gp_get_field(gp_sim *sim, int32_t field, void *dst, int32_t dtype,
+                       int32_t on_device);
+
+/* Enqueue nsteps full steps (asynchronous).  Argument errors return at once;
+ * device errors are latched for the next synchronising call. */
+gp_status gp_step(gp_sim *sim, int32_t nsteps);
+
+/* Wait for the sim's stream; returns the latched device error, if any. */
+gp_status gp_sync(gp_sim *sim);
+
+/* Copy the most recent min(max, available) diagnostics records, oldest first.
+ * The device keeps the last 4096 records. */
+gp_status gp_get_diag(gp_sim *sim, gp_diag *out, int32_t max, int32_t *count);
+
+/* Set (t, step) of the current state, e.g. when resuming from saved fields. */
+gp_status gp_set_time(gp_sim *sim, double t, int64_t step);
+gp_status gp_get_time(gp_sim *sim, double *t, double *dt, int64_t *step);
+
+/* Run one stage of a step (GP_STAGE_*), in order, for per-stage checks.
+ * Between GP_STAGE_EUL and GP_STAGE_LAG, gp_get_field returns the
+ * post-Eulerian fields.  GP_E_STATE if called out of order. */
+gp_status gp_debug_stage(gp_sim *sim, int32_t stage);
+
+/* Run nsteps steps kernel by kernel with HIP events around every launch and
+ * return the mean duration in milliseconds of each GP_K_* kernel in ms[0..]
+ * (max entries).  The state advances as with gp_step. */
+gp_status gp_time_kernels(gp_sim *sim, int32_t nsteps, double *ms, int32_t max);
+
+/* Use a captured HIP graph per step (default on).  Results are identical. */
+gp_status gp_use_graph(gp_sim *sim, int32_t enable);
+
+const char *gp_status_str(gp_status s);
+const char *gp_last_error(const gp_sim *sim);
+
+/* Bytes the kernels move per cell per step by design (reads + writes of the
+ * state, potential and spectrum), for the roofline; see the source for the
+ * per-kernel split.  kernel = GP_K_* or -1 for the whole step. */
+double gp_algorithmic_bytes_per_cell(const gp_sim *sim, int32_t kernel);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPUPEGAS_H */

@@ -1,0 +1,392 @@
+// Lagrangian (FlIC) stage of one GPUPEGAS step (Kulikov, arXiv:1311.0861,
+// Sec. 2.1, Fig. "lagrange"), with the end-of-step cell work fused in:
+//   - every quantity f obeys (f^{n+1} - f^n)/tau + sum_d (F_{d+} - F_{d-})/h = 0,
+//     F on a face = (1/4) sum over its 4 corners of v_d f^+, f^+ the upwind
+//     cell value for that corner's velocity; a corner velocity is the mean of
+//     the 8 cells sharing the vertex (post-Eulerian m/rho for the gas, q/n for
+//     the stars); written per cell as A+ f_c + A- f_{c+e_d};
+//   - correctness integrals kappa (Sec. 2.4) measured on the advected state;
+//   - energy balance: e := E - |m|^2/(2 rho) where that exceeds eta E, and
+//     each diagonal stress Pi_dd := W_dd - q_d^2/n where that exceeds eta W_dd;
+//   - s = rho + n for the Poisson solve, and per-block FP64 partial sums for
+//     the CFL step and the diagnostics.
+// rho and n are advected in FP64 with each face flux formed by the same
+// operations from both sides, so mass telescopes to rounding in both
+// precisions.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace gp {
+
+struct CellAcc {
+  double v[kNP];
+  uint32_t err;
+};
+
+__device__ __forceinline__ void acc_init(CellAcc& a) {
+#pragma unroll
+  for (int s = 0; s < kNP; s++) a.v[s] = 0.0;
+  a.err = 0u;
+}
+
+// Diagnostics terms of one cell of a finished state.
+template <typename T>
+__device__ __forceinline__ void cell_terms(CellAcc& a, double rho, double n, const T m[3], T E, T e,
+                                           const T q[3], const T P[6], const T W[6], T gamma) {
+  const T rr = T(rho), rn = T(n);
+  const T p = (gamma - T(1)) * e;
+  const T cs = sqrt(fmax(gamma * p / rr, T(0)));
+  T sp = T(0);
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const T cg = fabs(m[d] / rr) + cs;
+    const T cb = fabs(q[d] / rn) + sqrt(fmax(T(3) * P[sym(d, d)] / rn, T(0)));
+    sp = fmax(sp, fmax(cg, cb));
+  }
+  a.v[P_SPEED] = fmax(a.v[P_SPEED], (double)sp);
+  a.v[P_MGAS] += rho;
+  a.v[P_MBME] += n;
+#pragma unroll
+  for (int d = 0; d < 3; d++) a.v[P_MOMX + d] += (double)m[d] + (double)q[d];
+  a.v[P_EGAS] += (double)E;
+  a.v[P_EBME] += 0.5 * ((double)W[0] + (double)W[3] + (double)W[5]);
+
+  uint32_t err = 0u;
+  bool fin = isfinite(rho) && isfinite(n) && isfinite(E) && isfinite(e);
+#pragma unroll
+  for (int d = 0; d < 3; d++) fin = fin && isfinite(m[d]) && isfinite(q[d]);
+#pragma unroll
+  for (int s = 0; s < 6; s++) fin = fin && isfinite(P[s]) && isfinite(W[s]);
+  if (!fin) err |= ERR_NONFINITE;
+  if (!(rho > 0.0) || !(n > 0.0)) err |= ERR_DENSITY;
+  if (!(p > T(0))) err |= ERR_PRESSURE;
+  if (!(P[0] > T(0)) || !(P[3] > T(0)) || !(P[5] > T(0))) err |= ERR_STRESS;
+  a.err |= err;
+}
+
+// Correctness integrands of Sec. 2.4 and the thermal tensor T = W - q q / n.
+template <typename T>
+__device__ __forceinline__ void kappa_terms(double rho, double n, const T m[3], T E, T e, const T q[3],
+                                            const T P[6], const T W[6], T& ekin, T Tt[6], T& kg,
+                                            T& kb) {
+  const T rr = T(rho), rn = T(n);
+  ekin = (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / (T(2) * rr);
+  kg = fabs(E - e - ekin);
+  kb = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; a++)
+#pragma unroll
+    for (int b = a; b < 3; b++) {
+      const int s = sym(a, b);
+      Tt[s] = W[s] - q[a] * q[b] / rn;
+      kb += fabs(Tt[s] - P[s]);
+    }
+}
+
+// Fixed-order block reduction of the cell accumulators into one partial row.
+__device__ __forceinline__ void block_reduce_store(CellAcc& a, double* row) {
+  __shared__ double red[(kTX * kTY) / 64][kNP];
+  const int tid = threadIdx.x + kTX * threadIdx.y;
+  const int lane = tid & 63, wave = tid >> 6;
+  a.v[P_ERR] = (double)a.err;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a.v[P_SPEED] = fmax(a.v[P_SPEED], __shfl_xor(a.v[P_SPEED], off, 64));
+#pragma unroll
+    for (int s = P_MGAS; s < P_ERR; s++) a.v[s] += __shfl_xor(a.v[s], off, 64);
+    a.err |= (uint32_t)__shfl_xor((int)a.err, off, 64);
+  }
+  a.v[P_ERR] = (double)a.err;
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < kNP; s++) red[wave][s] = a.v[s];
+  }
+  __syncthreads();
+  if (tid < kNP) {
+    constexpr int nw = (kTX * kTY) / 64;
+    double v = red[0][tid];
+    if (tid == P_SPEED) {
+      for (int w = 1; w < nw; w++) v = fmax(v, red[w][tid]);
+    } else if (tid == P_ERR) {
+      uint32_t e = (uint32_t)v;
+      for (int w = 1; w < nw; w++) e |= (uint32_t)red[w][tid];
+      v = (double)e;
+    } else {
+      for (int w = 1; w < nw; w++) v += red[w][tid];
+    }
+    row[tid] = v;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T mul_rn(T a, T b);
+template <>
+__device__ __forceinline__ double mul_rn<double>(double a, double b) {
+  return __dmul_rn(a, b);
+}
+template <>
+__device__ __forceinline__ float mul_rn<float>(float a, float b) {
+  return __fmul_rn(a, b);
+}
+
+// Face flux of an FP64 density; both cells sharing the face evaluate exactly
+// this expression with the same operands.
+__device__ __forceinline__ double face_flux(double ap, double am, double fl, double fr) {
+  return __fma_rn(ap, fl, __dmul_rn(am, fr));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T> eul, Fields<T> out,
+                                                         T* __restrict__ s_out, Grid g, Phys ph,
+                                                         const DevScalars* __restrict__ sc,
+                                                         double* __restrict__ partials) {
+  const int i = blockIdx.x * kTX + threadIdx.x;
+  const int j = blockIdx.y * kTY + threadIdx.y;
+  const int k = blockIdx.z;
+  const bool active = (i < g.nx) && (j < g.ny);
+  CellAcc acc;
+  acc_init(acc);
+  if (active) {
+    const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
+    const double rd = sc->dt / g.h;
+    const T r = (T)rd;
+    const T gamma = (T)ph.gamma;
+    const size_t xi[3] = {(size_t)bc_index(i - 1, g.nx, g.bc[0]), (size_t)i,
+                          (size_t)bc_index(i + 1, g.nx, g.bc[0])};
+    const size_t yj[3] = {nx * bc_index(j - 1, g.ny, g.bc[1]), nx * j,
+                          nx * bc_index(j + 1, g.ny, g.bc[1])};
+    const size_t zk[3] = {nxy * bc_index(k - 1, g.nz, g.bc[2]), nxy * k,
+                          nxy * bc_index(k + 1, g.nz, g.bc[2])};
+    const size_t c = xi[1] + yj[1] + zk[1];
+
+    // corner velocities: corner s = sx + 2 sy + 4 sz sits at (i-1/2+sx, ...);
+    // each accumulates its 8 cells in the same (z, y, x) order from every cell
+    T cg[8][3], cb[8][3];
+#pragma unroll
+    for (int s = 0; s < 8; s++)
+#pragma unroll
+      for (int d = 0; d < 3; d++) cg[s][d] = cb[s][d] = T(0);
+#pragma unroll
+    for (int oz = 0; oz < 3; oz++)
+#pragma unroll
+      for (int oy = 0; oy < 3; oy++)
+#pragma unroll
+        for (int ox = 0; ox < 3; ox++) {
+          const size_t cc = xi[ox] + yj[oy] + zk[oz];
+          const T ir = T(1) / (T)cur.rho[cc];
+          const T in = T(1) / (T)cur.nb[cc];
+          T vg[3], vb[3];
+#pragma unroll
+          for (int d = 0; d < 3; d++) {
+            vg[d] = mul_rn(eul.o[oidx(GP_MX + d)][cc], ir);
+            vb[d] = mul_rn(eul.o[oidx(GP_QX + d)][cc], in);
+          }
+#pragma unroll
+          for (int sz = 0; sz < 2; sz++)
+#pragma unroll
+            for (int sy = 0; sy < 2; sy++)
+#pragma unroll
+              for (int sx = 0; sx < 2; sx++) {
+                // cell offset o - 1 lies in corner s's 2x2x2 block iff s - 1 <= o - 1 <= s
+                if (ox - 1 >= sx - 1 && ox - 1 <= sx && oy - 1 >= sy - 1 && oy - 1 <= sy &&
+                    oz - 1 >= sz - 1 && oz - 1 <= sz) {
+                  const int s = sx + 2 * sy + 4 * sz;
+#pragma unroll
+                  for (int d = 0; d < 3; d++) {
+                    cg[s][d] += vg[d];
+                    cb[s][d] += vb[d];
+                  }
+                }
+              }
+        }
+    // A+ / A- on the six faces: [axis][side], side 0 = minus face, 1 = plus face
+    T apg[3][2], amg[3][2], apb[3][2], amb[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+      for (int side = 0; side < 2; side++) {
+        T pg = T(0), ng = T(0), pb = T(0), nb = T(0);
+#pragma unroll
+        for (int s = 0; s < 8; s++) {
+          if (((s >> d) & 1) != side) continue;
+          const T vgd = cg[s][d] * T(0.125), vbd = cb[s][d] * T(0.125);
+          pg += fmax(vgd, T(0));
+          ng += fmin(vgd, T(0));
+          pb += fmax(vbd, T(0));
+          nb += fmin(vbd, T(0));
+        }
+        apg[d][side] = pg * T(0.25);
+        amg[d][side] = ng * T(0.25);
+        apb[d][side] = pb * T(0.25);
+        amb[d][side] = nb * T(0.25);
+      }
+
+    // neighbour indices along each axis
+    const size_t cmn[3] = {xi[0] + yj[1] + zk[1], xi[1] + yj[0] + zk[1], xi[1] + yj[1] + zk[0]};
+    const size_t cpl[3] = {xi[2] + yj[1] + zk[1], xi[1] + yj[2] + zk[1], xi[1] + yj[1] + zk[2]};
+    const int ci[3] = {i, j, k};
+    const int nn[3] = {g.nx, g.ny, g.nz};
+
+    // densities: explicit FP64 face fluxes, and the boundary outflow
+    double divr = 0.0, divn = 0.0, outg = 0.0, outb = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const double Fp = face_flux(apg[d][1], amg[d][1], cur.rho[c], cur.rho[cpl[d]]);
+      const double Fm = face_flux(apg[d][0], amg[d][0], cur.rho[cmn[d]], cur.rho[c]);
+      const double Gp = face_flux(apb[d][1], amb[d][1], cur.nb[c], cur.nb[cpl[d]]);
+      const double Gm = face_flux(apb[d][0], amb[d][0], cur.nb[cmn[d]], cur.nb[c]);
+      divr += Fp - Fm;
+      divn += Gp - Gm;
+      if (g.bc[d] == GP_BC_OUTFLOW) {
+        if (ci[d] == nn[d] - 1) { outg += Fp; outb += Gp; }
+        if (ci[d] == 0) { outg -= Fm; outb -= Gm; }
+      }
+    }
+    const double rho = cur.rho[c] - rd * divr;
+    const double n = cur.nb[c] - rd * divn;
+
+    // other fields: 7-point stencil with the same face coefficients
+    T wcg = T(1), wcb = T(1), wpg[3], wmg[3], wpb[3], wmb[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      wcg -= r * (apg[d][1] - amg[d][0]);
+      wcb -= r * (apb[d][1] - amb[d][0]);
+      wpg[d] = -r * amg[d][1];
+      wmg[d] = r * apg[d][0];
+      wpb[d] = -r * amb[d][1];
+      wmb[d] = r * apb[d][0];
+    }
+    T nv[kNO];
+#pragma unroll
+    for (int f = 0; f < kNO; f++) {
+      const T* src = eul.o[f];
+      const bool gas = f < oidx(GP_N + 1);  // mx my mz E e
+      const T wc = gas ? wcg : wcb;
+      T v = wc * src[c];
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        v += (gas ? wpg[d] : wpb[d]) * src[cpl[d]];
+        v += (gas ? wmg[d] : wmb[d]) * src[cmn[d]];
+      }
+      nv[f] = v;
+    }
+
+    // energy balance and correctness integrals
+    T m[3] = {nv[oidx(GP_MX)], nv[oidx(GP_MY)], nv[oidx(GP_MZ)]};
+    T q[3] = {nv[oidx(GP_QX)], nv[oidx(GP_QY)], nv[oidx(GP_QZ)]};
+    T E = nv[oidx(GP_E)], e = nv[oidx(GP_EINT)];
+    T P[6], W[6];
+#pragma unroll
+    for (int s = 0; s < 6; s++) {
+      P[s] = nv[oidx(GP_PXX + s)];
+      W[s] = nv[oidx(GP_WXX + s)];
+    }
+    T ekin, Tt[6], kg, kb;
+    kappa_terms(rho, n, m, E, e, q, P, W, ekin, Tt, kg, kb);
+    acc.v[P_KGAS] += (double)kg;
+    acc.v[P_KBME] += (double)kb;
+    if (ph.eta >= 0.0) {
+      const T eta = (T)ph.eta;
+      const T et = E - ekin;
+      if (et > eta * E) {
+        e = et;
+        acc.v[P_SYNCG] += 1.0;
+      }
+      bool any = false;
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        const int s = sym(d, d);
+        if (Tt[s] > eta * W[s]) {
+          P[s] = Tt[s];
+          any = true;
+        }
+      }
+      if (any) acc.v[P_SYNCB] += 1.0;
+    }
+    acc.v[P_OUTG] += outg;
+    acc.v[P_OUTB] += outb;
+
+    out.rho[c] = rho;
+    out.nb[c] = n;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      out.o[oidx(GP_MX + d)][c] = m[d];
+      out.o[oidx(GP_QX + d)][c] = q[d];
+    }
+    out.o[oidx(GP_E)][c] = E;
+    out.o[oidx(GP_EINT)][c] = e;
+#pragma unroll
+    for (int s = 0; s < 6; s++) {
+      out.o[oidx(GP_PXX + s)][c] = P[s];
+      out.o[oidx(GP_WXX + s)][c] = W[s];
+    }
+    s_out[c] = (T)(rho + n);
+    cell_terms(acc, rho, n, m, E, e, q, P, W, gamma);
+  }
+  const size_t blin = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+  block_reduce_store(acc, partials + blin * kNP);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTX* kTY) k_init_partials(Fields<T> cur, T* __restrict__ s_out, Grid g,
+                                                            Phys ph, double* __restrict__ partials) {
+  const int i = blockIdx.x * kTX + threadIdx.x;
+  const int j = blockIdx.y * kTY + threadIdx.y;
+  const int k = blockIdx.z;
+  CellAcc acc;
+  acc_init(acc);
+  if (i < g.nx && j < g.ny) {
+    const size_t c = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+    const double rho = cur.rho[c], n = cur.nb[c];
+    T m[3], q[3], P[6], W[6];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      m[d] = cur.o[oidx(GP_MX + d)][c];
+      q[d] = cur.o[oidx(GP_QX + d)][c];
+    }
+#pragma unroll
+    for (int s = 0; s < 6; s++) {
+      P[s] = cur.o[oidx(GP_PXX + s)][c];
+      W[s] = cur.o[oidx(GP_WXX + s)][c];
+    }
+    const T E = cur.o[oidx(GP_E)][c], e = cur.o[oidx(GP_EINT)][c];
+    T ekin, Tt[6], kg, kb;
+    kappa_terms(rho, n, m, E, e, q, P, W, ekin, Tt, kg, kb);
+    acc.v[P_KGAS] += (double)kg;
+    acc.v[P_KBME] += (double)kb;
+    s_out[c] = (T)(rho + n);
+    cell_terms(acc, rho, n, m, E, e, q, P, W, (T)ph.gamma);
+  }
+  const size_t blin = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+  block_reduce_store(acc, partials + blin * kNP);
+}
+
+template <typename T>
+void launch_lagrangian(const Fields<T>& cur, const Fields<T>& eul, const Fields<T>& out, T* s,
+                       const Grid& g, const Phys& ph, const DevScalars* sc, double* partials,
+                       hipStream_t st) {
+  dim3 block(kTX, kTY, 1);
+  dim3 grid((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY, g.nz);
+  k_lagrangian<T><<<grid, block, 0, st>>>(cur, eul, out, s, g, ph, sc, partials);
+}
+
+template <typename T>
+void launch_init_partials(const Fields<T>& cur, T* s, const Grid& g, const Phys& ph, double* partials,
+                          hipStream_t st) {
+  dim3 block(kTX, kTY, 1);
+  dim3 grid((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY, g.nz);
+  k_init_partials<T><<<grid, block, 0, st>>>(cur, s, g, ph, partials);
+}
+
+template void launch_lagrangian<double>(const Fields<double>&, const Fields<double>&, const Fields<double>&,
+                                        double*, const Grid&, const Phys&, const DevScalars*, double*,
+                                        hipStream_t);
+template void launch_lagrangian<float>(const Fields<float>&, const Fields<float>&, const Fields<float>&,
+                                       float*, const Grid&, const Phys&, const DevScalars*, double*,
+                                       hipStream_t);
+template void launch_init_partials<double>(const Fields<double>&, double*, const Grid&, const Phys&,
+                                           double*, hipStream_t);
+template void launch_init_partials<float>(const Fields<float>&, float*, const Grid&, const Phys&, double*,
+                                          hipStream_t);
+
+}  // namespace gp

@@ -1,0 +1,135 @@
+// End-of-step reductions of one GPUPEGAS step: the CFL step and the
+// diagnostics record, from the per-block FP64 partials of the cell kernels and
+// the spectral potential-energy partials of the Poisson z pass.
+//
+// The paper gives no CFL rule; the step is C h / (max over cells and axes of
+// the fastest signal speed of either component: |v_d| + sqrt(gamma p / rho) for
+// the gas, |u_d| + sqrt(3 Pi_dd / n) for the stars -- the largest eigenvalues of
+// the Eulerian systems of Sec. 2.1 and 2.2 shifted by the advection speed).
+// Reductions run in a fixed order (strided per-thread sums, then a fixed tree),
+// so results do not depend on scheduling.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace gp {
+
+constexpr int kRedThreads = 256;
+constexpr int kLanesPerSlot = kRedThreads / kNP;  // 16 lanes per partial slot
+
+__device__ __forceinline__ double combine(int slot, double a, double b) {
+  if (slot == P_SPEED) return fmax(a, b);
+  if (slot == P_ERR) return (double)((uint32_t)a | (uint32_t)b);
+  return a + b;
+}
+
+// rows [r0, r1) of a [row][kNP] table -> one kNP row (fixed order).
+__device__ void reduce_rows(const double* in, int r0, int r1, double* out) {
+  __shared__ double red[kRedThreads];
+  const int slot = threadIdx.x % kNP, lane = threadIdx.x / kNP;
+  double v = 0.0;
+  for (int r = r0 + lane; r < r1; r += kLanesPerSlot) v = combine(slot, v, in[(size_t)r * kNP + slot]);
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x < kNP) {
+    double a = red[threadIdx.x];
+    for (int l = 1; l < kLanesPerSlot; l++) a = combine(threadIdx.x, a, red[l * kNP + threadIdx.x]);
+    out[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_reduce_rows(const double* __restrict__ in, int nrows,
+                                                             double* __restrict__ out) {
+  const int chunk = (nrows + gridDim.x - 1) / gridDim.x;
+  const int r0 = min(nrows, (int)blockIdx.x * chunk), r1 = min(nrows, r0 + chunk);
+  reduce_rows(in, r0, r1, out + (size_t)blockIdx.x * kNP);
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restrict__ rows, int nrows,
+                                                          const double* __restrict__ epot, int nepot, Grid g,
+                                                          Phys ph, double epot_scale, int advanced,
+                                                          DevScalars* __restrict__ sc, gp_diag* __restrict__ ring) {
+  __shared__ double tot[kNP];
+  __shared__ double ered[kRedThreads];
+  reduce_rows(rows, 0, nrows, tot);
+  double e = 0.0;
+  for (int b = threadIdx.x; b < nepot; b += kRedThreads) e += epot[b];
+  ered[threadIdx.x] = e;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) ered[threadIdx.x] += ered[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+
+  const double h = g.h, h3 = h * h * h;
+  if (advanced) {
+    sc->outflow_gas += sc->dt * h * h * tot[P_OUTG];
+    sc->outflow_bme += sc->dt * h * h * tot[P_OUTB];
+    sc->t += sc->dt;
+    sc->step += 1;
+  }
+  uint32_t err = (uint32_t)tot[P_ERR];
+  double dt;
+  if (ph.fixed_dt > 0.0) {
+    dt = ph.fixed_dt;
+  } else if (tot[P_SPEED] > 0.0) {
+    dt = ph.cfl * h / tot[P_SPEED];
+  } else {
+    dt = 0.0;
+    err |= ERR_NOSPEED;
+  }
+  if (ph.t_end > 0.0) dt = fmin(dt, fmax(ph.t_end - sc->t, 0.0));
+  sc->dt = dt;
+  sc->err |= err;
+
+  gp_diag d;
+  d.step = sc->step;
+  d.t = sc->t;
+  d.dt = dt;
+  d.mass_gas = h3 * tot[P_MGAS];
+  d.mass_bme = h3 * tot[P_MBME];
+  d.mom[0] = h3 * tot[P_MOMX];
+  d.mom[1] = h3 * tot[P_MOMY];
+  d.mom[2] = h3 * tot[P_MOMZ];
+  d.e_gas = h3 * tot[P_EGAS];
+  d.e_bme = h3 * tot[P_EBME];
+  d.e_pot = 0.5 * h3 * epot_scale * ered[0];
+  d.kappa_gas = h3 * tot[P_KGAS];
+  d.kappa_bme = h3 * tot[P_KBME];
+  d.outflow_gas = sc->outflow_gas;
+  d.outflow_bme = sc->outflow_bme;
+  d.n_sync_gas = advanced ? tot[P_SYNCG] : 0.0;
+  d.n_sync_bme = advanced ? tot[P_SYNCB] : 0.0;
+  d.err = sc->err;
+  d.pad = 0u;
+  ring[sc->ndiag % kDiagCap] = d;
+  sc->ndiag += 1;
+}
+
+void launch_finalize(const double* partials, int nrows, double* scratch, int nscratch,
+                     const double* epot_partials, int nepot, const Grid& g, const Phys& ph,
+                     double epot_scale, int advanced, DevScalars* sc, gp_diag* ring, hipStream_t st) {
+  k_reduce_rows<<<nscratch, kRedThreads, 0, st>>>(partials, nrows, scratch);
+  k_finalize<<<1, kRedThreads, 0, st>>>(scratch, nscratch, epot_partials, nepot, g, ph, epot_scale, advanced,
+                                       sc, ring);
+}
+
+template <typename D, typename S>
+__global__ void k_convert(D* __restrict__ dst, const S* __restrict__ src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (D)src[i];
+}
+
+template <typename D, typename S>
+void launch_convert(D* dst, const S* src, size_t n, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+  k_convert<D, S><<<(unsigned)blocks, 256, 0, st>>>(dst, src, n);
+}
+
+template void launch_convert<double, double>(double*, const double*, size_t, hipStream_t);
+template void launch_convert<double, float>(double*, const float*, size_t, hipStream_t);
+template void launch_convert<float, double>(float*, const double*, size_t, hipStream_t);
+template void launch_convert<float, float>(float*, const float*, size_t, hipStream_t);
+
+}  // namespace gp
