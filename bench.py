@@ -29,6 +29,9 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=20, help="steps timed kernel by kernel")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run the library's plain copy kernel over MIB MiB of FP64 data "
+                         "(calibrates HBM counters) and exit")
     ap.add_argument("--traffic", default=None,
                     help="JSON with measured HBM bytes per launch of the dominant kernel")
     return ap.parse_args()
@@ -48,6 +51,24 @@ def rel_l1_max(got, ref):
     return worst, where
 
 
+def copy_probe(mib):
+    """Run the library's device copy kernel (set_field from a device FP64
+    tensor into an FP64 sim: reads and writes 8 bytes per cell) 5 times."""
+    import torch
+    from paper_1311_0861_amd import gpupegas as gp
+    from paper_1311_0861_amd import workloads as W
+    ncell = mib * 1024 * 1024 // 8
+    nz = ncell // (64 * 64)
+    cfg = W.base_config((64, 64, nz), lo=(0.0, 0.0, 0.0), hi=(64.0, 64.0, float(nz)), G=0.0)
+    sim = gp.Sim(cfg)
+    src = torch.ones(nz, 64, 64, dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        sim.set_field("rho", src)
+    sim.sync()
+    print(json.dumps({"copy_probe_bytes_read": 8 * 64 * 64 * nz, "copy_probe_bytes_written": 8 * 64 * 64 * nz,
+                      "launches": 5}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -60,6 +81,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     n = args.n
     cfg_cpu, st_cpu = W.two_disk_collision(n, device="cpu", precision=args.precision)
     ncell = n ** 3

@@ -5,8 +5,6 @@ field after 100 steps.  Rounding differs (FMA contraction and reciprocal
 forms on the GPU), so per-stage comparisons use 1e-12 and multi-step runs
 1e-9.
 """
-import math
-
 import numpy as np
 import pytest
 
@@ -222,4 +220,3 @@ def test_fp32_input_conversion(gp, W):
     sim.set_state({k: v.to("cuda", torch.float32) for k, v in st.items()})
     got = sim.get_field("rho").cpu().numpy()
     np.testing.assert_array_equal(got, st["rho"].float().double().numpy())
-    del math
