@@ -70,7 +70,7 @@ enum { GP_STAGE_EUL = 0, GP_STAGE_LAG = 1, GP_STAGE_POISSON = 2, GP_STAGE_FINALI
 
 /* Kernels timed by gp_time_kernels. */
 enum {
-  GP_K_EUL = 0, GP_K_LAG, GP_K_FFT_X_FWD, GP_K_FFT_Y_FWD, GP_K_FFT_Z, GP_K_FFT_Y_INV,
+  GP_K_EUL = 0, GP_K_VERTEX, GP_K_LAG, GP_K_FFT_X_FWD, GP_K_FFT_Y_FWD, GP_K_FFT_Z, GP_K_FFT_Y_INV,
   GP_K_FFT_X_INV, GP_K_FINALIZE, GP_NKERNELS
 };
 

@@ -83,4 +83,26 @@ inline unsigned cell_blocks(const Grid& g) {
   return ((g.nx + kTX - 1) / kTX) * ((g.ny + kTY - 1) / kTY) * g.nz;
 }
 
+// The hardware hands consecutive workgroups of a 1D grid to the 8 XCDs in
+// turn, and each XCD has its own L2.  Remap the dispatch index so that XCD x
+// gets one contiguous range of tiles (a slab of z planes, swept in order):
+// tiles that share y/z halos then run on the same XCD close in time.
+constexpr int kNumXcd = 8;
+struct TileId {
+  int tx, ty, tz;   // tile coordinates, x fastest
+  unsigned lin;     // linear tile index (row of the partial-sum table)
+};
+__device__ __forceinline__ TileId xcd_tile(int ntx, int nty) {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned q = nb / kNumXcd, rem = nb % kNumXcd;
+  const unsigned x = b % kNumXcd, idx = b / kNumXcd;
+  const unsigned v = x * q + min(x, rem) + idx;
+  TileId t;
+  t.lin = v;
+  t.tx = v % ntx;
+  t.ty = (v / ntx) % nty;
+  t.tz = v / (ntx * nty);
+  return t;
+}
+
 }  // namespace gp

@@ -35,6 +35,8 @@ struct gp_sim {
   double* dens[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][rho, n]
   void* cur[kNO] = {};
   void* tmp[kNO] = {};
+  void* vtx = nullptr;   // corner velocities, 6 components
+  size_t vstride = 0;
   void* s = nullptr;
   void* phi = nullptr;
   void* spec = nullptr;
@@ -225,9 +227,12 @@ void enqueue_stage(gp_sim* s, int stage, Timer* tm) {
       });
       break;
     case GP_STAGE_LAG:
+      timed(GP_K_VERTEX, [&] {
+        launch_vertex<T>(fields_tmp<T>(s), static_cast<T*>(s->vtx), s->vstride, s->g, s->st);
+      });
       timed(GP_K_LAG, [&] {
-        launch_lagrangian<T>(fields_cur<T>(s), fields_tmp<T>(s), fields_next<T>(s), static_cast<T*>(s->s), s->g,
-                             s->ph, s->sc, s->partials, s->st);
+        launch_lagrangian<T>(fields_cur<T>(s), fields_tmp<T>(s), fields_next<T>(s), static_cast<const T*>(s->vtx),
+                             s->vstride, static_cast<T*>(s->s), s->g, s->ph, s->sc, s->partials, s->st);
       });
       s->parity ^= 1;
       break;
@@ -412,6 +417,8 @@ gp_status gp_create(const gp_config* cfg, void* hip_stream, gp_sim** out) {
     s->cur[o] = dalloc(s, nc * es, &st);
     s->tmp[o] = dalloc(s, nc * es, &st);
   }
+  s->vstride = (((size_t)(s->g.nx + 1) * (s->g.ny + 1) * (s->g.nz + 1)) + 63) / 64 * 64;
+  s->vtx = dalloc(s, 6 * s->vstride * es, &st);
   s->s = dalloc(s, nc * es, &st);
   s->phi = dalloc(s, nc * es, &st);
   s->staging = dalloc(s, nc * sizeof(double), &st);
@@ -528,7 +535,23 @@ gp_status gp_get_field(gp_sim* s, int32_t field, void* dst, int32_t dtype, int32
   const void* src = field_ptr(s, field, &src_double);
   const bool dst_double = dtype == GP_FP64;
   const size_t nc = s->g.ncell;
-  if (on_device) {
+  const bool mid = s->next_stage == GP_STAGE_LAG;
+  const bool gas_mom = field >= GP_MX && field <= GP_MZ, bme_mom = field >= GP_QX && field <= GP_QZ;
+  if (mid && (gas_mom || bme_mom)) {
+    // between the stages the momentum slots hold velocities: return density * velocity
+    const double* dens = s->dens[s->parity][gas_mom ? 0 : 1];
+    void* out = on_device ? dst : s->staging;
+    if (s->prec == GP_FP64) {
+      if (dst_double) launch_density_times<double, double>((double*)out, dens, (const double*)src, nc, s->st);
+      else launch_density_times<float, double>((float*)out, dens, (const double*)src, nc, s->st);
+    } else {
+      if (dst_double) launch_density_times<double, float>((double*)out, dens, (const float*)src, nc, s->st);
+      else launch_density_times<float, float>((float*)out, dens, (const float*)src, nc, s->st);
+    }
+    if (!on_device)
+      HIP_TRY(s, hipMemcpyAsync(dst, s->staging, nc * (dst_double ? 8 : 4), hipMemcpyDeviceToHost, s->st));
+    HIP_TRY(s, hipStreamSynchronize(s->st));
+  } else if (on_device) {
     convert_any(dst, dst_double, src, src_double, nc, s->st);
     HIP_TRY(s, hipStreamSynchronize(s->st));
   } else {
@@ -645,14 +668,17 @@ gp_status gp_use_graph(gp_sim* s, int32_t enable) {
 double gp_algorithmic_bytes_per_cell(const gp_sim* s, int32_t kernel) {
   if (!s) return 0.0;
   const double es = (double)esize(s->prec);
-  const double eul = 2 * 8.0 + 20 * es + es + 20 * es;      // read rho, n, 20 fields, Phi; write 20
-  const double lag = 2 * 8.0 + 20 * es + 2 * 8.0 + 20 * es + es;  // read rho, n, 20; write 22 + s
+  const double vr = (double)(s->g.nx + 1) * (s->g.ny + 1) * (s->g.nz + 1) / (double)s->g.ncell;
+  const double eul = 2 * 8.0 + 20 * es + es + 20 * es;  // read rho, n, 20 fields, Phi; write 20
+  const double vtx = 6 * es + 6 * es * vr;              // read 6 velocities; write 6 per vertex
+  const double lag = 2 * 8.0 + 20 * es + 6 * es * vr + 2 * 8.0 + 20 * es + es;  // read rho, n, 20, corners; write 22 + s
   switch (kernel) {
     case GP_K_EUL: return eul;
+    case GP_K_VERTEX: return vtx;
     case GP_K_LAG: return lag;
     case GP_K_FINALIZE: return 0.0;
     case -1: {
-      double t = eul + lag;
+      double t = eul + vtx + lag;
       for (int k = GP_K_FFT_X_FWD; k <= GP_K_FFT_X_INV; k++) t += fft_bytes_per_cell(s, k);
       return t;
     }

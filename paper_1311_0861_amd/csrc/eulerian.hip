@@ -10,7 +10,9 @@
 //   W_ij -= tau/h sum_d d_d(Pi*_{jd} u*_i + Pi*_{id} u*_j) + tau (q_i g_j + q_j g_i)
 //   Pi_ij-= tau/h sum_d (Pi_jd d_d u*_i + Pi_id d_d u*_j)
 // (d_d X = X at face c+1/2 e_d minus X at face c-1/2 e_d).  rho and n are
-// not touched by this stage.
+// not touched by this stage.  The momentum slots of the output hold the
+// post-Eulerian velocities v' = m'/rho and u' = q'/n, which is what the
+// Lagrangian stage advects with (it rebuilds m' = rho v' where it needs it).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -26,23 +28,26 @@ template <typename T>
 __device__ __forceinline__ void load_prim(const Fields<T>& s, size_t c, T gm1, Prim<T>& q) {
   q.rho = (T)s.rho[c];
   q.n = (T)s.nb[c];
+  const T ir = T(1) / q.rho, in = T(1) / q.n;
 #pragma unroll
   for (int d = 0; d < 3; d++) {
-    q.v[d] = s.o[oidx(GP_MX + d)][c] / q.rho;
-    q.u[d] = s.o[oidx(GP_QX + d)][c] / q.n;
+    q.v[d] = s.o[oidx(GP_MX + d)][c] * ir;
+    q.u[d] = s.o[oidx(GP_QX + d)][c] * in;
   }
   q.p = gm1 * s.o[oidx(GP_EINT)][c];
 #pragma unroll
   for (int m = 0; m < 6; m++) q.P[m] = s.o[oidx(GP_PXX + m)][c];
 }
 
-// Sec. 2.1: V and P at a face between left and right states.
+// Sec. 2.1: V and P at a face between left and right states; z is the
+// acoustic impedance sqrt(gamma (pL + pR) rhoL rhoR / (rhoL + rhoR)).
 template <typename T>
 __device__ __forceinline__ void gas_face(const Prim<T>& L, const Prim<T>& R, int d, T gamma, T& V,
                                          T& P) {
   const T pl = L.p, pr = R.p;
-  const T z = sqrt(gamma * (pl + pr) * L.rho * R.rho / (L.rho + R.rho));  // acoustic impedance
-  V = T(0.5) * (L.v[d] + R.v[d]) + T(0.5) * (pl - pr) / z;
+  const T z = sqrt(gamma * (pl + pr) * L.rho * R.rho / (L.rho + R.rho));
+  const T rz = T(1) / z;
+  V = T(0.5) * (L.v[d] + R.v[d]) + T(0.5) * (pl - pr) * rz;
   P = T(0.5) * (pl + pr) + T(0.5) * (L.v[d] - R.v[d]) * z;
 }
 
@@ -60,18 +65,21 @@ __device__ __forceinline__ void bme_face(const Prim<T>& L, const Prim<T>& R, T u
   const T B = T(0.5) * (L.P[sDA] + R.P[sDA]);
   const T C = T(0.5) * (L.P[sDB] + R.P[sDB]);
   const T Z1 = sqrt(T(3) * nbar * A);  // sqrt(3 n Pi_DD): fast wave impedance
-  const T Z2 = sqrt(nbar * A);         // sqrt(n Pi_DD): slow (shear) wave impedance
+  const T rZ1 = T(1) / Z1;
+  const T Z2 = Z1 * T(0.57735026918962576451);   // sqrt(n Pi_DD): slow (shear) impedance
+  const T rZ2 = rZ1 * T(1.7320508075688772935);
+  const T rA = T(1) / A;
   const T dpdd = T(0.5) * (L.P[sDD] - R.P[sDD]);
   const T dpda = T(0.5) * (L.P[sDA] - R.P[sDA]);
   const T dpdb = T(0.5) * (L.P[sDB] - R.P[sDB]);
   const T dud = T(0.5) * (L.u[D] - R.u[D]);
   const T dua = T(0.5) * (L.u[A_] - R.u[A_]);
   const T dub = T(0.5) * (L.u[B_] - R.u[B_]);
-  const T cross_u = dpdd * (T(1) - sqrt3) / (A * Z1);  // coupling of the fast wave into u_a, u_b
-  const T cross_p = dud * nbar * (sqrt3 - T(1)) / Z2;   // and into Pi_Da, Pi_Db
-  us[D] = T(0.5) * (L.u[D] + R.u[D]) + dpdd / Z1;
-  us[A_] = T(0.5) * (L.u[A_] + R.u[A_]) + dpda / Z2 + B * cross_u;
-  us[B_] = T(0.5) * (L.u[B_] + R.u[B_]) + dpdb / Z2 + C * cross_u;
+  const T cross_u = dpdd * (T(1) - sqrt3) * rA * rZ1;  // coupling of the fast wave into u_a, u_b
+  const T cross_p = dud * nbar * (sqrt3 - T(1)) * rZ2;  // and into Pi_Da, Pi_Db
+  us[D] = T(0.5) * (L.u[D] + R.u[D]) + dpdd * rZ1;
+  us[A_] = T(0.5) * (L.u[A_] + R.u[A_]) + dpda * rZ2 + B * cross_u;
+  us[B_] = T(0.5) * (L.u[B_] + R.u[B_]) + dpdb * rZ2 + C * cross_u;
   ps[D] = A + dud * Z1;
   ps[A_] = B + dua * Z2 + B * cross_p;
   ps[B_] = C + dub * Z2 + C * cross_p;
@@ -109,9 +117,10 @@ template <typename T>
 __global__ void __launch_bounds__(kTX* kTY) k_eulerian(Fields<T> in, Fields<T> out,
                                                        const T* __restrict__ phi, Grid g, Phys ph,
                                                        const DevScalars* __restrict__ sc) {
-  const int i = blockIdx.x * kTX + threadIdx.x;
-  const int j = blockIdx.y * kTY + threadIdx.y;
-  const int k = blockIdx.z;
+  const TileId tl = xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY);
+  const int i = tl.tx * kTX + threadIdx.x;
+  const int j = tl.ty * kTY + threadIdx.y;
+  const int k = tl.tz;
   if (i >= g.nx || j >= g.ny) return;
   const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
   const size_t c = i + nx * j + nxy * k;
@@ -149,23 +158,24 @@ __global__ void __launch_bounds__(kTX* kTY) k_eulerian(Fields<T> in, Fields<T> o
   axis_terms<T, 2>(in, i + nx * j + nxy * km, i + nx * j + nxy * kp, C, gamma, gm1, dP[2], dPV, dV,
                    dq, dW, dPi);
 
-  // gas
+  // gas (momentum slots receive v' = m' / rho)
   T m[3];
 #pragma unroll
   for (int d = 0; d < 3; d++) m[d] = in.o[oidx(GP_MX + d)][c];
+  const T irho = T(1) / C.rho, inb = T(1) / C.n;
 #pragma unroll
-  for (int d = 0; d < 3; d++) out.o[oidx(GP_MX + d)][c] = m[d] - r * dP[d] - tau * C.rho * grad[d];
+  for (int d = 0; d < 3; d++) out.o[oidx(GP_MX + d)][c] = (m[d] - r * dP[d] - tau * C.rho * grad[d]) * irho;
   out.o[oidx(GP_E)][c] =
       in.o[oidx(GP_E)][c] - r * dPV - tau * (m[0] * grad[0] + m[1] * grad[1] + m[2] * grad[2]);
   const T e = in.o[oidx(GP_EINT)][c];
   out.o[oidx(GP_EINT)][c] = e - r * gm1 * e * dV;
 
-  // stars / dark matter
+  // stars / dark matter (momentum slots receive u' = q' / n)
   T q[3];
 #pragma unroll
   for (int d = 0; d < 3; d++) q[d] = in.o[oidx(GP_QX + d)][c];
 #pragma unroll
-  for (int d = 0; d < 3; d++) out.o[oidx(GP_QX + d)][c] = q[d] - r * dq[d] - tau * C.n * grad[d];
+  for (int d = 0; d < 3; d++) out.o[oidx(GP_QX + d)][c] = (q[d] - r * dq[d] - tau * C.n * grad[d]) * inb;
 #pragma unroll
   for (int a = 0; a < 3; a++)
 #pragma unroll
@@ -181,7 +191,7 @@ template <typename T>
 void launch_eulerian(const Fields<T>& in, const Fields<T>& out, const T* phi, const Grid& g,
                      const Phys& ph, const DevScalars* sc, hipStream_t st) {
   dim3 block(kTX, kTY, 1);
-  dim3 grid((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY, g.nz);
+  dim3 grid(cell_blocks(g), 1, 1);
   k_eulerian<T><<<grid, block, 0, st>>>(in, out, phi, g, ph, sc);
 }
 

@@ -11,13 +11,17 @@ void launch_eulerian(const Fields<T>& in, const Fields<T>& out, const T* phi, co
                      const Phys& ph, const DevScalars* sc, hipStream_t st);
 
 // ---- Lagrangian stage + energy balance + diagnostics partials -------------
-// cur: rho, n at t^n; eul: post-Eulerian fields; out: new state (its rho/n
-// pointers must differ from cur's).  Writes s = rho + n and one kNP-slot
-// partial row per block.
+// Corner velocities (6 components, (nx+1)(ny+1)(nz+1) vertices each, component
+// stride vstride) from the post-Eulerian velocities.
 template <typename T>
-void launch_lagrangian(const Fields<T>& cur, const Fields<T>& eul, const Fields<T>& out, T* s,
-                       const Grid& g, const Phys& ph, const DevScalars* sc, double* partials,
-                       hipStream_t st);
+void launch_vertex(const Fields<T>& eul, T* vtx, size_t vstride, const Grid& g, hipStream_t st);
+// cur: rho, n at t^n; eul: post-Eulerian fields (velocities in the momentum
+// slots); out: new state (its rho/n pointers must differ from cur's).  Writes
+// s = rho + n and one kNP-slot partial row per block.
+template <typename T>
+void launch_lagrangian(const Fields<T>& cur, const Fields<T>& eul, const Fields<T>& out, const T* vtx,
+                       size_t vstride, T* s, const Grid& g, const Phys& ph, const DevScalars* sc,
+                       double* partials, hipStream_t st);
 
 // Partials and s = rho + n of a state that has not been advanced (prologue).
 template <typename T>
@@ -78,5 +82,8 @@ void launch_finalize(const double* partials, int nrows, double* scratch, int nsc
 // ---- conversions ---------------------------------------------------------
 template <typename D, typename S>
 void launch_convert(D* dst, const S* src, size_t n, hipStream_t st);
+// dst = density * velocity (post-Eulerian momentum for inspection)
+template <typename D, typename T>
+void launch_density_times(D* dst, const double* dens, const T* vel, size_t n, hipStream_t st);
 
 }  // namespace gp

@@ -4,7 +4,8 @@
 //     F on a face = (1/4) sum over its 4 corners of v_d f^+, f^+ the upwind
 //     cell value for that corner's velocity; a corner velocity is the mean of
 //     the 8 cells sharing the vertex (post-Eulerian m/rho for the gas, q/n for
-//     the stars); written per cell as A+ f_c + A- f_{c+e_d};
+//     the stars), computed once per vertex by k_vertex; the flux is written per
+//     cell as A+ f_c + A- f_{c+e_d};
 //   - correctness integrals kappa (Sec. 2.4) measured on the advected state;
 //   - energy balance: e := E - |m|^2/(2 rho) where that exceeds eta E, and
 //     each diagonal stress Pi_dd := W_dd - q_d^2/n where that exceeds eta W_dd;
@@ -118,31 +119,57 @@ __device__ __forceinline__ void block_reduce_store(CellAcc& a, double* row) {
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T mul_rn(T a, T b);
-template <>
-__device__ __forceinline__ double mul_rn<double>(double a, double b) {
-  return __dmul_rn(a, b);
-}
-template <>
-__device__ __forceinline__ float mul_rn<float>(float a, float b) {
-  return __fmul_rn(a, b);
-}
-
 // Face flux of an FP64 density; both cells sharing the face evaluate exactly
 // this expression with the same operands.
 __device__ __forceinline__ double face_flux(double ap, double am, double fl, double fr) {
   return __fma_rn(ap, fl, __dmul_rn(am, fr));
 }
 
+// Corner velocities: vertex (I, J, K), I in [0, nx], sits between cells I-1
+// and I on x (likewise y, z); its velocity is the mean of the 8 cells sharing
+// it, cells outside the grid taken by the hydrodynamic boundary rule.  The
+// post-Eulerian momentum slots hold velocities already.
+template <typename T>
+__global__ void __launch_bounds__(kTX* kTY) k_vertex(Fields<T> eul, T* __restrict__ vtx, Grid g,
+                                                     size_t vstride) {
+  const TileId tl = xcd_tile((g.nx + 1 + kTX - 1) / kTX, (g.ny + 1 + kTY - 1) / kTY);
+  const int I = tl.tx * kTX + threadIdx.x;
+  const int J = tl.ty * kTY + threadIdx.y;
+  const int K = tl.tz;
+  if (I > g.nx || J > g.ny) return;
+  const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
+  const size_t xi[2] = {(size_t)bc_index(I - 1, g.nx, g.bc[0]), (size_t)bc_index(I, g.nx, g.bc[0])};
+  const size_t yj[2] = {nx * bc_index(J - 1, g.ny, g.bc[1]), nx * bc_index(J, g.ny, g.bc[1])};
+  const size_t zk[2] = {nxy * bc_index(K - 1, g.nz, g.bc[2]), nxy * bc_index(K, g.nz, g.bc[2])};
+  T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int c3 = 0; c3 < 2; c3++)
+#pragma unroll
+    for (int b3 = 0; b3 < 2; b3++)
+#pragma unroll
+      for (int a3 = 0; a3 < 2; a3++) {
+        const size_t cc = xi[a3] + yj[b3] + zk[c3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+          acc[d] += eul.o[oidx(GP_MX + d)][cc];
+          acc[3 + d] += eul.o[oidx(GP_QX + d)][cc];
+        }
+      }
+  const size_t w = I + (size_t)(g.nx + 1) * (J + (size_t)(g.ny + 1) * K);
+#pragma unroll
+  for (int v = 0; v < 6; v++) vtx[v * vstride + w] = acc[v] * T(0.125);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T> eul, Fields<T> out,
+                                                         const T* __restrict__ vtx, size_t vstride,
                                                          T* __restrict__ s_out, Grid g, Phys ph,
                                                          const DevScalars* __restrict__ sc,
                                                          double* __restrict__ partials) {
-  const int i = blockIdx.x * kTX + threadIdx.x;
-  const int j = blockIdx.y * kTY + threadIdx.y;
-  const int k = blockIdx.z;
+  const TileId tl = xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY);
+  const int i = tl.tx * kTX + threadIdx.x;
+  const int j = tl.ty * kTY + threadIdx.y;
+  const int k = tl.tz;
   const bool active = (i < g.nx) && (j < g.ny);
   CellAcc acc;
   acc_init(acc);
@@ -159,47 +186,11 @@ __global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T
                           nxy * bc_index(k + 1, g.nz, g.bc[2])};
     const size_t c = xi[1] + yj[1] + zk[1];
 
-    // corner velocities: corner s = sx + 2 sy + 4 sz sits at (i-1/2+sx, ...);
-    // each accumulates its 8 cells in the same (z, y, x) order from every cell
-    T cg[8][3], cb[8][3];
-#pragma unroll
-    for (int s = 0; s < 8; s++)
-#pragma unroll
-      for (int d = 0; d < 3; d++) cg[s][d] = cb[s][d] = T(0);
-#pragma unroll
-    for (int oz = 0; oz < 3; oz++)
-#pragma unroll
-      for (int oy = 0; oy < 3; oy++)
-#pragma unroll
-        for (int ox = 0; ox < 3; ox++) {
-          const size_t cc = xi[ox] + yj[oy] + zk[oz];
-          const T ir = T(1) / (T)cur.rho[cc];
-          const T in = T(1) / (T)cur.nb[cc];
-          T vg[3], vb[3];
-#pragma unroll
-          for (int d = 0; d < 3; d++) {
-            vg[d] = mul_rn(eul.o[oidx(GP_MX + d)][cc], ir);
-            vb[d] = mul_rn(eul.o[oidx(GP_QX + d)][cc], in);
-          }
-#pragma unroll
-          for (int sz = 0; sz < 2; sz++)
-#pragma unroll
-            for (int sy = 0; sy < 2; sy++)
-#pragma unroll
-              for (int sx = 0; sx < 2; sx++) {
-                // cell offset o - 1 lies in corner s's 2x2x2 block iff s - 1 <= o - 1 <= s
-                if (ox - 1 >= sx - 1 && ox - 1 <= sx && oy - 1 >= sy - 1 && oy - 1 <= sy &&
-                    oz - 1 >= sz - 1 && oz - 1 <= sz) {
-                  const int s = sx + 2 * sy + 4 * sz;
-#pragma unroll
-                  for (int d = 0; d < 3; d++) {
-                    cg[s][d] += vg[d];
-                    cb[s][d] += vb[d];
-                  }
-                }
-              }
-        }
-    // A+ / A- on the six faces: [axis][side], side 0 = minus face, 1 = plus face
+    // A+ / A- on the six faces: [axis][side], side 0 = minus face, 1 = plus face.
+    // Corner s = sx + 2 sy + 4 sz is vertex (i + sx, j + sy, k + sz); a face
+    // normal to d on side `side` has the 4 corners with s_d = side.
+    const size_t vx = g.nx + 1, vxy = (size_t)(g.nx + 1) * (g.ny + 1);
+    const size_t w0 = i + vx * j + vxy * k;
     T apg[3][2], amg[3][2], apb[3][2], amb[3][2];
 #pragma unroll
     for (int d = 0; d < 3; d++)
@@ -209,7 +200,8 @@ __global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T
 #pragma unroll
         for (int s = 0; s < 8; s++) {
           if (((s >> d) & 1) != side) continue;
-          const T vgd = cg[s][d] * T(0.125), vbd = cb[s][d] * T(0.125);
+          const size_t w = w0 + (s & 1) + vx * ((s >> 1) & 1) + vxy * ((s >> 2) & 1);
+          const T vgd = vtx[d * vstride + w], vbd = vtx[(3 + d) * vstride + w];
           pg += fmax(vgd, T(0));
           ng += fmin(vgd, T(0));
           pb += fmax(vbd, T(0));
@@ -227,14 +219,25 @@ __global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T
     const int ci[3] = {i, j, k};
     const int nn[3] = {g.nx, g.ny, g.nz};
 
-    // densities: explicit FP64 face fluxes, and the boundary outflow
+    // densities at the 7 points: centre, then minus / plus neighbour per axis
+    double rh[7], nd[7];
+    rh[0] = cur.rho[c];
+    nd[0] = cur.nb[c];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      rh[1 + 2 * d] = cur.rho[cmn[d]];
+      rh[2 + 2 * d] = cur.rho[cpl[d]];
+      nd[1 + 2 * d] = cur.nb[cmn[d]];
+      nd[2 + 2 * d] = cur.nb[cpl[d]];
+    }
+    // explicit FP64 face fluxes of rho and n, and the boundary outflow
     double divr = 0.0, divn = 0.0, outg = 0.0, outb = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-      const double Fp = face_flux(apg[d][1], amg[d][1], cur.rho[c], cur.rho[cpl[d]]);
-      const double Fm = face_flux(apg[d][0], amg[d][0], cur.rho[cmn[d]], cur.rho[c]);
-      const double Gp = face_flux(apb[d][1], amb[d][1], cur.nb[c], cur.nb[cpl[d]]);
-      const double Gm = face_flux(apb[d][0], amb[d][0], cur.nb[cmn[d]], cur.nb[c]);
+      const double Fp = face_flux(apg[d][1], amg[d][1], rh[0], rh[2 + 2 * d]);
+      const double Fm = face_flux(apg[d][0], amg[d][0], rh[1 + 2 * d], rh[0]);
+      const double Gp = face_flux(apb[d][1], amb[d][1], nd[0], nd[2 + 2 * d]);
+      const double Gm = face_flux(apb[d][0], amb[d][0], nd[1 + 2 * d], nd[0]);
       divr += Fp - Fm;
       divn += Gp - Gm;
       if (g.bc[d] == GP_BC_OUTFLOW) {
@@ -242,10 +245,11 @@ __global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T
         if (ci[d] == 0) { outg -= Fm; outb -= Gm; }
       }
     }
-    const double rho = cur.rho[c] - rd * divr;
-    const double n = cur.nb[c] - rd * divn;
+    const double rho = rh[0] - rd * divr;
+    const double n = nd[0] - rd * divn;
 
-    // other fields: 7-point stencil with the same face coefficients
+    // other fields: 7-point stencil with the same face coefficients; the
+    // momenta are rebuilt as density times post-Eulerian velocity
     T wcg = T(1), wcb = T(1), wpg[3], wmg[3], wpb[3], wmb[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
@@ -261,12 +265,18 @@ __global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T
     for (int f = 0; f < kNO; f++) {
       const T* src = eul.o[f];
       const bool gas = f < oidx(GP_N + 1);  // mx my mz E e
+      const bool gmom = f <= oidx(GP_MZ);
+      const bool bmom = f >= oidx(GP_QX) && f <= oidx(GP_QZ);
+      auto val = [&](int p, size_t idx) -> T {
+        const T x = src[idx];
+        return gmom ? (T)rh[p] * x : (bmom ? (T)nd[p] * x : x);
+      };
       const T wc = gas ? wcg : wcb;
-      T v = wc * src[c];
+      T v = wc * val(0, c);
 #pragma unroll
       for (int d = 0; d < 3; d++) {
-        v += (gas ? wpg[d] : wpb[d]) * src[cpl[d]];
-        v += (gas ? wmg[d] : wmb[d]) * src[cmn[d]];
+        v += (gas ? wpg[d] : wpb[d]) * val(2 + 2 * d, cpl[d]);
+        v += (gas ? wmg[d] : wmb[d]) * val(1 + 2 * d, cmn[d]);
       }
       nv[f] = v;
     }
@@ -323,16 +333,16 @@ __global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T
     s_out[c] = (T)(rho + n);
     cell_terms(acc, rho, n, m, E, e, q, P, W, gamma);
   }
-  const size_t blin = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
-  block_reduce_store(acc, partials + blin * kNP);
+  block_reduce_store(acc, partials + (size_t)tl.lin * kNP);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kTX* kTY) k_init_partials(Fields<T> cur, T* __restrict__ s_out, Grid g,
                                                             Phys ph, double* __restrict__ partials) {
-  const int i = blockIdx.x * kTX + threadIdx.x;
-  const int j = blockIdx.y * kTY + threadIdx.y;
-  const int k = blockIdx.z;
+  const TileId tl = xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY);
+  const int i = tl.tx * kTX + threadIdx.x;
+  const int j = tl.ty * kTY + threadIdx.y;
+  const int k = tl.tz;
   CellAcc acc;
   acc_init(acc);
   if (i < g.nx && j < g.ny) {
@@ -357,33 +367,41 @@ __global__ void __launch_bounds__(kTX* kTY) k_init_partials(Fields<T> cur, T* __
     s_out[c] = (T)(rho + n);
     cell_terms(acc, rho, n, m, E, e, q, P, W, (T)ph.gamma);
   }
-  const size_t blin = blockIdx.x + (size_t)gridDim.x * (blockIdx.y + (size_t)gridDim.y * blockIdx.z);
-  block_reduce_store(acc, partials + blin * kNP);
+  block_reduce_store(acc, partials + (size_t)tl.lin * kNP);
 }
 
 template <typename T>
-void launch_lagrangian(const Fields<T>& cur, const Fields<T>& eul, const Fields<T>& out, T* s,
-                       const Grid& g, const Phys& ph, const DevScalars* sc, double* partials,
-                       hipStream_t st) {
+void launch_vertex(const Fields<T>& eul, T* vtx, size_t vstride, const Grid& g, hipStream_t st) {
   dim3 block(kTX, kTY, 1);
-  dim3 grid((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY, g.nz);
-  k_lagrangian<T><<<grid, block, 0, st>>>(cur, eul, out, s, g, ph, sc, partials);
+  dim3 grid(((g.nx + 1 + kTX - 1) / kTX) * ((g.ny + 1 + kTY - 1) / kTY) * (g.nz + 1), 1, 1);
+  k_vertex<T><<<grid, block, 0, st>>>(eul, vtx, g, vstride);
+}
+
+template <typename T>
+void launch_lagrangian(const Fields<T>& cur, const Fields<T>& eul, const Fields<T>& out, const T* vtx,
+                       size_t vstride, T* s, const Grid& g, const Phys& ph, const DevScalars* sc,
+                       double* partials, hipStream_t st) {
+  dim3 block(kTX, kTY, 1);
+  dim3 grid(cell_blocks(g), 1, 1);
+  k_lagrangian<T><<<grid, block, 0, st>>>(cur, eul, out, vtx, vstride, s, g, ph, sc, partials);
 }
 
 template <typename T>
 void launch_init_partials(const Fields<T>& cur, T* s, const Grid& g, const Phys& ph, double* partials,
                           hipStream_t st) {
   dim3 block(kTX, kTY, 1);
-  dim3 grid((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY, g.nz);
+  dim3 grid(cell_blocks(g), 1, 1);
   k_init_partials<T><<<grid, block, 0, st>>>(cur, s, g, ph, partials);
 }
 
+template void launch_vertex<double>(const Fields<double>&, double*, size_t, const Grid&, hipStream_t);
+template void launch_vertex<float>(const Fields<float>&, float*, size_t, const Grid&, hipStream_t);
 template void launch_lagrangian<double>(const Fields<double>&, const Fields<double>&, const Fields<double>&,
-                                        double*, const Grid&, const Phys&, const DevScalars*, double*,
-                                        hipStream_t);
+                                        const double*, size_t, double*, const Grid&, const Phys&,
+                                        const DevScalars*, double*, hipStream_t);
 template void launch_lagrangian<float>(const Fields<float>&, const Fields<float>&, const Fields<float>&,
-                                       float*, const Grid&, const Phys&, const DevScalars*, double*,
-                                       hipStream_t);
+                                       const float*, size_t, float*, const Grid&, const Phys&,
+                                       const DevScalars*, double*, hipStream_t);
 template void launch_init_partials<double>(const Fields<double>&, double*, const Grid&, const Phys&,
                                            double*, hipStream_t);
 template void launch_init_partials<float>(const Fields<float>&, float*, const Grid&, const Phys&, double*,

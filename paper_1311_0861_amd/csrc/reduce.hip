@@ -127,6 +127,24 @@ void launch_convert(D* dst, const S* src, size_t n, hipStream_t st) {
   k_convert<D, S><<<(unsigned)blocks, 256, 0, st>>>(dst, src, n);
 }
 
+template <typename D, typename T>
+__global__ void k_density_times(D* __restrict__ dst, const double* __restrict__ dens, const T* __restrict__ vel,
+                                size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (D)((T)dens[i] * vel[i]);
+}
+
+template <typename D, typename T>
+void launch_density_times(D* dst, const double* dens, const T* vel, size_t n, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 65536);
+  k_density_times<D, T><<<(unsigned)blocks, 256, 0, st>>>(dst, dens, vel, n);
+}
+
+template void launch_density_times<double, double>(double*, const double*, const double*, size_t, hipStream_t);
+template void launch_density_times<float, double>(float*, const double*, const double*, size_t, hipStream_t);
+template void launch_density_times<double, float>(double*, const double*, const float*, size_t, hipStream_t);
+template void launch_density_times<float, float>(float*, const double*, const float*, size_t, hipStream_t);
+
 template void launch_convert<double, double>(double*, const double*, size_t, hipStream_t);
 template void launch_convert<double, float>(double*, const float*, size_t, hipStream_t);
 template void launch_convert<float, double>(float*, const double*, size_t, hipStream_t);

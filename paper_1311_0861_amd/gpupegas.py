@@ -25,7 +25,7 @@ FIELD_NAMES = [
     "Wxx", "Wxy", "Wxz", "Wyy", "Wyz", "Wzz",
 ]
 GP_PHI = 22
-KERNEL_NAMES = ["eulerian", "lagrangian", "fft_x_fwd", "fft_y_fwd", "fft_z_green", "fft_y_inv",
+KERNEL_NAMES = ["eulerian", "vertex", "lagrangian", "fft_x_fwd", "fft_y_fwd", "fft_z_green", "fft_y_inv",
                 "fft_x_inv", "finalize"]
 
 
