@@ -29,6 +29,9 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=20, help="steps timed kernel by kernel")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the FP32 (256^3, 512^3) and 48-run ensemble measurements")
+    ap.add_argument("--form-steps", type=int, default=100, help="timed steps of the extra forms")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the library's plain copy kernel over MIB MiB of FP64 data "
                          "(calibrates HBM counters) and exit")
@@ -58,15 +61,122 @@ def copy_probe(mib):
     from paper_1311_0861_amd import gpupegas as gp
     from paper_1311_0861_amd import workloads as W
     ncell = mib * 1024 * 1024 // 8
-    nz = ncell // (64 * 64)
-    cfg = W.base_config((64, 64, nz), lo=(0.0, 0.0, 0.0), hi=(64.0, 64.0, float(nz)), G=0.0)
+    nz = max(4, min(1024, ncell // (256 * 256)))
+    cfg = W.base_config((256, 256, nz), lo=(0.0, 0.0, 0.0), hi=(256.0, 256.0, float(nz)), G=0.0)
     sim = gp.Sim(cfg)
-    src = torch.ones(nz, 64, 64, dtype=torch.float64, device="cuda")
+    src = torch.ones(nz, 256, 256, dtype=torch.float64, device="cuda")
     for _ in range(5):
         sim.set_field("rho", src)
     sim.sync()
-    print(json.dumps({"copy_probe_bytes_read": 8 * 64 * 64 * nz, "copy_probe_bytes_written": 8 * 64 * 64 * nz,
+    print(json.dumps({"copy_probe_bytes_read": 8 * 256 * 256 * nz, "copy_probe_bytes_written": 8 * 256 * 256 * nz,
                       "launches": 5}), flush=True)
+
+
+def timed_steps(obj, steps, warmup):
+    """Warm up, then time exactly `steps` graph-replayed steps of a Sim/Batch."""
+    import torch
+    obj.step(warmup)
+    obj.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obj.step(steps)
+    obj.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def mass_drift(diag):
+    out = 0.0
+    for comp in ("gas", "bme"):
+        m0 = diag[0]["mass_" + comp]
+        out = max(out, max(abs(r["mass_" + comp] + r["outflow_" + comp] - m0) / m0 for r in diag))
+    return out
+
+
+def precision_forms(args):
+    """FP32 two-disk at 256^3 against the FP64 GPU step after 100 steps, and the
+    FP32 three-disk 512^3 run with per-kernel bandwidth."""
+    import torch
+    from paper_1311_0861_amd import gpupegas as gp
+    from paper_1311_0861_amd import workloads as W
+    out = {}
+    cfg, st = W.two_disk_collision(256, device="cuda")
+    states = {}
+    for prec in ("fp64", "fp32"):
+        c = dict(cfg)
+        c["precision"] = prec
+        s = gp.Sim(c)
+        s.set_state(st)
+        s.step(100)
+        s.sync()
+        states[prec] = s.get_state()
+        if prec == "fp32":
+            drift = mass_drift(s.diag())
+            sec = timed_steps(s, args.form_steps, 5)
+            out["fp32_256"] = {"workload": "two-disk collision 256^3 FP32 (rho, n FP64)",
+                               "value": round(256 ** 3 * args.form_steps / sec / 1e6, 2),
+                               "unit": "Mcell-updates/s", "steps": args.form_steps,
+                               "mass_drift_100_steps": drift}
+        else:
+            sec = timed_steps(s, args.form_steps, 5)
+            out["fp64_256"] = {"workload": "two-disk collision 256^3 FP64",
+                               "value": round(256 ** 3 * args.form_steps / sec / 1e6, 2),
+                               "unit": "Mcell-updates/s", "steps": args.form_steps}
+        s.close()
+    err = {}
+    for grp in (["rho"], ["mx", "my", "mz"], ["E"], ["e"], ["n"], ["qx", "qy", "qz"],
+                ["Pxx", "Pxy", "Pxz", "Pyy", "Pyz", "Pzz"], ["Wxx", "Wxy", "Wxz", "Wyy", "Wyz", "Wzz"]):
+        den = sum(float(states["fp64"][f].abs().sum()) for f in grp)
+        for f in grp:
+            err[f] = float((states["fp32"][f] - states["fp64"][f]).abs().sum()) / den
+    out["fp32_256"]["rel_l1_vs_fp64_gpu_100_steps"] = {k: float("%.3g" % v) for k, v in err.items()}
+    out["fp32_256"]["rel_l1_max"] = max(err.values())
+    del states
+    torch.cuda.empty_cache()
+
+    cfg, st = W.three_disk_collision(512, device="cuda", precision="fp32")
+    s = gp.Sim(cfg)
+    s.set_state(st)
+    del st
+    torch.cuda.empty_cache()
+    sec = timed_steps(s, 50, 2)
+    kt = s.time_kernels(3)
+    n = 512 ** 3
+    out["fp32_512"] = {"workload": "three-disk collision 512^3 FP32 (rho, n FP64), 50 steps",
+                       "value": round(n * 50 / sec / 1e6, 2), "unit": "Mcell-updates/s",
+                       "mass_drift": mass_drift(s.diag()),
+                       "kernels": {k: {"ms": round(v, 4),
+                                       "GB/s": round(s.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * n / (v * 1e-3) / 1e9, 1)
+                                       if v > 0 else None} for k, v in kt.items()}}
+    s.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_form(args):
+    """48 independent two-disk runs (64^3 / 96^3 / 128^3, FP32) advanced together."""
+    import torch
+    from paper_1311_0861_amd import gpupegas as gp
+    from paper_1311_0861_amd import workloads as W
+    members = [W.ensemble_member(r, device="cuda") for r in range(48)]
+    b = gp.Batch([c for c, _ in members])
+    for r, (_, st) in enumerate(members):
+        b.set_state(r, st)
+    del members
+    torch.cuda.empty_cache()
+    cells = b.cells()
+    sec = timed_steps(b, args.form_steps, 5)
+    kt = b.time_kernels(3)
+    out = {"workload": "48 two-disk runs, sizes drawn from 64^3/96^3/128^3, FP32, one launch per stage",
+           "cells": cells, "value": round(cells * args.form_steps / sec / 1e6, 2), "unit": "Mcell-updates/s",
+           "steps": args.form_steps,
+           "launch": {k: b.get_launch(k) for k in ("eulerian", "vertex", "lagrangian")},
+           "kernels": {k: {"ms": round(v, 4),
+                           "GB/s": round(b.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * cells / (v * 1e-3) / 1e9, 1)
+                           if v > 0 else None} for k, v in kt.items()}}
+    b.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -127,6 +237,7 @@ def main():
                    "GB/s": round(sim.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * ncell / (v * 1e-3) / 1e9, 1)
                    if v > 0 else None} for k, v in kt.items()}
     step_bytes = sim.bytes_per_cell(-1)
+    launch = {k: sim.get_launch(k) for k in ("eulerian", "vertex", "lagrangian")}
     sim.close()
 
     # ---- CPU oracle on a bounded sample of the same workload -----------------
@@ -159,6 +270,11 @@ def main():
         error = {"vs": "oracle", "metric": "max per-field relative L1", "value": worst, "field": field,
                  "steps": steps}
 
+    forms = None
+    if not args.no_forms:
+        forms = precision_forms(args)
+        forms["batch48"] = batch_form(args)
+
     out = {
         "metric": "Mcell-updates/s per full timestep incl. FFT Poisson",
         "value": round(value, 3),
@@ -179,6 +295,8 @@ def main():
         "cpu_baseline": cpu,
         "error": error,
         "kernels": kernels,
+        "launch": launch,
+        "forms": forms,
         "step_algorithmic_bytes_per_cell": step_bytes,
         "step_hbm_frac": round(step_bytes * ncell / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
     }

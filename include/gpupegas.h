@@ -70,8 +70,8 @@ enum { GP_STAGE_EUL = 0, GP_STAGE_LAG = 1, GP_STAGE_POISSON = 2, GP_STAGE_FINALI
 
 /* Kernels timed by gp_time_kernels. */
 enum {
-  GP_K_EUL = 0, GP_K_VERTEX, GP_K_LAG, GP_K_FFT_X_FWD, GP_K_FFT_Y_FWD, GP_K_FFT_Z, GP_K_FFT_Y_INV,
-  GP_K_FFT_X_INV, GP_K_FINALIZE, GP_NKERNELS
+  GP_K_EUL = 0, GP_K_VERTEX, GP_K_LAG, GP_K_REDUCE, GP_K_FFT_X_FWD, GP_K_FFT_Y_FWD, GP_K_FFT_Z,
+  GP_K_FFT_Y_INV, GP_K_FFT_X_INV, GP_K_FINALIZE, GP_NKERNELS
 };
 
 typedef struct {
@@ -158,8 +158,42 @@ gp_status gp_time_kernels(gp_sim *sim, int32_t nsteps, double *ms, int32_t max);
 /* Use a captured HIP graph per step (default on).  Results are identical. */
 gp_status gp_use_graph(gp_sim *sim, int32_t enable);
 
+/* Persistent grid size (workgroups) of a per-cell kernel (GP_K_EUL,
+ * GP_K_VERTEX or GP_K_LAG).  By default the first step times a few
+ * candidates and keeps the fastest; gp_set_launch fixes the size instead
+ * (0 = one workgroup per tile) and disables that tuning.  Results never
+ * depend on the grid size. */
+gp_status gp_set_launch(gp_sim *sim, int32_t kernel, int32_t blocks);
+gp_status gp_get_launch(gp_sim *sim, int32_t kernel, int32_t *blocks);
+
 const char *gp_status_str(gp_status s);
 const char *gp_last_error(const gp_sim *sim);
+
+/* ---- Ensembles --------------------------------------------------------------
+ * A batch advances nruns independent runs (grids of any supported sizes, one
+ * shared precision) in lockstep: each stage is one launch over all runs (the
+ * Poisson passes one launch per distinct grid size), and each step is one
+ * graph replay.  Every run keeps its own tau, time, diagnostics and error bits,
+ * and evolves exactly as it would in its own gp_sim.  Fields, diagnostics and
+ * errors are addressed by run index 0..nruns-1; other conventions are those of
+ * the single-run calls above. */
+typedef struct gp_batch gp_batch;
+
+gp_status gp_batch_create(const gp_config *cfgs, int32_t nruns, void *hip_stream, gp_batch **out);
+gp_status gp_batch_destroy(gp_batch *b);
+gp_status gp_batch_set_field(gp_batch *b, int32_t run, int32_t field, const void *src, int32_t dtype,
+                             int32_t on_device);
+gp_status gp_batch_get_field(gp_batch *b, int32_t run, int32_t field, void *dst, int32_t dtype,
+                             int32_t on_device);
+gp_status gp_batch_step(gp_batch *b, int32_t nsteps);
+gp_status gp_batch_sync(gp_batch *b);
+gp_status gp_batch_get_diag(gp_batch *b, int32_t run, gp_diag *out, int32_t max, int32_t *count);
+gp_status gp_batch_time_kernels(gp_batch *b, int32_t nsteps, double *ms, int32_t max);
+gp_status gp_batch_set_launch(gp_batch *b, int32_t kernel, int32_t blocks);
+gp_status gp_batch_get_launch(gp_batch *b, int32_t kernel, int32_t *blocks);
+double gp_batch_algorithmic_bytes_per_cell(const gp_batch *b, int32_t kernel);
+int64_t gp_batch_cells(const gp_batch *b);  /* total cells over all runs */
+const char *gp_batch_last_error(const gp_batch *b);
 
 /* Bytes the kernels move per cell per step by design (reads + writes of the
  * state, potential and spectrum), for the roofline; see the source for the

@@ -35,9 +35,9 @@ __host__ __device__ constexpr int oidx(int field) { return field < GP_N ? field 
 // mass flux in both precisions); the other 20 fields use the working type T.
 template <typename T>
 struct Fields {
-  double* rho;
-  double* nb;
-  T* o[kNO];  // mx my mz E e | qx qy qz | Pxx Pxy Pxz Pyy Pyz Pzz | Wxx Wxy Wxz Wyy Wyz Wzz
+  __attribute__((address_space(1))) double* rho;
+  __attribute__((address_space(1))) double* nb;
+  __attribute__((address_space(1))) T* o[kNO];  // mx my mz E e | qx qy qz | Pxx..Pzz | Wxx..Wzz
 };
 
 struct Grid {
@@ -57,6 +57,7 @@ struct DevScalars {
   double dt;             // step the next update uses
   double outflow_gas;    // cumulative outflow
   double outflow_bme;
+  double shift;          // FP64 mean of rho + n, removed from the Poisson source
   int64_t step;
   uint32_t err;          // latched error bits
   uint32_t ndiag;        // diagnostics records written so far
@@ -74,35 +75,115 @@ __device__ __forceinline__ int bc_index(int i, int n, int bc) {
 }
 __device__ __forceinline__ int wrap_index(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Launch shape of the per-cell kernels: 64 x 4 threads cover a 64 x 4 tile
-// of an x-y plane; blockIdx.z walks the z planes.
+// Per-cell kernels work on 64 x 4 tiles of an x-y plane (one thread per cell,
+// a wave covers 64 consecutive x cells); a tile index runs x fastest, then y,
+// then z.
 constexpr int kTX = 64;
 constexpr int kTY = 4;
+constexpr int kBlock = kTX * kTY;
 
-inline unsigned cell_blocks(const Grid& g) {
-  return ((g.nx + kTX - 1) / kTX) * ((g.ny + kTY - 1) / kTY) * g.nz;
+// Device descriptor of one run of a batch (a single simulation is a batch of
+// one).  rho and n alternate between dens[0] and dens[1] each step; "cur"
+// holds the state, "tmp" the post-Eulerian fields.
+template <typename T>
+struct RunDev {
+  Grid g;
+  Phys ph;
+  double* dens[2][2];  // [parity][rho, n]
+  T* cur[kNO];
+  T* tmp[kNO];
+  T* vtx;              // corner velocities, 6 components of vstride each
+  size_t vstride;
+  T* phi;
+  DevScalars* sc;
+  unsigned row0;       // first row of this run in the partial-sum table
+  int ntx, nty;        // cell tiles per plane and per column
+  int vntx, vnty;      // unused (vertices go in flat order)
+};
+
+struct WorkItem {
+  int run;
+  int tile;
+};
+
+// The hardware hands consecutive workgroups to the 8 XCDs in turn, and each
+// XCD has its own L2.  A persistent launch gives XCD x one contiguous range of
+// work items (tiles of one slab of z planes, in order); its workgroups stride
+// through that range together, so tiles sharing y/z halos run on the same XCD
+// close in time.  Which workgroup takes a tile never changes a result.
+constexpr unsigned kNumXcd = 8;
+struct WorkRange {
+  unsigned first, end, stride;
+};
+__device__ __forceinline__ WorkRange xcd_range(unsigned nwork) {
+  const unsigned G = gridDim.x, b = blockIdx.x;
+  const unsigned x = b % kNumXcd, slot = b / kNumXcd;
+  const unsigned nb_x = (G - x + kNumXcd - 1) / kNumXcd;  // workgroups on XCD x
+  const unsigned q = nwork / kNumXcd, rem = nwork % kNumXcd;
+  const unsigned start = x * q + min(x, rem);
+  const unsigned count = q + (x < rem ? 1u : 0u);
+  WorkRange r;
+  r.first = start + slot;
+  r.end = start + count;
+  r.stride = nb_x;
+  return r;
 }
 
-// The hardware hands consecutive workgroups of a 1D grid to the 8 XCDs in
-// turn, and each XCD has its own L2.  Remap the dispatch index so that XCD x
-// gets one contiguous range of tiles (a slab of z planes, swept in order):
-// tiles that share y/z halos then run on the same XCD close in time.
-constexpr int kNumXcd = 8;
-struct TileId {
-  int tx, ty, tz;   // tile coordinates, x fastest
-  unsigned lin;     // linear tile index (row of the partial-sum table)
-};
-__device__ __forceinline__ TileId xcd_tile(int ntx, int nty) {
-  const unsigned nb = gridDim.x, b = blockIdx.x;
-  const unsigned q = nb / kNumXcd, rem = nb % kNumXcd;
-  const unsigned x = b % kNumXcd, idx = b / kNumXcd;
-  const unsigned v = x * q + min(x, rem) + idx;
-  TileId t;
-  t.lin = v;
-  t.tx = v % ntx;
-  t.ty = (v / ntx) % nty;
-  t.tz = v / (ntx * nty);
-  return t;
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Pointers read from a descriptor in memory are generic to the compiler;
+// typing them as global-address-space pointers lets it emit global (not flat)
+// memory instructions for every access through them.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+// Reciprocal by Newton's iteration r <- r + r (1 - x r) from the hardware
+// estimate: two steps in FP64 and one in FP32 reach the working precision to
+// within an ulp or so, at about half the cost of an IEEE divide.  Used for
+// the strictly positive densities, pressures and impedances of the stencils.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+
+template <typename T>
+__device__ __forceinline__ Fields<T> fields_state(const RunDev<T>& R, int parity) {
+  Fields<T> f;
+  f.rho = as_global(R.dens[parity][0]);
+  f.nb = as_global(R.dens[parity][1]);
+#pragma unroll
+  for (int o = 0; o < kNO; o++) f.o[o] = as_global(R.cur[o]);
+  return f;
+}
+template <typename T>
+__device__ __forceinline__ Fields<T> fields_eul(const RunDev<T>& R) {
+  Fields<T> f;
+  f.rho = nullptr;
+  f.nb = nullptr;
+#pragma unroll
+  for (int o = 0; o < kNO; o++) f.o[o] = as_global(R.tmp[o]);
+  return f;
+}
+template <typename T>
+__device__ __forceinline__ Fields<T> fields_next(const RunDev<T>& R, int parity) {
+  Fields<T> f;
+  f.rho = as_global(R.dens[parity ^ 1][0]);
+  f.nb = as_global(R.dens[parity ^ 1][1]);
+#pragma unroll
+  for (int o = 0; o < kNO; o++) f.o[o] = as_global(R.cur[o]);
+  return f;
 }
 
 }  // namespace gp

@@ -1,20 +1,32 @@
 // Host engine and C ABI of the GPUPEGAS timestep library.
 //
-// A sim owns its device state: rho and n in FP64 (two buffers that swap each
-// step), the 20 other fields in the working precision in two sets ("cur" holds
-// the state, "tmp" the post-Eulerian fields), the potential, s = rho + n, the
-// half spectrum, per-block partial sums, and the device scalars (t, tau, step,
-// error bits, diagnostics ring).  A step is enqueued as
-//   Eulerian -> Lagrangian(+epilogue) -> 5 FFT passes -> reduce/finalize
-// and, by default, replayed from a captured HIP graph (one per buffer parity);
-// tau never leaves the device.
+// The engine advances a batch of independent runs in lockstep; a single
+// simulation (gp_sim) is a batch of one (gp_batch), so both go through the
+// same kernels and a batch member is bitwise equal to the same run alone.
+//
+// Device state per run: rho and n in FP64 (two buffers that swap each step),
+// the 20 other fields in the working precision in two sets ("cur" holds the
+// state, "tmp" the post-Eulerian fields), corner velocities, device scalars
+// (t, tau, step, error bits, mean density, cumulative outflow) and a ring of
+// diagnostics records.  Runs of one grid size form a size class whose Poisson
+// source, potential and half spectrum are stored back to back, so each FFT
+// pass is one launch per class.  Per-cell stages are persistent launches over
+// a (run, tile) work list.  One step is
+//   Eulerian -> vertex -> Lagrangian(+epilogue) -> 5 FFT passes per class
+//   -> reduce -> finalize (one workgroup per run)
+// and is replayed from a captured HIP graph (one per buffer parity); tau never
+// leaves the device.  The persistent grid size of each per-cell stage is
+// picked by timing candidates during the first step (results do not depend
+// on it).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -22,39 +34,74 @@
 
 using namespace gp;
 
-struct gp_sim {
+namespace {
+
+constexpr int kTunedKernels = 3;  // Eulerian, vertex, Lagrangian
+const int kTunedIds[kTunedKernels] = {GP_K_EUL, GP_K_VERTEX, GP_K_LAG};
+
+struct RunHost {
   gp_config cfg{};
   Grid g{};
   Phys ph{};
-  int prec = GP_FP64;
-  int device = 0;
-  hipStream_t st = nullptr;
-  bool own_stream = false;
-
-  std::vector<std::pair<void*, size_t>> allocs;
-  double* dens[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][rho, n]
+  double* dens[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   void* cur[kNO] = {};
   void* tmp[kNO] = {};
-  void* vtx = nullptr;   // corner velocities, 6 components
+  void* vtx = nullptr;
   size_t vstride = 0;
-  void* s = nullptr;
   void* phi = nullptr;
-  void* spec = nullptr;
-  void* staging = nullptr;
-  double* partials = nullptr;
-  int nrows = 0;
-  double* scratch = nullptr;
-  int nscratch = 0;
-  double* epot = nullptr;
-  int nepot = 0;
   DevScalars* sc = nullptr;
   gp_diag* ring = nullptr;
+  unsigned row0 = 0, ntiles = 0, nvtiles = 0;
+  int ntx = 0, nty = 0, vntx = 0, vnty = 0;
+  int cls = 0, slot = 0;  // size class and position inside it
+};
+
+struct SizeClass {
+  int nx = 0, ny = 0, nz = 0;
+  double h = 0.0, G = 0.0;
+  std::vector<int> runs;
+  SrcSlot* src = nullptr;  // per run slot: densities and mean, for the source
+  void* phi = nullptr;
+  void* spec = nullptr;
   void* tw_x = nullptr;
   void* wn_x = nullptr;
   void* tw_y = nullptr;
   void* tw_z = nullptr;
   double* dtab[3] = {nullptr, nullptr, nullptr};
   FftGeom fg{};
+  unsigned eoff = 0;  // first potential-energy partial of the class
+  unsigned nep_run = 0;
+};
+
+struct Timer {
+  hipEvent_t ev[2 * GP_NKERNELS];
+  double acc[GP_NKERNELS];
+  bool on = false;
+};
+
+}  // namespace
+
+struct gp_batch {
+  int prec = GP_FP64;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  std::vector<RunHost> runs;
+  std::vector<SizeClass> classes;
+  std::vector<std::pair<void*, size_t>> allocs;
+
+  void* runs_dev = nullptr;  // RunDev<T>[nruns]
+  WorkItem* cell_work = nullptr;
+  unsigned ncell_work = 0;
+  WorkItem* vtx_work = nullptr;
+  unsigned nvtx_work = 0;
+  double* partials = nullptr;
+  RedItem* red_items = nullptr;
+  int nred = 0;
+  double* scratch = nullptr;
+  FinDesc* fin = nullptr;
+  double* epot = nullptr;
+  unsigned nepot = 0;
+  void* staging = nullptr;
 
   int parity = 0;
   bool need_prologue = true;
@@ -62,20 +109,26 @@ struct gp_sim {
   bool use_graph = true;
   bool graph_ready[2] = {false, false};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  unsigned blocks[GP_NKERNELS] = {};
+  bool tuned = false;
+  bool tune = true;
   std::string last_error;
 };
 
+// A single simulation is a batch of one run.
+struct gp_sim : gp_batch {};
+
 namespace {
 
-gp_status hip_fail(gp_sim* s, hipError_t e, const char* what) {
-  if (s) s->last_error = std::string(what) + ": " + hipGetErrorString(e);
+gp_status hip_fail(gp_batch* b, hipError_t e, const char* what) {
+  if (b) b->last_error = std::string(what) + ": " + hipGetErrorString(e);
   return GP_E_HIP;
 }
 
-#define HIP_TRY(sim, expr)                                     \
-  do {                                                         \
-    hipError_t e_ = (expr);                                    \
-    if (e_ != hipSuccess) return hip_fail((sim), e_, #expr);   \
+#define HIP_TRY(b, expr)                                     \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return hip_fail((b), e_, #expr);   \
   } while (0)
 
 bool fft_len_ok(int n) {
@@ -98,221 +151,254 @@ FftAxis make_axis(int L) {
 
 size_t esize(int prec) { return prec == GP_FP64 ? sizeof(double) : sizeof(float); }
 
-void* dalloc(gp_sim* s, size_t bytes, gp_status* st) {
+void* dalloc(gp_batch* b, size_t bytes, gp_status* st) {
   void* p = nullptr;
   if (*st != GP_OK) return nullptr;
-  bytes = (bytes + 255) & ~size_t(255);
+  bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
   if (hipMalloc(&p, bytes) != hipSuccess) {
     *st = GP_E_NOMEM;
-    s->last_error = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+    b->last_error = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
     return nullptr;
   }
-  s->allocs.push_back({p, bytes});
+  b->allocs.push_back({p, bytes});
   return p;
 }
 
-template <typename T>
-Fields<T> fields_cur(const gp_sim* s) {
-  Fields<T> f{};
-  f.rho = s->dens[s->parity][0];
-  f.nb = s->dens[s->parity][1];
-  for (int o = 0; o < kNO; o++) f.o[o] = static_cast<T*>(s->cur[o]);
-  return f;
-}
-template <typename T>
-Fields<T> fields_tmp(const gp_sim* s) {
-  Fields<T> f{};
-  for (int o = 0; o < kNO; o++) f.o[o] = static_cast<T*>(s->tmp[o]);
-  return f;
-}
-template <typename T>
-Fields<T> fields_next(const gp_sim* s) {
-  Fields<T> f{};
-  f.rho = s->dens[s->parity ^ 1][0];
-  f.nb = s->dens[s->parity ^ 1][1];
-  for (int o = 0; o < kNO; o++) f.o[o] = static_cast<T*>(s->cur[o]);
-  return f;
-}
-
-template <typename T>
-FftTables<T> tables(const gp_sim* s) {
-  FftTables<T> t{};
-  t.tw_x = static_cast<const cplx<T>*>(s->tw_x);
-  t.wn_x = static_cast<const cplx<T>*>(s->wn_x);
-  t.tw_y = static_cast<const cplx<T>*>(s->tw_y);
-  t.tw_z = static_cast<const cplx<T>*>(s->tw_z);
-  t.dx = s->dtab[0];
-  t.dy = s->dtab[1];
-  t.dz = s->dtab[2];
-  return t;
-}
-
-// Kernel-launch hooks: timing brackets each launch with events when asked.
-struct Timer {
-  hipEvent_t ev[2 * GP_NKERNELS];
-  double acc[GP_NKERNELS];
-  bool on = false;
-};
-
-template <typename T>
-void enqueue_poisson(gp_sim* s, Timer* tm) {
-  if (s->cfg.G == 0.0) return;
-  const FftTables<T> t = tables<T>(s);
-  auto* spec = static_cast<cplx<T>*>(s->spec);
-  auto mark = [&](int k, int side) {
-    if (tm && tm->on) (void)hipEventRecord(tm->ev[2 * k + side], s->st);
-  };
-  auto done = [&](int k) {
-    if (tm && tm->on) {
-      (void)hipEventSynchronize(tm->ev[2 * k + 1]);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, tm->ev[2 * k], tm->ev[2 * k + 1]);
-      tm->acc[k] += ms;
-    }
-  };
-  mark(GP_K_FFT_X_FWD, 0);
-  launch_fft_x_fwd<T>(static_cast<const T*>(s->s), spec, s->fg, t, s->st);
-  mark(GP_K_FFT_X_FWD, 1);
-  done(GP_K_FFT_X_FWD);
-  mark(GP_K_FFT_Y_FWD, 0);
-  launch_fft_y<T>(spec, s->fg, t, false, s->st);
-  mark(GP_K_FFT_Y_FWD, 1);
-  done(GP_K_FFT_Y_FWD);
-  mark(GP_K_FFT_Z, 0);
-  launch_fft_z_green<T>(spec, s->fg, t, s->epot, s->st);
-  mark(GP_K_FFT_Z, 1);
-  done(GP_K_FFT_Z);
-  mark(GP_K_FFT_Y_INV, 0);
-  launch_fft_y<T>(spec, s->fg, t, true, s->st);
-  mark(GP_K_FFT_Y_INV, 1);
-  done(GP_K_FFT_Y_INV);
-  mark(GP_K_FFT_X_INV, 0);
-  launch_fft_x_inv<T>(spec, static_cast<T*>(s->phi), s->fg, t, s->st);
-  mark(GP_K_FFT_X_INV, 1);
-  done(GP_K_FFT_X_INV);
-}
-
-void enqueue_finalize(gp_sim* s, int advanced, Timer* tm) {
-  const double escale = 1.0 / ((double)s->g.nx * s->g.ny * s->g.nz);
-  if (tm && tm->on) (void)hipEventRecord(tm->ev[2 * GP_K_FINALIZE], s->st);
-  launch_finalize(s->partials, s->nrows, s->scratch, s->nscratch, s->epot, s->cfg.G != 0.0 ? s->nepot : 0, s->g,
-                  s->ph, escale, advanced, s->sc, s->ring, s->st);
-  if (tm && tm->on) {
-    (void)hipEventRecord(tm->ev[2 * GP_K_FINALIZE + 1], s->st);
-    (void)hipEventSynchronize(tm->ev[2 * GP_K_FINALIZE + 1]);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, tm->ev[2 * GP_K_FINALIZE], tm->ev[2 * GP_K_FINALIZE + 1]);
-    tm->acc[GP_K_FINALIZE] += ms;
+gp_status validate(const gp_config* cfg) {
+  for (int d = 0; d < 3; d++) {
+    if (cfg->n[d] < 4 || cfg->n[d] > 1024 || !(cfg->hi[d] > cfg->lo[d])) return GP_E_INVALID;
+    if (cfg->bc[d] != GP_BC_OUTFLOW && cfg->bc[d] != GP_BC_PERIODIC) return GP_E_INVALID;
   }
-}
-
-template <typename T>
-void enqueue_stage(gp_sim* s, int stage, Timer* tm) {
-  auto timed = [&](int k, auto&& fn) {
-    if (tm && tm->on) (void)hipEventRecord(tm->ev[2 * k], s->st);
-    fn();
-    if (tm && tm->on) {
-      (void)hipEventRecord(tm->ev[2 * k + 1], s->st);
-      (void)hipEventSynchronize(tm->ev[2 * k + 1]);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, tm->ev[2 * k], tm->ev[2 * k + 1]);
-      tm->acc[k] += ms;
-    }
-  };
-  switch (stage) {
-    case GP_STAGE_EUL:
-      timed(GP_K_EUL, [&] {
-        launch_eulerian<T>(fields_cur<T>(s), fields_tmp<T>(s), static_cast<const T*>(s->phi), s->g, s->ph, s->sc,
-                           s->st);
-      });
-      break;
-    case GP_STAGE_LAG:
-      timed(GP_K_VERTEX, [&] {
-        launch_vertex<T>(fields_tmp<T>(s), static_cast<T*>(s->vtx), s->vstride, s->g, s->st);
-      });
-      timed(GP_K_LAG, [&] {
-        launch_lagrangian<T>(fields_cur<T>(s), fields_tmp<T>(s), fields_next<T>(s), static_cast<const T*>(s->vtx),
-                             s->vstride, static_cast<T*>(s->s), s->g, s->ph, s->sc, s->partials, s->st);
-      });
-      s->parity ^= 1;
-      break;
-    case GP_STAGE_POISSON:
-      enqueue_poisson<T>(s, tm);
-      break;
-    case GP_STAGE_FINALIZE:
-      enqueue_finalize(s, 1, tm);
-      break;
-  }
-}
-
-template <typename T>
-void enqueue_prologue(gp_sim* s) {
-  launch_init_partials<T>(fields_cur<T>(s), static_cast<T*>(s->s), s->g, s->ph, s->partials, s->st);
-  enqueue_poisson<T>(s, nullptr);
-  enqueue_finalize(s, 0, nullptr);
-}
-
-void run_prologue(gp_sim* s) {
-  if (s->prec == GP_FP64)
-    enqueue_prologue<double>(s);
-  else
-    enqueue_prologue<float>(s);
-  s->need_prologue = false;
-  s->next_stage = GP_STAGE_EUL;
-}
-
-void run_stage(gp_sim* s, int stage, Timer* tm) {
-  if (s->prec == GP_FP64)
-    enqueue_stage<double>(s, stage, tm);
-  else
-    enqueue_stage<float>(s, stage, tm);
-}
-
-void run_step_direct(gp_sim* s, Timer* tm) {
-  for (int st = 0; st < 4; st++) run_stage(s, st, tm);
-}
-
-gp_status build_graph(gp_sim* s, int parity) {
-  const int saved = s->parity;
-  s->parity = parity;
-  hipGraph_t graph = nullptr;
-  HIP_TRY(s, hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
-  run_step_direct(s, nullptr);
-  hipError_t e = hipStreamEndCapture(s->st, &graph);
-  s->parity = saved;
-  if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
-  e = hipGraphInstantiate(&s->gexec[parity], graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
-  s->graph_ready[parity] = true;
+  const double h = (cfg->hi[0] - cfg->lo[0]) / cfg->n[0];
+  for (int d = 1; d < 3; d++)
+    if (std::fabs((cfg->hi[d] - cfg->lo[d]) / cfg->n[d] - h) > 1e-12 * h) return GP_E_INVALID;
+  if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0) || cfg->reserved != 0) return GP_E_INVALID;
+  if (cfg->precision != GP_FP64 && cfg->precision != GP_FP32) return GP_E_INVALID;
+  if (cfg->G != 0.0)
+    for (int d = 0; d < 3; d++)
+      if (!fft_len_ok(cfg->n[d]) || cfg->n[d] % 2 != 0) return GP_E_UNSUPPORTED;
   return GP_OK;
 }
 
-gp_status latched(gp_sim* s) {
-  DevScalars h{};
-  HIP_TRY(s, hipMemcpy(&h, s->sc, sizeof(h), hipMemcpyDeviceToHost));
-  if (h.err & ERR_NONFINITE) {
-    s->last_error = "non-finite value in the state";
+template <typename T>
+FftTables<T> tables(const SizeClass& c) {
+  FftTables<T> t{};
+  t.tw_x = static_cast<const cplx<T>*>(c.tw_x);
+  t.wn_x = static_cast<const cplx<T>*>(c.wn_x);
+  t.tw_y = static_cast<const cplx<T>*>(c.tw_y);
+  t.tw_z = static_cast<const cplx<T>*>(c.tw_z);
+  t.dx = c.dtab[0];
+  t.dy = c.dtab[1];
+  t.dz = c.dtab[2];
+  return t;
+}
+
+void tmark(gp_batch* b, Timer* tm, int k, int side) {
+  if (tm && tm->on) (void)hipEventRecord(tm->ev[2 * k + side], b->st);
+}
+void tdone(Timer* tm, int k) {
+  if (tm && tm->on) {
+    (void)hipEventSynchronize(tm->ev[2 * k + 1]);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, tm->ev[2 * k], tm->ev[2 * k + 1]);
+    tm->acc[k] += ms;
+  }
+}
+
+template <typename T>
+void enqueue_poisson(gp_batch* b, Timer* tm) {
+  // each pass runs over every size class before the next pass starts
+  const int passes[5] = {GP_K_FFT_X_FWD, GP_K_FFT_Y_FWD, GP_K_FFT_Z, GP_K_FFT_Y_INV, GP_K_FFT_X_INV};
+  for (int k : passes) {
+    tmark(b, tm, k, 0);
+    for (SizeClass& c : b->classes) {
+      if (c.G == 0.0) continue;
+      const FftTables<T> t = tables<T>(c);
+      auto* spec = static_cast<cplx<T>*>(c.spec);
+      switch (k) {
+        case GP_K_FFT_X_FWD: launch_fft_x_fwd<T>(c.src, b->parity, spec, c.fg, t, b->st); break;
+        case GP_K_FFT_Y_FWD: launch_fft_y<T>(spec, c.fg, t, false, b->st); break;
+        case GP_K_FFT_Z: launch_fft_z_green<T>(spec, c.fg, t, b->epot + c.eoff, b->st); break;
+        case GP_K_FFT_Y_INV: launch_fft_y<T>(spec, c.fg, t, true, b->st); break;
+        case GP_K_FFT_X_INV: launch_fft_x_inv<T>(spec, static_cast<T*>(c.phi), c.fg, t, b->st); break;
+      }
+    }
+    tmark(b, tm, k, 1);
+    tdone(tm, k);
+  }
+}
+
+// partial rows -> per-run scratch rows and the mean density of each run
+void enqueue_reduce(gp_batch* b, Timer* tm) {
+  tmark(b, tm, GP_K_REDUCE, 0);
+  launch_reduce(b->partials, b->red_items, b->nred, b->scratch, b->fin, (int)b->runs.size(), b->st);
+  tmark(b, tm, GP_K_REDUCE, 1);
+  tdone(tm, GP_K_REDUCE);
+}
+
+void enqueue_finalize(gp_batch* b, int advanced, Timer* tm) {
+  tmark(b, tm, GP_K_FINALIZE, 0);
+  launch_finalize(b->scratch, b->epot, b->fin, (int)b->runs.size(), advanced, b->st);
+  tmark(b, tm, GP_K_FINALIZE, 1);
+  tdone(tm, GP_K_FINALIZE);
+}
+
+template <typename T>
+void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
+  const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
+  switch (k) {
+    case GP_K_EUL: launch_eulerian<T>(runs, b->cell_work, b->ncell_work, b->parity, nblocks, b->st); break;
+    case GP_K_VERTEX: launch_vertex<T>(runs, b->vtx_work, b->nvtx_work, nblocks, b->st); break;
+    case GP_K_LAG: launch_lagrangian<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, nblocks, b->st);
+  }
+}
+
+unsigned work_count(const gp_batch* b, int k) { return k == GP_K_VERTEX ? b->nvtx_work : b->ncell_work; }
+
+// Time the persistent grid-size candidates of kernel k and keep the fastest.
+// Every per-cell stage is idempotent with respect to its inputs (none of them
+// writes what it reads), so re-running it during the first step changes
+// nothing but the timing.
+template <typename T>
+void tune_kernel(gp_batch* b, int k) {
+  const unsigned nw = work_count(b, k);
+  std::vector<unsigned> cand = {nw};
+  for (unsigned c : {8192u, 4096u, 2048u, 1024u})
+    if (c < nw) cand.push_back(c);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best = 1e30f;
+  unsigned pick = nw;
+  for (unsigned c : cand) {
+    launch_cell_kernel<T>(b, k, c);  // warm
+    (void)hipEventRecord(e0, b->st);
+    for (int rep = 0; rep < 3; rep++) launch_cell_kernel<T>(b, k, c);
+    (void)hipEventRecord(e1, b->st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->blocks[k] = pick;
+}
+
+template <typename T>
+void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
+  auto cell = [&](int k) {
+    if (allow_tune && b->tune && !b->tuned) tune_kernel<T>(b, k);
+    tmark(b, tm, k, 0);
+    launch_cell_kernel<T>(b, k, b->blocks[k]);
+    tmark(b, tm, k, 1);
+    tdone(tm, k);
+  };
+  switch (stage) {
+    case GP_STAGE_EUL:
+      cell(GP_K_EUL);
+      break;
+    case GP_STAGE_LAG:
+      cell(GP_K_VERTEX);
+      cell(GP_K_LAG);
+      if (allow_tune && b->tune) b->tuned = true;
+      b->parity ^= 1;
+      enqueue_reduce(b, tm);
+      break;
+    case GP_STAGE_POISSON:
+      enqueue_poisson<T>(b, tm);
+      break;
+    case GP_STAGE_FINALIZE:
+      enqueue_finalize(b, 1, tm);
+      break;
+  }
+}
+
+template <typename T>
+void enqueue_prologue(gp_batch* b) {
+  const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
+  launch_init_partials<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, b->blocks[GP_K_LAG], b->st);
+  enqueue_reduce(b, nullptr);
+  enqueue_poisson<T>(b, nullptr);
+  enqueue_finalize(b, 0, nullptr);
+}
+
+void run_prologue(gp_batch* b) {
+  if (b->prec == GP_FP64)
+    enqueue_prologue<double>(b);
+  else
+    enqueue_prologue<float>(b);
+  b->need_prologue = false;
+  b->next_stage = GP_STAGE_EUL;
+}
+
+void run_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
+  if (b->prec == GP_FP64)
+    enqueue_stage<double>(b, stage, tm, allow_tune);
+  else
+    enqueue_stage<float>(b, stage, tm, allow_tune);
+}
+
+void run_step_direct(gp_batch* b, Timer* tm, bool allow_tune) {
+  for (int st = 0; st < 4; st++) run_stage(b, st, tm, allow_tune);
+}
+
+gp_status build_graph(gp_batch* b, int parity) {
+  const int saved = b->parity;
+  b->parity = parity;
+  hipGraph_t graph = nullptr;
+  HIP_TRY(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  run_step_direct(b, nullptr, false);
+  hipError_t e = hipStreamEndCapture(b->st, &graph);
+  b->parity = saved;
+  if (e != hipSuccess) return hip_fail(b, e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&b->gexec[parity], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(b, e, "hipGraphInstantiate");
+  b->graph_ready[parity] = true;
+  return GP_OK;
+}
+
+void drop_graphs(gp_batch* b) {
+  for (int p = 0; p < 2; p++) {
+    if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
+    b->gexec[p] = nullptr;
+    b->graph_ready[p] = false;
+  }
+}
+
+gp_status latched(gp_batch* b) {
+  uint32_t err = 0;
+  for (const RunHost& r : b->runs) {
+    DevScalars h{};
+    HIP_TRY(b, hipMemcpy(&h, r.sc, sizeof(h), hipMemcpyDeviceToHost));
+    err |= h.err;
+  }
+  if (err & ERR_NONFINITE) {
+    b->last_error = "non-finite value in the state";
     return GP_E_NONFINITE;
   }
-  if (h.err & (ERR_DENSITY | ERR_PRESSURE | ERR_STRESS | ERR_NOSPEED)) {
-    s->last_error = "non-positive density, pressure or diagonal stress (bits " + std::to_string(h.err) + ")";
+  if (err & (ERR_DENSITY | ERR_PRESSURE | ERR_STRESS | ERR_NOSPEED)) {
+    b->last_error = "non-positive density, pressure or diagonal stress (bits " + std::to_string(err) + ")";
     return GP_E_NONPOSITIVE;
   }
   return GP_OK;
 }
 
-// device pointer of field `id` in the state visible to gp_get_field / gp_set_field
-void* field_ptr(gp_sim* s, int id, bool* is_double) {
+// device pointer of field `id` of run r in the state visible to get/set
+void* field_ptr(gp_batch* b, int r, int id, bool* is_double) {
+  RunHost& R = b->runs[r];
   if (id == GP_RHO || id == GP_N) {
     *is_double = true;
-    return s->dens[s->parity][id == GP_RHO ? 0 : 1];
+    return R.dens[b->parity][id == GP_RHO ? 0 : 1];
   }
-  *is_double = s->prec == GP_FP64;
-  if (id == GP_PHI) return s->phi;
+  *is_double = b->prec == GP_FP64;
+  if (id == GP_PHI) return R.phi;
   // between the Eulerian and Lagrangian stages the post-Eulerian fields are visible
-  const bool mid = (s->next_stage == GP_STAGE_LAG);
-  return mid ? s->tmp[oidx(id)] : s->cur[oidx(id)];
+  return (b->next_stage == GP_STAGE_LAG) ? R.tmp[oidx(id)] : R.cur[oidx(id)];
 }
 
 void convert_any(void* dst, bool dst_double, const void* src, bool src_double, size_t n, hipStream_t st) {
@@ -326,17 +412,450 @@ void convert_any(void* dst, bool dst_double, const void* src, bool src_double, s
     launch_convert<float, float>((float*)dst, (const float*)src, n, st);
 }
 
-double fft_bytes_per_cell(const gp_sim* s, int k) {
-  if (s->cfg.G == 0.0) return 0.0;
-  const double es = (double)esize(s->prec);
-  const double spec = 2.0 * es * s->fg.px / s->g.nx;  // half-spectrum bytes per cell
-  switch (k) {
-    case GP_K_FFT_X_FWD: return es + spec;
-    case GP_K_FFT_X_INV: return spec + es;
-    case GP_K_FFT_Y_FWD:
-    case GP_K_FFT_Z:
-    case GP_K_FFT_Y_INV: return 2.0 * spec;
-    default: return 0.0;
+template <typename T>
+RunDev<T> make_rundev(const RunHost& r) {
+  RunDev<T> d{};
+  d.g = r.g;
+  d.ph = r.ph;
+  for (int p = 0; p < 2; p++)
+    for (int q = 0; q < 2; q++) d.dens[p][q] = r.dens[p][q];
+  for (int o = 0; o < kNO; o++) {
+    d.cur[o] = static_cast<T*>(r.cur[o]);
+    d.tmp[o] = static_cast<T*>(r.tmp[o]);
+  }
+  d.vtx = static_cast<T*>(r.vtx);
+  d.vstride = r.vstride;
+  d.phi = static_cast<T*>(r.phi);
+  d.sc = r.sc;
+  d.row0 = r.row0;
+  d.ntx = r.ntx;
+  d.nty = r.nty;
+  d.vntx = r.vntx;
+  d.vnty = r.vnty;
+  return d;
+}
+
+gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip_stream) {
+  if (!cfgs || nruns < 1) return GP_E_INVALID;
+  for (int r = 0; r < nruns; r++) {
+    const gp_status v = validate(&cfgs[r]);
+    if (v != GP_OK) {
+      b->last_error = "run " + std::to_string(r) + ": invalid configuration";
+      return v;
+    }
+    if (cfgs[r].precision != cfgs[0].precision) return GP_E_INVALID;
+  }
+  b->prec = cfgs[0].precision;
+  if (hip_stream) {
+    b->st = static_cast<hipStream_t>(hip_stream);
+  } else {
+    // a blocking stream orders after work on the legacy default stream
+    if (hipStreamCreate(&b->st) != hipSuccess) return GP_E_HIP;
+    b->own_stream = true;
+  }
+  const size_t es = esize(b->prec);
+  gp_status st = GP_OK;
+
+  // runs and size classes (same grid, cell size and G share FFT launches)
+  std::map<std::tuple<int, int, int, double, double>, int> cls_of;
+  b->runs.resize(nruns);
+  unsigned row = 0;
+  for (int r = 0; r < nruns; r++) {
+    RunHost& R = b->runs[r];
+    R.cfg = cfgs[r];
+    R.g.nx = cfgs[r].n[0];
+    R.g.ny = cfgs[r].n[1];
+    R.g.nz = cfgs[r].n[2];
+    for (int d = 0; d < 3; d++) R.g.bc[d] = cfgs[r].bc[d];
+    R.g.h = (cfgs[r].hi[0] - cfgs[r].lo[0]) / cfgs[r].n[0];
+    R.g.ncell = (size_t)R.g.nx * R.g.ny * R.g.nz;
+    R.ph = Phys{cfgs[r].gamma, cfgs[r].G, cfgs[r].cfl, cfgs[r].eta, cfgs[r].fixed_dt, cfgs[r].t_end};
+    R.ntx = (R.g.nx + kTX - 1) / kTX;
+    R.nty = (R.g.ny + kTY - 1) / kTY;
+    R.ntiles = (unsigned)(R.ntx * R.nty * R.g.nz);
+    R.vntx = 0;  // vertices go in flat order, kBlock per work item
+    R.vnty = 0;
+    R.nvtiles = (unsigned)(((size_t)(R.g.nx + 1) * (R.g.ny + 1) * (R.g.nz + 1) + kBlock - 1) / kBlock);
+    R.row0 = row;
+    row += R.ntiles;
+    const auto key = std::make_tuple(R.g.nx, R.g.ny, R.g.nz, R.g.h, R.ph.G);
+    auto it = cls_of.find(key);
+    if (it == cls_of.end()) {
+      SizeClass c;
+      c.nx = R.g.nx;
+      c.ny = R.g.ny;
+      c.nz = R.g.nz;
+      c.h = R.g.h;
+      c.G = R.ph.G;
+      b->classes.push_back(c);
+      it = cls_of.emplace(key, (int)b->classes.size() - 1).first;
+    }
+    R.cls = it->second;
+    R.slot = (int)b->classes[R.cls].runs.size();
+    b->classes[R.cls].runs.push_back(r);
+  }
+
+  // per-run buffers
+  size_t max_cells = 0;
+  for (RunHost& R : b->runs) {
+    const size_t nc = R.g.ncell;
+    max_cells = std::max(max_cells, nc);
+    for (int p = 0; p < 2; p++)
+      for (int q = 0; q < 2; q++) R.dens[p][q] = static_cast<double*>(dalloc(b, nc * sizeof(double), &st));
+    for (int o = 0; o < kNO; o++) {
+      R.cur[o] = dalloc(b, nc * es, &st);
+      R.tmp[o] = dalloc(b, nc * es, &st);
+    }
+    R.vstride = (((size_t)(R.g.nx + 1) * (R.g.ny + 1) * (R.g.nz + 1)) + 63) / 64 * 64;
+    R.vtx = dalloc(b, 6 * R.vstride * es, &st);
+    R.sc = static_cast<DevScalars*>(dalloc(b, sizeof(DevScalars), &st));
+    R.ring = static_cast<gp_diag*>(dalloc(b, sizeof(gp_diag) * kDiagCap, &st));
+  }
+  b->staging = dalloc(b, max_cells * sizeof(double), &st);
+
+  // size classes: contiguous source / potential / spectrum, FFT tables
+  const int maxpts = 32768 / (int)(2 * es);
+  unsigned eoff = 0;
+  for (SizeClass& c : b->classes) {
+    FftGeom& f = c.fg;
+    f.nx = c.nx;
+    f.ny = c.ny;
+    f.nz = c.nz;
+    f.nruns = (int)c.runs.size();
+    f.px = f.nx / 2 + 1;
+    f.ax = make_axis(f.nx / 2);
+    f.ay = make_axis(f.ny);
+    f.az = make_axis(f.nz);
+    f.rows_per_block = std::max(1, maxpts / (2 * f.ax.L));
+    // columns per workgroup: at most 16 (and the LDS budget), spread evenly
+    // over the px = nx/2 + 1 half-spectrum columns so no chunk is nearly empty
+    auto even_cols = [&](int L) {
+      const int cmax = std::max(1, std::min({16, f.px, maxpts / L}));
+      const int nch = (f.px + cmax - 1) / cmax;
+      return (f.px + nch - 1) / nch;
+    };
+    f.cols_y = even_cols(f.ay.L);
+    f.cols_z = even_cols(f.az.L);
+    f.green_scale = -4.0 * M_PI * c.G * c.h * c.h / 6.0;
+    f.norm = 2.0 / ((double)f.nx * f.ny * f.nz);
+    const size_t nc = (size_t)c.nx * c.ny * c.nz, R = c.runs.size();
+    c.src = static_cast<SrcSlot*>(dalloc(b, R * sizeof(SrcSlot), &st));
+    c.phi = dalloc(b, R * nc * es, &st);
+    c.eoff = eoff;
+    if (c.G != 0.0) {
+      c.spec = dalloc(b, R * (size_t)f.px * f.ny * f.nz * 2 * es, &st);
+      c.tw_x = dalloc(b, (size_t)f.ax.L * 2 * es, &st);
+      c.wn_x = dalloc(b, (size_t)(f.ax.L + 1) * 2 * es, &st);
+      c.tw_y = dalloc(b, (size_t)f.ay.L * 2 * es, &st);
+      c.tw_z = dalloc(b, (size_t)f.az.L * 2 * es, &st);
+      c.dtab[0] = static_cast<double*>(dalloc(b, (size_t)f.px * sizeof(double), &st));
+      c.dtab[1] = static_cast<double*>(dalloc(b, (size_t)f.ny * sizeof(double), &st));
+      c.dtab[2] = static_cast<double*>(dalloc(b, (size_t)f.nz * sizeof(double), &st));
+      c.nep_run = (unsigned)(fft_blocks_z(f) / f.nruns);
+      eoff += (unsigned)fft_blocks_z(f);
+    }
+    if (st != GP_OK) return st;
+    for (size_t k = 0; k < R; k++) {
+      RunHost& run = b->runs[c.runs[k]];
+      run.phi = static_cast<char*>(c.phi) + k * nc * es;
+    }
+  }
+  b->nepot = eoff;
+  b->epot = static_cast<double*>(dalloc(b, std::max(1u, eoff) * sizeof(double), &st));
+
+  // work lists, partial rows, reduction items, finalize descriptors
+  std::vector<WorkItem> cw, vw;
+  std::vector<RedItem> items;
+  std::vector<FinDesc> fins;
+  unsigned soff = 0;
+  for (int r = 0; r < nruns; r++) {
+    RunHost& R = b->runs[r];
+    for (unsigned t = 0; t < R.ntiles; t++) cw.push_back({r, (int)t});
+    for (unsigned t = 0; t < R.nvtiles; t++) vw.push_back({r, (int)t});
+    const unsigned nscr = std::max(1u, std::min(256u, R.ntiles / 64));
+    const unsigned chunk = (R.ntiles + nscr - 1) / nscr;
+    for (unsigned c = 0; c < nscr; c++) {
+      const unsigned a = std::min(R.ntiles, c * chunk), e = std::min(R.ntiles, a + chunk);
+      items.push_back({R.row0 + a, R.row0 + e});
+    }
+    FinDesc fd{};
+    fd.g = R.g;
+    fd.ph = R.ph;
+    fd.soff = soff;
+    fd.nscr = nscr;
+    const SizeClass& c = b->classes[R.cls];
+    fd.eoff = c.eoff + (unsigned)R.slot * c.nep_run;
+    fd.nep = (c.G != 0.0) ? c.nep_run : 0u;
+    fd.epot_scale = 1.0 / (double)R.g.ncell;
+    fd.sc = R.sc;
+    fd.ring = R.ring;
+    fins.push_back(fd);
+    soff += nscr;
+  }
+  b->ncell_work = (unsigned)cw.size();
+  b->nvtx_work = (unsigned)vw.size();
+  b->nred = (int)items.size();
+  b->cell_work = static_cast<WorkItem*>(dalloc(b, cw.size() * sizeof(WorkItem), &st));
+  b->vtx_work = static_cast<WorkItem*>(dalloc(b, vw.size() * sizeof(WorkItem), &st));
+  b->partials = static_cast<double*>(dalloc(b, (size_t)row * kNP * sizeof(double), &st));
+  b->red_items = static_cast<RedItem*>(dalloc(b, items.size() * sizeof(RedItem), &st));
+  b->scratch = static_cast<double*>(dalloc(b, (size_t)soff * kNP * sizeof(double), &st));
+  b->fin = static_cast<FinDesc*>(dalloc(b, fins.size() * sizeof(FinDesc), &st));
+  const size_t rdsz = b->prec == GP_FP64 ? sizeof(RunDev<double>) : sizeof(RunDev<float>);
+  b->runs_dev = dalloc(b, rdsz * nruns, &st);
+  if (st != GP_OK) return st;
+
+  hipError_t e = hipSuccess;
+  for (auto& a : b->allocs)
+    if (e == hipSuccess) e = hipMemset(a.first, 0, a.second);
+  auto put = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  put(b->cell_work, cw.data(), cw.size() * sizeof(WorkItem));
+  put(b->vtx_work, vw.data(), vw.size() * sizeof(WorkItem));
+  put(b->red_items, items.data(), items.size() * sizeof(RedItem));
+  put(b->fin, fins.data(), fins.size() * sizeof(FinDesc));
+  if (b->prec == GP_FP64) {
+    std::vector<RunDev<double>> rd;
+    for (auto& R : b->runs) rd.push_back(make_rundev<double>(R));
+    put(b->runs_dev, rd.data(), rd.size() * sizeof(rd[0]));
+  } else {
+    std::vector<RunDev<float>> rd;
+    for (auto& R : b->runs) rd.push_back(make_rundev<float>(R));
+    put(b->runs_dev, rd.data(), rd.size() * sizeof(rd[0]));
+  }
+  auto put_tw = [&](void* dst, int n, int L) {
+    // exp(-2 pi i k / L), k < n, from host FP64 libm
+    std::vector<double> d(2 * (size_t)n);
+    for (int k = 0; k < n; k++) {
+      const double a = 2.0 * M_PI * (double)k / (double)L;
+      d[2 * k] = std::cos(a);
+      d[2 * k + 1] = -std::sin(a);
+    }
+    if (b->prec == GP_FP64) {
+      put(dst, d.data(), d.size() * sizeof(double));
+    } else {
+      std::vector<float> fl(d.begin(), d.end());
+      put(dst, fl.data(), fl.size() * sizeof(float));
+    }
+  };
+  auto put_d = [&](double* dst, int n, int N) {
+    std::vector<double> d(n);
+    for (int k = 0; k < n; k++) {
+      const double sn = std::sin(M_PI * (double)k / (double)N);
+      d[k] = 1.0 - 2.0 / 3.0 * sn * sn;
+    }
+    put(dst, d.data(), n * sizeof(double));
+  };
+  for (SizeClass& c : b->classes) {
+    std::vector<SrcSlot> slots;
+    for (int r : c.runs) {
+      const RunHost& R = b->runs[r];
+      slots.push_back({{R.dens[0][0], R.dens[1][0]}, {R.dens[0][1], R.dens[1][1]}, R.sc});
+    }
+    put(c.src, slots.data(), slots.size() * sizeof(SrcSlot));
+    if (c.G == 0.0) continue;
+    const FftGeom& f = c.fg;
+    put_tw(c.tw_x, f.ax.L, f.ax.L);
+    put_tw(c.wn_x, f.ax.L + 1, f.nx);
+    put_tw(c.tw_y, f.ay.L, f.ay.L);
+    put_tw(c.tw_z, f.az.L, f.az.L);
+    put_d(c.dtab[0], f.px, f.nx);
+    put_d(c.dtab[1], f.ny, f.ny);
+    put_d(c.dtab[2], f.nz, f.nz);
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(b, e, "engine upload");
+  for (int k = 0; k < GP_NKERNELS; k++) b->blocks[k] = 0;
+  b->blocks[GP_K_EUL] = b->ncell_work;
+  b->blocks[GP_K_LAG] = b->ncell_work;
+  b->blocks[GP_K_VERTEX] = b->nvtx_work;
+  return GP_OK;
+}
+
+void engine_free(gp_batch* b) {
+  if (b->st) (void)hipStreamSynchronize(b->st);
+  drop_graphs(b);
+  for (auto& a : b->allocs) (void)hipFree(a.first);
+  b->allocs.clear();
+  if (b->own_stream && b->st) (void)hipStreamDestroy(b->st);
+}
+
+gp_status engine_set_field(gp_batch* b, int r, int32_t field, const void* src, int32_t dtype, int32_t on_device) {
+  if (r < 0 || r >= (int)b->runs.size() || !src || field < 0 || field >= GP_NFIELDS ||
+      (dtype != GP_FP64 && dtype != GP_FP32))
+    return GP_E_INVALID;
+  if (b->next_stage != GP_STAGE_EUL) return GP_E_STATE;
+  bool dst_double = false;
+  void* dst = field_ptr(b, r, field, &dst_double);
+  const bool src_double = dtype == GP_FP64;
+  const size_t nc = b->runs[r].g.ncell;
+  if (on_device) {
+    convert_any(dst, dst_double, src, src_double, nc, b->st);
+  } else {
+    const size_t bytes = nc * (src_double ? sizeof(double) : sizeof(float));
+    if (src_double == dst_double) {
+      HIP_TRY(b, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->st));
+    } else {
+      HIP_TRY(b, hipMemcpyAsync(b->staging, src, bytes, hipMemcpyHostToDevice, b->st));
+      convert_any(dst, dst_double, b->staging, src_double, nc, b->st);
+    }
+    HIP_TRY(b, hipStreamSynchronize(b->st));
+  }
+  HIP_TRY(b, hipGetLastError());
+  b->need_prologue = true;
+  return GP_OK;
+}
+
+gp_status engine_get_field(gp_batch* b, int r, int32_t field, void* dst, int32_t dtype, int32_t on_device) {
+  if (r < 0 || r >= (int)b->runs.size() || !dst || field < 0 || field > GP_PHI ||
+      (dtype != GP_FP64 && dtype != GP_FP32))
+    return GP_E_INVALID;
+  if (field == GP_PHI && b->need_prologue) {
+    if (b->next_stage != GP_STAGE_EUL) return GP_E_STATE;
+    run_prologue(b);
+  }
+  bool src_double = false;
+  const void* src = field_ptr(b, r, field, &src_double);
+  const bool dst_double = dtype == GP_FP64;
+  const size_t nc = b->runs[r].g.ncell;
+  const bool mid = b->next_stage == GP_STAGE_LAG;
+  const bool gas_mom = field >= GP_MX && field <= GP_MZ, bme_mom = field >= GP_QX && field <= GP_QZ;
+  if (mid && (gas_mom || bme_mom)) {
+    // between the stages the momentum slots hold velocities: return density * velocity
+    const double* dens = b->runs[r].dens[b->parity][gas_mom ? 0 : 1];
+    void* out = on_device ? dst : b->staging;
+    if (b->prec == GP_FP64) {
+      if (dst_double) launch_density_times<double, double>((double*)out, dens, (const double*)src, nc, b->st);
+      else launch_density_times<float, double>((float*)out, dens, (const double*)src, nc, b->st);
+    } else {
+      if (dst_double) launch_density_times<double, float>((double*)out, dens, (const float*)src, nc, b->st);
+      else launch_density_times<float, float>((float*)out, dens, (const float*)src, nc, b->st);
+    }
+    if (!on_device)
+      HIP_TRY(b, hipMemcpyAsync(dst, b->staging, nc * (dst_double ? 8 : 4), hipMemcpyDeviceToHost, b->st));
+  } else if (on_device) {
+    convert_any(dst, dst_double, src, src_double, nc, b->st);
+  } else {
+    const size_t bytes = nc * (dst_double ? sizeof(double) : sizeof(float));
+    if (src_double == dst_double) {
+      HIP_TRY(b, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, b->st));
+    } else {
+      convert_any(b->staging, dst_double, src, src_double, nc, b->st);
+      HIP_TRY(b, hipMemcpyAsync(dst, b->staging, bytes, hipMemcpyDeviceToHost, b->st));
+    }
+  }
+  HIP_TRY(b, hipStreamSynchronize(b->st));
+  HIP_TRY(b, hipGetLastError());
+  return latched(b);
+}
+
+gp_status engine_step(gp_batch* b, int32_t nsteps) {
+  if (nsteps < 0) return GP_E_INVALID;
+  if (b->next_stage != GP_STAGE_EUL) return GP_E_STATE;
+  if (b->need_prologue) run_prologue(b);
+  for (int t = 0; t < nsteps; t++) {
+    if (b->use_graph && (b->tuned || !b->tune)) {
+      if (!b->graph_ready[b->parity]) {
+        gp_status r = build_graph(b, b->parity);
+        if (r != GP_OK) return r;
+      }
+      HIP_TRY(b, hipGraphLaunch(b->gexec[b->parity], b->st));
+      b->parity ^= 1;
+    } else {
+      run_step_direct(b, nullptr, true);
+    }
+  }
+  HIP_TRY(b, hipGetLastError());
+  return GP_OK;
+}
+
+gp_status engine_get_diag(gp_batch* b, int r, gp_diag* out, int32_t max, int32_t* count) {
+  if (r < 0 || r >= (int)b->runs.size() || !out || !count || max < 0) return GP_E_INVALID;
+  if (b->need_prologue && b->next_stage == GP_STAGE_EUL) run_prologue(b);
+  HIP_TRY(b, hipStreamSynchronize(b->st));
+  DevScalars h{};
+  HIP_TRY(b, hipMemcpy(&h, b->runs[r].sc, sizeof(h), hipMemcpyDeviceToHost));
+  const int avail = (int)std::min<uint32_t>(h.ndiag, (uint32_t)kDiagCap);
+  const int n = std::min(avail, (int)max);
+  std::vector<gp_diag> all(kDiagCap);
+  HIP_TRY(b, hipMemcpy(all.data(), b->runs[r].ring, sizeof(gp_diag) * kDiagCap, hipMemcpyDeviceToHost));
+  for (int t = 0; t < n; t++) out[t] = all[(h.ndiag - n + t) % kDiagCap];
+  *count = n;
+  return GP_OK;
+}
+
+gp_status engine_time_kernels(gp_batch* b, int32_t nsteps, double* ms, int32_t max) {
+  if (!ms || nsteps <= 0 || max < 0) return GP_E_INVALID;
+  if (b->next_stage != GP_STAGE_EUL) return GP_E_STATE;
+  if (b->need_prologue) run_prologue(b);
+  if (b->tune && !b->tuned) run_step_direct(b, nullptr, true);  // tune first
+  Timer tm;
+  tm.on = true;
+  for (int k = 0; k < 2 * GP_NKERNELS; k++) HIP_TRY(b, hipEventCreate(&tm.ev[k]));
+  for (int k = 0; k < GP_NKERNELS; k++) tm.acc[k] = 0.0;
+  for (int t = 0; t < nsteps; t++) run_step_direct(b, &tm, false);
+  for (int k = 0; k < 2 * GP_NKERNELS; k++) (void)hipEventDestroy(tm.ev[k]);
+  for (int k = 0; k < std::min<int>(max, GP_NKERNELS); k++) ms[k] = tm.acc[k] / nsteps;
+  HIP_TRY(b, hipGetLastError());
+  return GP_OK;
+}
+
+gp_status engine_set_launch(gp_batch* b, int32_t kernel, int32_t blocks) {
+  int which = -1;
+  for (int q = 0; q < kTunedKernels; q++)
+    if (kTunedIds[q] == kernel) which = q;
+  if (which < 0 || blocks < 0) return GP_E_INVALID;
+  const unsigned nw = work_count(b, kernel);
+  b->blocks[kernel] = blocks == 0 ? nw : std::min<unsigned>((unsigned)blocks, nw);
+  b->tune = false;
+  drop_graphs(b);
+  return GP_OK;
+}
+
+double fft_bytes_per_cell(const gp_batch* b, int k) {
+  // cell-weighted over the runs that solve Poisson
+  double cells = 0.0, bytes = 0.0;
+  const double es = (double)esize(b->prec);
+  for (const RunHost& R : b->runs) {
+    cells += (double)R.g.ncell;
+    if (R.ph.G == 0.0) continue;
+    const double spec = 2.0 * es * (R.g.nx / 2 + 1) / R.g.nx;
+    double v = 0.0;
+    switch (k) {
+      case GP_K_FFT_X_FWD: v = 16.0 + spec; break;  // reads rho and n (FP64)
+      case GP_K_FFT_X_INV: v = spec + es; break;
+      case GP_K_FFT_Y_FWD:
+      case GP_K_FFT_Z:
+      case GP_K_FFT_Y_INV: v = 2.0 * spec; break;
+    }
+    bytes += v * (double)R.g.ncell;
+  }
+  return cells > 0 ? bytes / cells : 0.0;
+}
+
+double engine_bytes_per_cell(const gp_batch* b, int32_t kernel) {
+  const double es = (double)esize(b->prec);
+  double cells = 0.0, vr = 0.0;
+  for (const RunHost& R : b->runs) {
+    cells += (double)R.g.ncell;
+    vr += (double)(R.g.nx + 1) * (R.g.ny + 1) * (R.g.nz + 1);
+  }
+  vr /= cells;  // vertices per cell
+  const double eul = 2 * 8.0 + 20 * es + es + 20 * es;  // read rho, n, 20 fields, Phi; write 20
+  const double vtx = 6 * es + 6 * es * vr;              // read 6 velocities; write 6 per vertex
+  const double lag = 2 * 8.0 + 20 * es + 6 * es * vr + 2 * 8.0 + 20 * es;  // + corners; write 22
+  switch (kernel) {
+    case GP_K_EUL: return eul;
+    case GP_K_VERTEX: return vtx;
+    case GP_K_LAG: return lag;
+    case GP_K_FINALIZE: return 0.0;
+    case -1: {
+      double t = eul + vtx + lag;
+      for (int k = GP_K_FFT_X_FWD; k <= GP_K_FFT_X_INV; k++) t += fft_bytes_per_cell(b, k);
+      return t;
+    }
+    default: return fft_bytes_per_cell(b, kernel);
   }
 }
 
@@ -358,234 +877,44 @@ const char* gp_status_str(gp_status s) {
   return "unknown status";
 }
 
-const char* gp_last_error(const gp_sim* sim) { return sim ? sim->last_error.c_str() : "null sim"; }
+// ---- single simulation ------------------------------------------------------
 
-gp_status gp_destroy(gp_sim* s) {
-  if (!s) return GP_E_INVALID;
-  if (s->st) (void)hipStreamSynchronize(s->st);
-  for (int p = 0; p < 2; p++)
-    if (s->gexec[p]) (void)hipGraphExecDestroy(s->gexec[p]);
-  for (auto& a : s->allocs) (void)hipFree(a.first);
-  if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
-  delete s;
-  return GP_OK;
-}
+const char* gp_last_error(const gp_sim* sim) { return sim ? sim->last_error.c_str() : "null sim"; }
 
 gp_status gp_create(const gp_config* cfg, void* hip_stream, gp_sim** out) {
   if (!cfg || !out) return GP_E_INVALID;
   *out = nullptr;
-  for (int d = 0; d < 3; d++) {
-    if (cfg->n[d] < 4 || cfg->n[d] > 1024 || !(cfg->hi[d] > cfg->lo[d])) return GP_E_INVALID;
-    if (cfg->bc[d] != GP_BC_OUTFLOW && cfg->bc[d] != GP_BC_PERIODIC) return GP_E_INVALID;
-  }
-  const double h = (cfg->hi[0] - cfg->lo[0]) / cfg->n[0];
-  for (int d = 1; d < 3; d++)
-    if (std::fabs((cfg->hi[d] - cfg->lo[d]) / cfg->n[d] - h) > 1e-12 * h) return GP_E_INVALID;
-  if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0) || cfg->reserved != 0) return GP_E_INVALID;
-  if (cfg->precision != GP_FP64 && cfg->precision != GP_FP32) return GP_E_INVALID;
-  if (cfg->G != 0.0)
-    for (int d = 0; d < 3; d++)
-      if (!fft_len_ok(cfg->n[d]) || cfg->n[d] % 2 != 0) return GP_E_UNSUPPORTED;
-
   gp_sim* s = new gp_sim();
-  s->cfg = *cfg;
-  s->prec = cfg->precision;
-  s->g.nx = cfg->n[0];
-  s->g.ny = cfg->n[1];
-  s->g.nz = cfg->n[2];
-  for (int d = 0; d < 3; d++) s->g.bc[d] = cfg->bc[d];
-  s->g.h = h;
-  s->g.ncell = (size_t)s->g.nx * s->g.ny * s->g.nz;
-  s->ph = Phys{cfg->gamma, cfg->G, cfg->cfl, cfg->eta, cfg->fixed_dt, cfg->t_end};
-  (void)hipGetDevice(&s->device);
-  if (hip_stream) {
-    s->st = static_cast<hipStream_t>(hip_stream);
-  } else {
-    // a blocking stream orders after work on the legacy default stream
-    if (hipStreamCreate(&s->st) != hipSuccess) {
-      delete s;
-      return GP_E_HIP;
-    }
-    s->own_stream = true;
-  }
-
-  const size_t nc = s->g.ncell, es = esize(s->prec);
-  gp_status st = GP_OK;
-  for (int p = 0; p < 2; p++)
-    for (int q = 0; q < 2; q++) s->dens[p][q] = static_cast<double*>(dalloc(s, nc * sizeof(double), &st));
-  for (int o = 0; o < kNO; o++) {
-    s->cur[o] = dalloc(s, nc * es, &st);
-    s->tmp[o] = dalloc(s, nc * es, &st);
-  }
-  s->vstride = (((size_t)(s->g.nx + 1) * (s->g.ny + 1) * (s->g.nz + 1)) + 63) / 64 * 64;
-  s->vtx = dalloc(s, 6 * s->vstride * es, &st);
-  s->s = dalloc(s, nc * es, &st);
-  s->phi = dalloc(s, nc * es, &st);
-  s->staging = dalloc(s, nc * sizeof(double), &st);
-  s->nrows = (int)cell_blocks(s->g);
-  s->partials = static_cast<double*>(dalloc(s, (size_t)s->nrows * kNP * sizeof(double), &st));
-  s->nscratch = std::max(1, std::min(256, s->nrows / 64));
-  s->scratch = static_cast<double*>(dalloc(s, (size_t)s->nscratch * kNP * sizeof(double), &st));
-  s->sc = static_cast<DevScalars*>(dalloc(s, sizeof(DevScalars), &st));
-  s->ring = static_cast<gp_diag*>(dalloc(s, sizeof(gp_diag) * kDiagCap, &st));
-
-  // FFT geometry and tables (host FP64 libm, converted to the working type)
-  FftGeom& f = s->fg;
-  f.nx = s->g.nx;
-  f.ny = s->g.ny;
-  f.nz = s->g.nz;
-  f.px = f.nx / 2 + 1;
-  f.ax = make_axis(f.nx / 2);
-  f.ay = make_axis(f.ny);
-  f.az = make_axis(f.nz);
-  const int maxpts = 32768 / (int)(2 * es);
-  f.rows_per_block = std::max(1, maxpts / (2 * f.ax.L));
-  f.cols_y = std::max(1, std::min({16, f.px, maxpts / f.ay.L}));
-  f.cols_z = std::max(1, std::min({16, f.px, maxpts / f.az.L}));
-  f.green_scale = -4.0 * M_PI * cfg->G * h * h / 6.0;
-  f.norm = 2.0 / ((double)f.nx * f.ny * f.nz);
-  s->nepot = fft_blocks_z(f);
-  s->spec = dalloc(s, (size_t)f.px * f.ny * f.nz * 2 * es, &st);
-  s->epot = static_cast<double*>(dalloc(s, (size_t)s->nepot * sizeof(double), &st));
-  s->tw_x = dalloc(s, (size_t)f.ax.L * 2 * es, &st);
-  s->wn_x = dalloc(s, (size_t)(f.ax.L + 1) * 2 * es, &st);
-  s->tw_y = dalloc(s, (size_t)f.ay.L * 2 * es, &st);
-  s->tw_z = dalloc(s, (size_t)f.az.L * 2 * es, &st);
-  s->dtab[0] = static_cast<double*>(dalloc(s, (size_t)f.px * sizeof(double), &st));
-  s->dtab[1] = static_cast<double*>(dalloc(s, (size_t)f.ny * sizeof(double), &st));
-  s->dtab[2] = static_cast<double*>(dalloc(s, (size_t)f.nz * sizeof(double), &st));
-  if (st != GP_OK) {
-    gp_destroy(s);
-    return st;
-  }
-
-  auto upload_tw = [&](void* dst, int n, int L) -> hipError_t {
-    // exp(-2 pi i k / L), k < n
-    std::vector<double> d(2 * (size_t)n);
-    for (int k = 0; k < n; k++) {
-      const double a = 2.0 * M_PI * (double)k / (double)L;
-      d[2 * k] = std::cos(a);
-      d[2 * k + 1] = -std::sin(a);
-    }
-    if (s->prec == GP_FP64) return hipMemcpy(dst, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice);
-    std::vector<float> fl(d.begin(), d.end());
-    return hipMemcpy(dst, fl.data(), fl.size() * sizeof(float), hipMemcpyHostToDevice);
-  };
-  auto upload_d = [&](double* dst, int n, int N) -> hipError_t {
-    std::vector<double> d(n);
-    for (int k = 0; k < n; k++) {
-      const double sn = std::sin(M_PI * (double)k / (double)N);
-      d[k] = 1.0 - 2.0 / 3.0 * sn * sn;
-    }
-    return hipMemcpy(dst, d.data(), n * sizeof(double), hipMemcpyHostToDevice);
-  };
-  hipError_t e = hipSuccess;
-  // zero every buffer once (outside any captured graph), then fill the tables
-  for (auto& a : s->allocs)
-    if (e == hipSuccess) e = hipMemset(a.first, 0, a.second);
-  if (e == hipSuccess) e = upload_tw(s->tw_x, f.ax.L, f.ax.L);
-  if (e == hipSuccess) e = upload_tw(s->wn_x, f.ax.L + 1, f.nx);
-  if (e == hipSuccess) e = upload_tw(s->tw_y, f.ay.L, f.ay.L);
-  if (e == hipSuccess) e = upload_tw(s->tw_z, f.az.L, f.az.L);
-  if (e == hipSuccess) e = upload_d(s->dtab[0], f.px, f.nx);
-  if (e == hipSuccess) e = upload_d(s->dtab[1], f.ny, f.ny);
-  if (e == hipSuccess) e = upload_d(s->dtab[2], f.nz, f.nz);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    hip_fail(s, e, "gp_create upload");
-    gp_destroy(s);
-    return GP_E_HIP;
+  const gp_status r = engine_create(s, cfg, 1, hip_stream);
+  if (r != GP_OK) {
+    engine_free(s);
+    delete s;
+    return r;
   }
   *out = s;
   return GP_OK;
 }
 
-gp_status gp_set_field(gp_sim* s, int32_t field, const void* src, int32_t dtype, int32_t on_device) {
-  if (!s || !src || field < 0 || field >= GP_NFIELDS || (dtype != GP_FP64 && dtype != GP_FP32))
-    return GP_E_INVALID;
-  if (s->next_stage != GP_STAGE_EUL) return GP_E_STATE;
-  bool dst_double = false;
-  void* dst = field_ptr(s, field, &dst_double);
-  const bool src_double = dtype == GP_FP64;
-  const size_t nc = s->g.ncell;
-  if (on_device) {
-    convert_any(dst, dst_double, src, src_double, nc, s->st);
-  } else {
-    const size_t bytes = nc * (src_double ? sizeof(double) : sizeof(float));
-    if (src_double == dst_double) {
-      HIP_TRY(s, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->st));
-    } else {
-      HIP_TRY(s, hipMemcpyAsync(s->staging, src, bytes, hipMemcpyHostToDevice, s->st));
-      convert_any(dst, dst_double, s->staging, src_double, nc, s->st);
-    }
-    HIP_TRY(s, hipStreamSynchronize(s->st));
-  }
-  HIP_TRY(s, hipGetLastError());
-  s->need_prologue = true;
+gp_status gp_destroy(gp_sim* s) {
+  if (!s) return GP_E_INVALID;
+  engine_free(s);
+  delete s;
   return GP_OK;
+}
+
+gp_status gp_set_field(gp_sim* s, int32_t field, const void* src, int32_t dtype, int32_t on_device) {
+  if (!s) return GP_E_INVALID;
+  return engine_set_field(s, 0, field, src, dtype, on_device);
 }
 
 gp_status gp_get_field(gp_sim* s, int32_t field, void* dst, int32_t dtype, int32_t on_device) {
-  if (!s || !dst || field < 0 || field > GP_PHI || (dtype != GP_FP64 && dtype != GP_FP32)) return GP_E_INVALID;
-  if (field == GP_PHI && s->need_prologue) {
-    if (s->next_stage != GP_STAGE_EUL) return GP_E_STATE;
-    run_prologue(s);
-  }
-  bool src_double = false;
-  const void* src = field_ptr(s, field, &src_double);
-  const bool dst_double = dtype == GP_FP64;
-  const size_t nc = s->g.ncell;
-  const bool mid = s->next_stage == GP_STAGE_LAG;
-  const bool gas_mom = field >= GP_MX && field <= GP_MZ, bme_mom = field >= GP_QX && field <= GP_QZ;
-  if (mid && (gas_mom || bme_mom)) {
-    // between the stages the momentum slots hold velocities: return density * velocity
-    const double* dens = s->dens[s->parity][gas_mom ? 0 : 1];
-    void* out = on_device ? dst : s->staging;
-    if (s->prec == GP_FP64) {
-      if (dst_double) launch_density_times<double, double>((double*)out, dens, (const double*)src, nc, s->st);
-      else launch_density_times<float, double>((float*)out, dens, (const double*)src, nc, s->st);
-    } else {
-      if (dst_double) launch_density_times<double, float>((double*)out, dens, (const float*)src, nc, s->st);
-      else launch_density_times<float, float>((float*)out, dens, (const float*)src, nc, s->st);
-    }
-    if (!on_device)
-      HIP_TRY(s, hipMemcpyAsync(dst, s->staging, nc * (dst_double ? 8 : 4), hipMemcpyDeviceToHost, s->st));
-    HIP_TRY(s, hipStreamSynchronize(s->st));
-  } else if (on_device) {
-    convert_any(dst, dst_double, src, src_double, nc, s->st);
-    HIP_TRY(s, hipStreamSynchronize(s->st));
-  } else {
-    const size_t bytes = nc * (dst_double ? sizeof(double) : sizeof(float));
-    if (src_double == dst_double) {
-      HIP_TRY(s, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->st));
-    } else {
-      convert_any(s->staging, dst_double, src, src_double, nc, s->st);
-      HIP_TRY(s, hipMemcpyAsync(dst, s->staging, bytes, hipMemcpyDeviceToHost, s->st));
-    }
-    HIP_TRY(s, hipStreamSynchronize(s->st));
-  }
-  HIP_TRY(s, hipGetLastError());
-  return latched(s);
+  if (!s) return GP_E_INVALID;
+  return engine_get_field(s, 0, field, dst, dtype, on_device);
 }
 
 gp_status gp_step(gp_sim* s, int32_t nsteps) {
-  if (!s || nsteps < 0) return GP_E_INVALID;
-  if (s->next_stage != GP_STAGE_EUL) return GP_E_STATE;
-  if (s->need_prologue) run_prologue(s);
-  for (int t = 0; t < nsteps; t++) {
-    if (s->use_graph) {
-      if (!s->graph_ready[s->parity]) {
-        gp_status r = build_graph(s, s->parity);
-        if (r != GP_OK) return r;
-      }
-      HIP_TRY(s, hipGraphLaunch(s->gexec[s->parity], s->st));
-      s->parity ^= 1;
-    } else {
-      run_step_direct(s, nullptr);
-    }
-  }
-  HIP_TRY(s, hipGetLastError());
-  return GP_OK;
+  if (!s) return GP_E_INVALID;
+  return engine_step(s, nsteps);
 }
 
 gp_status gp_sync(gp_sim* s) {
@@ -595,18 +924,8 @@ gp_status gp_sync(gp_sim* s) {
 }
 
 gp_status gp_get_diag(gp_sim* s, gp_diag* out, int32_t max, int32_t* count) {
-  if (!s || !out || !count || max < 0) return GP_E_INVALID;
-  if (s->need_prologue && s->next_stage == GP_STAGE_EUL) run_prologue(s);
-  HIP_TRY(s, hipStreamSynchronize(s->st));
-  DevScalars h{};
-  HIP_TRY(s, hipMemcpy(&h, s->sc, sizeof(h), hipMemcpyDeviceToHost));
-  const int avail = (int)std::min<uint32_t>(h.ndiag, (uint32_t)kDiagCap);
-  const int n = std::min(avail, (int)max);
-  std::vector<gp_diag> all(kDiagCap);
-  HIP_TRY(s, hipMemcpy(all.data(), s->ring, sizeof(gp_diag) * kDiagCap, hipMemcpyDeviceToHost));
-  for (int t = 0; t < n; t++) out[t] = all[(h.ndiag - n + t) % kDiagCap];
-  *count = n;
-  return GP_OK;
+  if (!s) return GP_E_INVALID;
+  return engine_get_diag(s, 0, out, max, count);
 }
 
 gp_status gp_set_time(gp_sim* s, double t, int64_t step) {
@@ -614,10 +933,10 @@ gp_status gp_set_time(gp_sim* s, double t, int64_t step) {
   if (s->next_stage != GP_STAGE_EUL) return GP_E_STATE;
   HIP_TRY(s, hipStreamSynchronize(s->st));
   DevScalars h{};
-  HIP_TRY(s, hipMemcpy(&h, s->sc, sizeof(h), hipMemcpyDeviceToHost));
+  HIP_TRY(s, hipMemcpy(&h, s->runs[0].sc, sizeof(h), hipMemcpyDeviceToHost));
   h.t = t;
   h.step = step;
-  HIP_TRY(s, hipMemcpy(s->sc, &h, sizeof(h), hipMemcpyHostToDevice));
+  HIP_TRY(s, hipMemcpy(s->runs[0].sc, &h, sizeof(h), hipMemcpyHostToDevice));
   s->need_prologue = true;
   return GP_OK;
 }
@@ -627,7 +946,7 @@ gp_status gp_get_time(gp_sim* s, double* t, double* dt, int64_t* step) {
   if (s->need_prologue && s->next_stage == GP_STAGE_EUL) run_prologue(s);
   HIP_TRY(s, hipStreamSynchronize(s->st));
   DevScalars h{};
-  HIP_TRY(s, hipMemcpy(&h, s->sc, sizeof(h), hipMemcpyDeviceToHost));
+  HIP_TRY(s, hipMemcpy(&h, s->runs[0].sc, sizeof(h), hipMemcpyDeviceToHost));
   if (t) *t = h.t;
   if (dt) *dt = h.dt;
   if (step) *step = h.step;
@@ -638,25 +957,15 @@ gp_status gp_debug_stage(gp_sim* s, int32_t stage) {
   if (!s || stage < GP_STAGE_EUL || stage > GP_STAGE_FINALIZE) return GP_E_INVALID;
   if (s->need_prologue && s->next_stage == GP_STAGE_EUL) run_prologue(s);
   if (stage != s->next_stage) return GP_E_STATE;
-  run_stage(s, stage, nullptr);
+  run_stage(s, stage, nullptr, false);
   s->next_stage = (stage + 1) % 4;
   HIP_TRY(s, hipGetLastError());
   return GP_OK;
 }
 
 gp_status gp_time_kernels(gp_sim* s, int32_t nsteps, double* ms, int32_t max) {
-  if (!s || !ms || nsteps <= 0 || max < 0) return GP_E_INVALID;
-  if (s->next_stage != GP_STAGE_EUL) return GP_E_STATE;
-  if (s->need_prologue) run_prologue(s);
-  Timer tm;
-  tm.on = true;
-  for (int k = 0; k < 2 * GP_NKERNELS; k++) HIP_TRY(s, hipEventCreate(&tm.ev[k]));
-  for (int k = 0; k < GP_NKERNELS; k++) tm.acc[k] = 0.0;
-  for (int t = 0; t < nsteps; t++) run_step_direct(s, &tm);
-  for (int k = 0; k < 2 * GP_NKERNELS; k++) (void)hipEventDestroy(tm.ev[k]);
-  for (int k = 0; k < std::min<int>(max, GP_NKERNELS); k++) ms[k] = tm.acc[k] / nsteps;
-  HIP_TRY(s, hipGetLastError());
-  return GP_OK;
+  if (!s) return GP_E_INVALID;
+  return engine_time_kernels(s, nsteps, ms, max);
 }
 
 gp_status gp_use_graph(gp_sim* s, int32_t enable) {
@@ -665,25 +974,99 @@ gp_status gp_use_graph(gp_sim* s, int32_t enable) {
   return GP_OK;
 }
 
-double gp_algorithmic_bytes_per_cell(const gp_sim* s, int32_t kernel) {
-  if (!s) return 0.0;
-  const double es = (double)esize(s->prec);
-  const double vr = (double)(s->g.nx + 1) * (s->g.ny + 1) * (s->g.nz + 1) / (double)s->g.ncell;
-  const double eul = 2 * 8.0 + 20 * es + es + 20 * es;  // read rho, n, 20 fields, Phi; write 20
-  const double vtx = 6 * es + 6 * es * vr;              // read 6 velocities; write 6 per vertex
-  const double lag = 2 * 8.0 + 20 * es + 6 * es * vr + 2 * 8.0 + 20 * es + es;  // read rho, n, 20, corners; write 22 + s
-  switch (kernel) {
-    case GP_K_EUL: return eul;
-    case GP_K_VERTEX: return vtx;
-    case GP_K_LAG: return lag;
-    case GP_K_FINALIZE: return 0.0;
-    case -1: {
-      double t = eul + vtx + lag;
-      for (int k = GP_K_FFT_X_FWD; k <= GP_K_FFT_X_INV; k++) t += fft_bytes_per_cell(s, k);
-      return t;
-    }
-    default: return fft_bytes_per_cell(s, kernel);
-  }
+gp_status gp_set_launch(gp_sim* s, int32_t kernel, int32_t blocks) {
+  if (!s) return GP_E_INVALID;
+  return engine_set_launch(s, kernel, blocks);
 }
+
+gp_status gp_get_launch(gp_sim* s, int32_t kernel, int32_t* blocks) {
+  if (!s || !blocks || kernel < 0 || kernel >= GP_NKERNELS) return GP_E_INVALID;
+  *blocks = (int32_t)s->blocks[kernel];
+  return GP_OK;
+}
+
+double gp_algorithmic_bytes_per_cell(const gp_sim* s, int32_t kernel) {
+  return s ? engine_bytes_per_cell(s, kernel) : 0.0;
+}
+
+// ---- batches -------------------------------------------------------------------
+
+gp_status gp_batch_create(const gp_config* cfgs, int32_t nruns, void* hip_stream, gp_batch** out) {
+  if (!cfgs || !out || nruns < 1) return GP_E_INVALID;
+  *out = nullptr;
+  gp_batch* b = new gp_batch();
+  const gp_status r = engine_create(b, cfgs, nruns, hip_stream);
+  if (r != GP_OK) {
+    engine_free(b);
+    delete b;
+    return r;
+  }
+  *out = b;
+  return GP_OK;
+}
+
+gp_status gp_batch_destroy(gp_batch* b) {
+  if (!b) return GP_E_INVALID;
+  engine_free(b);
+  delete b;
+  return GP_OK;
+}
+
+gp_status gp_batch_set_field(gp_batch* b, int32_t run, int32_t field, const void* src, int32_t dtype,
+                             int32_t on_device) {
+  if (!b) return GP_E_INVALID;
+  return engine_set_field(b, run, field, src, dtype, on_device);
+}
+
+gp_status gp_batch_get_field(gp_batch* b, int32_t run, int32_t field, void* dst, int32_t dtype,
+                             int32_t on_device) {
+  if (!b) return GP_E_INVALID;
+  return engine_get_field(b, run, field, dst, dtype, on_device);
+}
+
+gp_status gp_batch_step(gp_batch* b, int32_t nsteps) {
+  if (!b) return GP_E_INVALID;
+  return engine_step(b, nsteps);
+}
+
+gp_status gp_batch_sync(gp_batch* b) {
+  if (!b) return GP_E_INVALID;
+  HIP_TRY(b, hipStreamSynchronize(b->st));
+  return latched(b);
+}
+
+gp_status gp_batch_get_diag(gp_batch* b, int32_t run, gp_diag* out, int32_t max, int32_t* count) {
+  if (!b) return GP_E_INVALID;
+  return engine_get_diag(b, run, out, max, count);
+}
+
+gp_status gp_batch_time_kernels(gp_batch* b, int32_t nsteps, double* ms, int32_t max) {
+  if (!b) return GP_E_INVALID;
+  return engine_time_kernels(b, nsteps, ms, max);
+}
+
+gp_status gp_batch_set_launch(gp_batch* b, int32_t kernel, int32_t blocks) {
+  if (!b) return GP_E_INVALID;
+  return engine_set_launch(b, kernel, blocks);
+}
+
+gp_status gp_batch_get_launch(gp_batch* b, int32_t kernel, int32_t* blocks) {
+  if (!b || !blocks || kernel < 0 || kernel >= GP_NKERNELS) return GP_E_INVALID;
+  *blocks = (int32_t)b->blocks[kernel];
+  return GP_OK;
+}
+
+double gp_batch_algorithmic_bytes_per_cell(const gp_batch* b, int32_t kernel) {
+  return b ? engine_bytes_per_cell(b, kernel) : 0.0;
+}
+
+int64_t gp_batch_cells(const gp_batch* b) {
+  if (!b) return 0;
+  int64_t n = 0;
+  for (const RunHost& R : b->runs) n += (int64_t)R.g.ncell;
+  return n;
+}
+
+const char* gp_batch_last_error(const gp_batch* b) { return b ? b->last_error.c_str() : "null batch"; }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ template <typename T>
 __device__ __forceinline__ void load_prim(const Fields<T>& s, size_t c, T gm1, Prim<T>& q) {
   q.rho = (T)s.rho[c];
   q.n = (T)s.nb[c];
-  const T ir = T(1) / q.rho, in = T(1) / q.n;
+  const T ir = rcp(q.rho), in = rcp(q.n);
 #pragma unroll
   for (int d = 0; d < 3; d++) {
     q.v[d] = s.o[oidx(GP_MX + d)][c] * ir;
@@ -45,8 +45,8 @@ template <typename T>
 __device__ __forceinline__ void gas_face(const Prim<T>& L, const Prim<T>& R, int d, T gamma, T& V,
                                          T& P) {
   const T pl = L.p, pr = R.p;
-  const T z = sqrt(gamma * (pl + pr) * L.rho * R.rho / (L.rho + R.rho));
-  const T rz = T(1) / z;
+  const T z = sqrt(gamma * (pl + pr) * L.rho * R.rho * rcp(L.rho + R.rho));
+  const T rz = rcp(z);
   V = T(0.5) * (L.v[d] + R.v[d]) + T(0.5) * (pl - pr) * rz;
   P = T(0.5) * (pl + pr) + T(0.5) * (L.v[d] - R.v[d]) * z;
 }
@@ -65,10 +65,10 @@ __device__ __forceinline__ void bme_face(const Prim<T>& L, const Prim<T>& R, T u
   const T B = T(0.5) * (L.P[sDA] + R.P[sDA]);
   const T C = T(0.5) * (L.P[sDB] + R.P[sDB]);
   const T Z1 = sqrt(T(3) * nbar * A);  // sqrt(3 n Pi_DD): fast wave impedance
-  const T rZ1 = T(1) / Z1;
+  const T rZ1 = rcp(Z1);
   const T Z2 = Z1 * T(0.57735026918962576451);   // sqrt(n Pi_DD): slow (shear) impedance
   const T rZ2 = rZ1 * T(1.7320508075688772935);
-  const T rA = T(1) / A;
+  const T rA = rcp(A);
   const T dpdd = T(0.5) * (L.P[sDD] - R.P[sDD]);
   const T dpda = T(0.5) * (L.P[sDA] - R.P[sDA]);
   const T dpdb = T(0.5) * (L.P[sDB] - R.P[sDB]);
@@ -113,18 +113,13 @@ __device__ __forceinline__ void axis_terms(const Fields<T>& in, size_t cm, size_
     }
 }
 
+// One cell of the Eulerian stage; tau_d is the step, (i, j, k) the cell.
 template <typename T>
-__global__ void __launch_bounds__(kTX* kTY) k_eulerian(Fields<T> in, Fields<T> out,
-                                                       const T* __restrict__ phi, Grid g, Phys ph,
-                                                       const DevScalars* __restrict__ sc) {
-  const TileId tl = xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY);
-  const int i = tl.tx * kTX + threadIdx.x;
-  const int j = tl.ty * kTY + threadIdx.y;
-  const int k = tl.tz;
-  if (i >= g.nx || j >= g.ny) return;
+__device__ __forceinline__ void eulerian_cell(const Fields<T>& in, const Fields<T>& out,
+                                              gptr<const T> phi, const Grid& g, const Phys& ph,
+                                              double tau_d, int i, int j, int k) {
   const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
   const size_t c = i + nx * j + nxy * k;
-  const double tau_d = sc->dt;
   const T tau = (T)tau_d, r = (T)(tau_d / g.h);
   const T gamma = (T)ph.gamma, gm1 = gamma - T(1);
 
@@ -137,7 +132,7 @@ __global__ void __launch_bounds__(kTX* kTY) k_eulerian(Fields<T> in, Fields<T> o
   // gravity: central difference of the periodic potential
   T grad[3] = {T(0), T(0), T(0)};
   if (ph.G != 0.0) {
-    const T r2h = T(1) / (T(2) * (T)g.h);
+    const T r2h = (T)(0.5 / g.h);
     const size_t wim = wrap_index(i - 1, g.nx), wip = wrap_index(i + 1, g.nx);
     const size_t wjm = wrap_index(j - 1, g.ny), wjp = wrap_index(j + 1, g.ny);
     const size_t wkm = wrap_index(k - 1, g.nz), wkp = wrap_index(k + 1, g.nz);
@@ -162,7 +157,7 @@ __global__ void __launch_bounds__(kTX* kTY) k_eulerian(Fields<T> in, Fields<T> o
   T m[3];
 #pragma unroll
   for (int d = 0; d < 3; d++) m[d] = in.o[oidx(GP_MX + d)][c];
-  const T irho = T(1) / C.rho, inb = T(1) / C.n;
+  const T irho = rcp(C.rho), inb = rcp(C.n);
 #pragma unroll
   for (int d = 0; d < 3; d++) out.o[oidx(GP_MX + d)][c] = (m[d] - r * dP[d] - tau * C.rho * grad[d]) * irho;
   out.o[oidx(GP_E)][c] =
@@ -187,17 +182,31 @@ __global__ void __launch_bounds__(kTX* kTY) k_eulerian(Fields<T> in, Fields<T> o
     }
 }
 
+// Persistent launch over the (run, tile) work list of a batch.
 template <typename T>
-void launch_eulerian(const Fields<T>& in, const Fields<T>& out, const T* phi, const Grid& g,
-                     const Phys& ph, const DevScalars* sc, hipStream_t st) {
-  dim3 block(kTX, kTY, 1);
-  dim3 grid(cell_blocks(g), 1, 1);
-  k_eulerian<T><<<grid, block, 0, st>>>(in, out, phi, g, ph, sc);
+__global__ void __launch_bounds__(kBlock, 3) k_eulerian(const RunDev<T>* __restrict__ runs,
+                                                     const WorkItem* __restrict__ work, unsigned nwork,
+                                                     int parity) {
+  const WorkRange wr = xcd_range(nwork);
+  for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
+    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const RunDev<T>& R = runs[run];
+    const int ntx = R.ntx, nty = R.nty;
+    const int i = (tile % ntx) * kTX + threadIdx.x;
+    const int j = ((tile / ntx) % nty) * kTY + threadIdx.y;
+    const int k = tile / (ntx * nty);
+    if (i < R.g.nx && j < R.g.ny)
+      eulerian_cell<T>(fields_state(R, parity), fields_eul(R), as_global((const T*)R.phi), R.g, R.ph, R.sc->dt, i, j, k);
+  }
 }
 
-template void launch_eulerian<double>(const Fields<double>&, const Fields<double>&, const double*,
-                                      const Grid&, const Phys&, const DevScalars*, hipStream_t);
-template void launch_eulerian<float>(const Fields<float>&, const Fields<float>&, const float*,
-                                     const Grid&, const Phys&, const DevScalars*, hipStream_t);
+template <typename T>
+void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, unsigned nblocks,
+                     hipStream_t st) {
+  k_eulerian<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+}
+
+template void launch_eulerian<double>(const RunDev<double>*, const WorkItem*, unsigned, int, unsigned, hipStream_t);
+template void launch_eulerian<float>(const RunDev<float>*, const WorkItem*, unsigned, int, unsigned, hipStream_t);
 
 }  // namespace gp

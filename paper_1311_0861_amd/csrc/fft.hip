@@ -4,8 +4,12 @@
 //   minus sign that Laplace(Phi) = 4 pi G s requires).
 //
 // Five passes over a half spectrum C[z][y][kx], kx in [0, nx/2] (row pitch px):
-//   x forward  : real rows of length nx -> complex FFT of length nx/2 on packed
-//                (even, odd) pairs, then the even/odd split to nx/2+1 bins;
+//   x forward  : the source s = rho + n - <rho + n> is formed in FP64 from the
+//                densities (the constant leaves Phi unchanged, as its zero mode
+//                is dropped, and keeping it out of an FP32 transform keeps the
+//                other modes accurate); real rows of length nx -> complex FFT
+//                of length nx/2 on packed (even, odd) pairs, then the even/odd
+//                split to nx/2+1 bins;
 //   y forward  : columns of C along y;
 //   z fused    : forward along z, multiply by the symbol (and the inverse
 //                normalisation), accumulate sum |s^|^2 G for the potential
@@ -155,22 +159,31 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* src, 
 
 // ---- x forward: rows of s (length nx) -> C rows (nx/2 + 1 bins) -------------
 template <typename T>
-__global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const T* __restrict__ s, cplx<T>* __restrict__ spec,
-                                                           FftGeom f, FftTables<T> t) {
+__global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __restrict__ src, int parity,
+                                                           cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int M = f.ax.L;
   const int RB = f.rows_per_block;
   cplx<T>* tw = lds + RB * M;
   cplx<T>* wn = tw + M;
-  const int nrows = f.ny * f.nz;
+  const int rows_run = f.ny * f.nz;
+  const int nrows = rows_run * f.nruns;
   const int row0 = blockIdx.x * RB;
   const int rows = min(RB, nrows - row0);
   load_twiddles(tw, t.tw_x, M);
   load_twiddles(wn, t.wn_x, M + 1);
-  // packed (even, odd) pairs of each row
-  const cplx<T>* src = reinterpret_cast<const cplx<T>*>(s) + (size_t)row0 * M;
-  for (int q = threadIdx.x; q < rows * M; q += kFftThreads) lds[q] = src[q];
+  // packed (even, odd) pairs of each row of s
+  for (int q = threadIdx.x; q < rows * M; q += kFftThreads) {
+    const int row = row0 + q / M, m = q % M;
+    const int slot = row / rows_run;
+    const size_t c = (size_t)(row - slot * rows_run) * f.nx + 2 * m;
+    const SrcSlot& S = src[slot];
+    const double shift = S.sc->shift;
+    const double* rho = S.rho[parity];
+    const double* nb = S.nb[parity];
+    lds[q] = {(T)(rho[c] + nb[c] - shift), (T)(rho[c + 1] + nb[c + 1] - shift)};
+  }
   __syncthreads();
   lds_fft(lds, rows, M, f.ax, tw, false);
   // even/odd split: X[k] = E[k] + W_N^k O[k]
@@ -196,7 +209,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __rest
   cplx<T>* xin = lds + RB * M;          // RB rows of M + 1 bins
   cplx<T>* tw = xin + RB * (M + 1);
   cplx<T>* wn = tw + M;
-  const int nrows = f.ny * f.nz;
+  const int nrows = f.ny * f.nz * f.nruns;
   const int row0 = blockIdx.x * RB;
   const int rows = min(RB, nrows - row0);
   load_twiddles(tw, t.tw_x, M);
@@ -223,12 +236,14 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __rest
 
 // ---- column passes (y, and the fused z pass) -------------------------------
 // A workgroup takes `cb` consecutive kx columns and one index of the other
-// transverse axis; line j of column c lives at base + j * stride + c.
+// transverse axis of one run; line j of column c lives at base + j * stride + c
+// with base = run * run_stride + o * outer_stride + kx0 for outer index
+// run * outer_div + o.
 template <typename T, int MODE>  // MODE 0: forward, 1: inverse, 2: forward * symbol * inverse
 __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t,
                                                          FftAxis ax, const cplx<T>* __restrict__ twg, int cb,
-                                                         size_t stride, size_t outer_stride,
-                                                         double* __restrict__ epot_partials) {
+                                                         size_t stride, size_t outer_stride, int outer_div,
+                                                         size_t run_stride, double* __restrict__ epot_partials) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int L = ax.L;
@@ -236,11 +251,12 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
   cplx<T>* tw = lds + cb * lp;
   const int nchunks = (f.px + cb - 1) / cb;
   const int chunk = blockIdx.x % nchunks;
-  const int outer = blockIdx.x / nchunks;
+  const int oline = blockIdx.x / nchunks;
+  const int outer = oline % outer_div;
   const int kx0 = chunk * cb;
   const int ncols = min(cb, f.px - kx0);
   load_twiddles(tw, twg, L);
-  cplx<T>* base = spec + (size_t)outer * outer_stride + kx0;
+  cplx<T>* base = spec + (size_t)(oline / outer_div) * run_stride + (size_t)outer * outer_stride + kx0;
   for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
     const int c = q % cb, j = q / cb;
     lds[c * lp + j] = (c < ncols) ? base[(size_t)j * stride + c] : cplx<T>{T(0), T(0)};
@@ -287,18 +303,19 @@ static size_t x_lds_bytes(const FftGeom& f, size_t csz, bool inv) {
   return csz * (RB * M + (inv ? RB * (M + 1) : 0) + M + M + 1);
 }
 
-int fft_blocks_z(const FftGeom& f) { return ((f.px + f.cols_z - 1) / f.cols_z) * f.ny; }
+int fft_blocks_z(const FftGeom& f) { return ((f.px + f.cols_z - 1) / f.cols_z) * f.ny * f.nruns; }
 
 template <typename T>
-void launch_fft_x_fwd(const T* s, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, hipStream_t st) {
-  const int nrows = f.ny * f.nz;
+void launch_fft_x_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
+                      hipStream_t st) {
+  const int nrows = f.ny * f.nz * f.nruns;
   const int nblk = (nrows + f.rows_per_block - 1) / f.rows_per_block;
-  k_fft_x_fwd<T><<<nblk, kFftThreads, x_lds_bytes(f, sizeof(cplx<T>), false), st>>>(s, spec, f, t);
+  k_fft_x_fwd<T><<<nblk, kFftThreads, x_lds_bytes(f, sizeof(cplx<T>), false), st>>>(src, parity, spec, f, t);
 }
 
 template <typename T>
 void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st) {
-  const int nrows = f.ny * f.nz;
+  const int nrows = f.ny * f.nz * f.nruns;
   const int nblk = (nrows + f.rows_per_block - 1) / f.rows_per_block;
   k_fft_x_inv<T><<<nblk, kFftThreads, x_lds_bytes(f, sizeof(cplx<T>), true), st>>>(spec, phi, f, t);
 }
@@ -306,13 +323,13 @@ void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTa
 template <typename T>
 void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool inverse, hipStream_t st) {
   const int cb = f.cols_y;
-  const int nblk = ((f.px + cb - 1) / cb) * f.nz;
+  const int nblk = ((f.px + cb - 1) / cb) * f.nz * f.nruns;
   const size_t lds = sizeof(cplx<T>) * ((size_t)cb * (f.ay.L + 1) + f.ay.L);
-  const size_t stride = f.px, outer = (size_t)f.px * f.ny;
+  const size_t stride = f.px, outer = (size_t)f.px * f.ny, run = outer * f.nz;
   if (inverse)
-    k_fft_col<T, 1><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, nullptr);
+    k_fft_col<T, 1><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr);
   else
-    k_fft_col<T, 0><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, nullptr);
+    k_fft_col<T, 0><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr);
 }
 
 template <typename T>
@@ -321,13 +338,14 @@ void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, 
   const int cb = f.cols_z;
   const int nblk = fft_blocks_z(f);
   const size_t lds = sizeof(cplx<T>) * ((size_t)cb * (f.az.L + 1) + f.az.L);
-  const size_t stride = (size_t)f.px * f.ny, outer = f.px;
-  k_fft_col<T, 2><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, cb, stride, outer, epot_partials);
+  const size_t stride = (size_t)f.px * f.ny, outer = f.px, run = stride * f.nz;
+  k_fft_col<T, 2><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, cb, stride, outer, f.ny, run,
+                                                  epot_partials);
 }
 
-template void launch_fft_x_fwd<double>(const double*, cplx<double>*, const FftGeom&, const FftTables<double>&,
-                                       hipStream_t);
-template void launch_fft_x_fwd<float>(const float*, cplx<float>*, const FftGeom&, const FftTables<float>&,
+template void launch_fft_x_fwd<double>(const SrcSlot*, int, cplx<double>*, const FftGeom&,
+                                       const FftTables<double>&, hipStream_t);
+template void launch_fft_x_fwd<float>(const SrcSlot*, int, cplx<float>*, const FftGeom&, const FftTables<float>&,
                                       hipStream_t);
 template void launch_fft_x_inv<double>(const cplx<double>*, double*, const FftGeom&, const FftTables<double>&,
                                        hipStream_t);

@@ -5,28 +5,27 @@
 
 namespace gp {
 
+// All per-cell stages are persistent launches of `nblocks` workgroups over a
+// (run, tile) work list; runs[] are the device descriptors of the batch.
+
 // ---- Eulerian stage --------------------------------------------------------
 template <typename T>
-void launch_eulerian(const Fields<T>& in, const Fields<T>& out, const T* phi, const Grid& g,
-                     const Phys& ph, const DevScalars* sc, hipStream_t st);
+void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, unsigned nblocks,
+                     hipStream_t st);
 
 // ---- Lagrangian stage + energy balance + diagnostics partials -------------
-// Corner velocities (6 components, (nx+1)(ny+1)(nz+1) vertices each, component
-// stride vstride) from the post-Eulerian velocities.
+// Corner velocities from the post-Eulerian velocities (vertex work list).
 template <typename T>
-void launch_vertex(const Fields<T>& eul, T* vtx, size_t vstride, const Grid& g, hipStream_t st);
-// cur: rho, n at t^n; eul: post-Eulerian fields (velocities in the momentum
-// slots); out: new state (its rho/n pointers must differ from cur's).  Writes
-// s = rho + n and one kNP-slot partial row per block.
+void launch_vertex(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, unsigned nblocks, hipStream_t st);
+// New state into cur / dens[parity ^ 1] and one kNP-slot partial row per tile
+// (row R.row0 + tile).
 template <typename T>
-void launch_lagrangian(const Fields<T>& cur, const Fields<T>& eul, const Fields<T>& out, const T* vtx,
-                       size_t vstride, T* s, const Grid& g, const Phys& ph, const DevScalars* sc,
-                       double* partials, hipStream_t st);
-
-// Partials and s = rho + n of a state that has not been advanced (prologue).
+void launch_lagrangian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, double* partials,
+                       unsigned nblocks, hipStream_t st);
+// Partial rows of a state that has not been advanced (prologue).
 template <typename T>
-void launch_init_partials(const Fields<T>& cur, T* s, const Grid& g, const Phys& ph,
-                          double* partials, hipStream_t st);
+void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity,
+                          double* partials, unsigned nblocks, hipStream_t st);
 
 // ---- FFT Poisson ---------------------------------------------------------
 template <typename T>
@@ -53,6 +52,7 @@ struct FftTables {
 
 struct FftGeom {
   int nx, ny, nz, px;     // px = nx / 2 + 1 (half-spectrum row length)
+  int nruns;              // runs of this size stored back to back
   FftAxis ax, ay, az;     // ax.L = nx / 2
   int rows_per_block;     // x passes
   int cols_y, cols_z;     // columns per block in the y / z passes
@@ -62,8 +62,16 @@ struct FftGeom {
 
 int fft_blocks_z(const FftGeom& f);
 
+// Poisson source of each run of a size class: s = rho + n - <rho + n>, formed
+// in FP64 from the current densities (slot = run position in the class).
+struct SrcSlot {
+  const double* rho[2];  // by buffer parity
+  const double* nb[2];
+  const DevScalars* sc;  // holds the mean <rho + n>
+};
 template <typename T>
-void launch_fft_x_fwd(const T* s, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, hipStream_t st);
+void launch_fft_x_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
+                      hipStream_t st);
 template <typename T>
 void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool inverse, hipStream_t st);
 template <typename T>
@@ -73,11 +81,27 @@ template <typename T>
 void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st);
 
 // ---- reductions / finalize ---------------------------------------------
-// Two-level fixed-order reduction of the per-block partials, then the CFL
-// step, time advance and diagnostics record.  advanced = 0 for the prologue.
-void launch_finalize(const double* partials, int nrows, double* scratch, int nscratch,
-                     const double* epot_partials, int nepot, const Grid& g, const Phys& ph,
-                     double epot_scale, int advanced, DevScalars* sc, gp_diag* ring, hipStream_t st);
+// Two-level fixed-order reduction of the per-tile partial rows, then per run
+// the CFL step, time advance and diagnostics record.  advanced = 1 after a
+// step, 0 for the initial state.
+struct RedItem {
+  unsigned src_begin, src_end;  // partial rows reduced into one scratch row
+};
+struct FinDesc {
+  Grid g;
+  Phys ph;
+  unsigned soff, nscr;  // scratch rows of the run
+  unsigned eoff, nep;   // potential-energy partials of the run
+  double epot_scale;    // 1 / (nx ny nz)
+  DevScalars* sc;
+  gp_diag* ring;
+};
+// First level (partial rows -> per-run scratch rows) and the per-run mean
+// density for the Poisson source; then the finalize proper.
+void launch_reduce(const double* partials, const RedItem* items, int nitems, double* scratch, const FinDesc* fin,
+                   int nruns, hipStream_t st);
+void launch_finalize(const double* scratch, const double* epot_partials, const FinDesc* fin, int nruns,
+                     int advanced, hipStream_t st);
 
 // ---- conversions ---------------------------------------------------------
 template <typename D, typename S>

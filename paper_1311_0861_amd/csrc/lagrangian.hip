@@ -9,8 +9,8 @@
 //   - correctness integrals kappa (Sec. 2.4) measured on the advected state;
 //   - energy balance: e := E - |m|^2/(2 rho) where that exceeds eta E, and
 //     each diagonal stress Pi_dd := W_dd - q_d^2/n where that exceeds eta W_dd;
-//   - s = rho + n for the Poisson solve, and per-block FP64 partial sums for
-//     the CFL step and the diagnostics.
+//   - per-tile FP64 partial sums for the CFL step and the diagnostics (the
+//     Poisson source is formed from rho and n by the first FFT pass).
 // rho and n are advected in FP64 with each face flux formed by the same
 // operations from both sides, so mass telescopes to rounding in both
 // precisions.
@@ -85,7 +85,7 @@ __device__ __forceinline__ void kappa_terms(double rho, double n, const T m[3], 
 }
 
 // Fixed-order block reduction of the cell accumulators into one partial row.
-__device__ __forceinline__ void block_reduce_store(CellAcc& a, double* row) {
+__device__ __forceinline__ void block_reduce_store(CellAcc& a, gptr<double> row) {
   __shared__ double red[(kTX * kTY) / 64][kNP];
   const int tid = threadIdx.x + kTX * threadIdx.y;
   const int lane = tid & 63, wave = tid >> 6;
@@ -117,6 +117,7 @@ __device__ __forceinline__ void block_reduce_store(CellAcc& a, double* row) {
     }
     row[tid] = v;
   }
+  __syncthreads();  // the next tile of a persistent workgroup reuses red[]
 }
 
 // Face flux of an FP64 density; both cells sharing the face evaluate exactly
@@ -130,13 +131,8 @@ __device__ __forceinline__ double face_flux(double ap, double am, double fl, dou
 // it, cells outside the grid taken by the hydrodynamic boundary rule.  The
 // post-Eulerian momentum slots hold velocities already.
 template <typename T>
-__global__ void __launch_bounds__(kTX* kTY) k_vertex(Fields<T> eul, T* __restrict__ vtx, Grid g,
-                                                     size_t vstride) {
-  const TileId tl = xcd_tile((g.nx + 1 + kTX - 1) / kTX, (g.ny + 1 + kTY - 1) / kTY);
-  const int I = tl.tx * kTX + threadIdx.x;
-  const int J = tl.ty * kTY + threadIdx.y;
-  const int K = tl.tz;
-  if (I > g.nx || J > g.ny) return;
+__device__ __forceinline__ void vertex_point(const Fields<T>& eul, gptr<T> vtx, const Grid& g,
+                                             size_t vstride, int I, int J, int K) {
   const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
   const size_t xi[2] = {(size_t)bc_index(I - 1, g.nx, g.bc[0]), (size_t)bc_index(I, g.nx, g.bc[0])};
   const size_t yj[2] = {nx * bc_index(J - 1, g.ny, g.bc[1]), nx * bc_index(J, g.ny, g.bc[1])};
@@ -160,251 +156,279 @@ __global__ void __launch_bounds__(kTX* kTY) k_vertex(Fields<T> eul, T* __restric
   for (int v = 0; v < 6; v++) vtx[v * vstride + w] = acc[v] * T(0.125);
 }
 
+// Vertices are processed in flat index order, kBlock per work item, so every
+// wave writes 64 consecutive vertices whatever the (nx+1) row length.
 template <typename T>
-__global__ void __launch_bounds__(kTX* kTY) k_lagrangian(Fields<T> cur, Fields<T> eul, Fields<T> out,
-                                                         const T* __restrict__ vtx, size_t vstride,
-                                                         T* __restrict__ s_out, Grid g, Phys ph,
-                                                         const DevScalars* __restrict__ sc,
-                                                         double* __restrict__ partials) {
-  const TileId tl = xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY);
-  const int i = tl.tx * kTX + threadIdx.x;
-  const int j = tl.ty * kTY + threadIdx.y;
-  const int k = tl.tz;
-  const bool active = (i < g.nx) && (j < g.ny);
-  CellAcc acc;
-  acc_init(acc);
-  if (active) {
-    const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
-    const double rd = sc->dt / g.h;
-    const T r = (T)rd;
-    const T gamma = (T)ph.gamma;
-    const size_t xi[3] = {(size_t)bc_index(i - 1, g.nx, g.bc[0]), (size_t)i,
-                          (size_t)bc_index(i + 1, g.nx, g.bc[0])};
-    const size_t yj[3] = {nx * bc_index(j - 1, g.ny, g.bc[1]), nx * j,
-                          nx * bc_index(j + 1, g.ny, g.bc[1])};
-    const size_t zk[3] = {nxy * bc_index(k - 1, g.nz, g.bc[2]), nxy * k,
-                          nxy * bc_index(k + 1, g.nz, g.bc[2])};
-    const size_t c = xi[1] + yj[1] + zk[1];
-
-    // A+ / A- on the six faces: [axis][side], side 0 = minus face, 1 = plus face.
-    // Corner s = sx + 2 sy + 4 sz is vertex (i + sx, j + sy, k + sz); a face
-    // normal to d on side `side` has the 4 corners with s_d = side.
-    const size_t vx = g.nx + 1, vxy = (size_t)(g.nx + 1) * (g.ny + 1);
-    const size_t w0 = i + vx * j + vxy * k;
-    T apg[3][2], amg[3][2], apb[3][2], amb[3][2];
-#pragma unroll
-    for (int d = 0; d < 3; d++)
-#pragma unroll
-      for (int side = 0; side < 2; side++) {
-        T pg = T(0), ng = T(0), pb = T(0), nb = T(0);
-#pragma unroll
-        for (int s = 0; s < 8; s++) {
-          if (((s >> d) & 1) != side) continue;
-          const size_t w = w0 + (s & 1) + vx * ((s >> 1) & 1) + vxy * ((s >> 2) & 1);
-          const T vgd = vtx[d * vstride + w], vbd = vtx[(3 + d) * vstride + w];
-          pg += fmax(vgd, T(0));
-          ng += fmin(vgd, T(0));
-          pb += fmax(vbd, T(0));
-          nb += fmin(vbd, T(0));
-        }
-        apg[d][side] = pg * T(0.25);
-        amg[d][side] = ng * T(0.25);
-        apb[d][side] = pb * T(0.25);
-        amb[d][side] = nb * T(0.25);
-      }
-
-    // neighbour indices along each axis
-    const size_t cmn[3] = {xi[0] + yj[1] + zk[1], xi[1] + yj[0] + zk[1], xi[1] + yj[1] + zk[0]};
-    const size_t cpl[3] = {xi[2] + yj[1] + zk[1], xi[1] + yj[2] + zk[1], xi[1] + yj[1] + zk[2]};
-    const int ci[3] = {i, j, k};
-    const int nn[3] = {g.nx, g.ny, g.nz};
-
-    // densities at the 7 points: centre, then minus / plus neighbour per axis
-    double rh[7], nd[7];
-    rh[0] = cur.rho[c];
-    nd[0] = cur.nb[c];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-      rh[1 + 2 * d] = cur.rho[cmn[d]];
-      rh[2 + 2 * d] = cur.rho[cpl[d]];
-      nd[1 + 2 * d] = cur.nb[cmn[d]];
-      nd[2 + 2 * d] = cur.nb[cpl[d]];
+__global__ void __launch_bounds__(kBlock) k_vertex(const RunDev<T>* __restrict__ runs,
+                                                   const WorkItem* __restrict__ work, unsigned nwork) {
+  const WorkRange wr = xcd_range(nwork);
+  const unsigned tid = threadIdx.x + kTX * threadIdx.y;
+  for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
+    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const RunDev<T>& R = runs[run];
+    const unsigned vx = R.g.nx + 1, vy = R.g.ny + 1;
+    const size_t v = (size_t)tile * kBlock + tid;
+    if (v < (size_t)vx * vy * (R.g.nz + 1)) {
+      const unsigned I = (unsigned)(v % vx);
+      const size_t JK = v / vx;
+      const unsigned J = (unsigned)(JK % vy), K = (unsigned)(JK / vy);
+      vertex_point<T>(fields_eul(R), as_global(R.vtx), R.g, R.vstride, (int)I, (int)J, (int)K);
     }
-    // explicit FP64 face fluxes of rho and n, and the boundary outflow
-    double divr = 0.0, divn = 0.0, outg = 0.0, outb = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-      const double Fp = face_flux(apg[d][1], amg[d][1], rh[0], rh[2 + 2 * d]);
-      const double Fm = face_flux(apg[d][0], amg[d][0], rh[1 + 2 * d], rh[0]);
-      const double Gp = face_flux(apb[d][1], amb[d][1], nd[0], nd[2 + 2 * d]);
-      const double Gm = face_flux(apb[d][0], amb[d][0], nd[1 + 2 * d], nd[0]);
-      divr += Fp - Fm;
-      divn += Gp - Gm;
-      if (g.bc[d] == GP_BC_OUTFLOW) {
-        if (ci[d] == nn[d] - 1) { outg += Fp; outb += Gp; }
-        if (ci[d] == 0) { outg -= Fm; outb -= Gm; }
-      }
-    }
-    const double rho = rh[0] - rd * divr;
-    const double n = nd[0] - rd * divn;
-
-    // other fields: 7-point stencil with the same face coefficients; the
-    // momenta are rebuilt as density times post-Eulerian velocity
-    T wcg = T(1), wcb = T(1), wpg[3], wmg[3], wpb[3], wmb[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-      wcg -= r * (apg[d][1] - amg[d][0]);
-      wcb -= r * (apb[d][1] - amb[d][0]);
-      wpg[d] = -r * amg[d][1];
-      wmg[d] = r * apg[d][0];
-      wpb[d] = -r * amb[d][1];
-      wmb[d] = r * apb[d][0];
-    }
-    T nv[kNO];
-#pragma unroll
-    for (int f = 0; f < kNO; f++) {
-      const T* src = eul.o[f];
-      const bool gas = f < oidx(GP_N + 1);  // mx my mz E e
-      const bool gmom = f <= oidx(GP_MZ);
-      const bool bmom = f >= oidx(GP_QX) && f <= oidx(GP_QZ);
-      auto val = [&](int p, size_t idx) -> T {
-        const T x = src[idx];
-        return gmom ? (T)rh[p] * x : (bmom ? (T)nd[p] * x : x);
-      };
-      const T wc = gas ? wcg : wcb;
-      T v = wc * val(0, c);
-#pragma unroll
-      for (int d = 0; d < 3; d++) {
-        v += (gas ? wpg[d] : wpb[d]) * val(2 + 2 * d, cpl[d]);
-        v += (gas ? wmg[d] : wmb[d]) * val(1 + 2 * d, cmn[d]);
-      }
-      nv[f] = v;
-    }
-
-    // energy balance and correctness integrals
-    T m[3] = {nv[oidx(GP_MX)], nv[oidx(GP_MY)], nv[oidx(GP_MZ)]};
-    T q[3] = {nv[oidx(GP_QX)], nv[oidx(GP_QY)], nv[oidx(GP_QZ)]};
-    T E = nv[oidx(GP_E)], e = nv[oidx(GP_EINT)];
-    T P[6], W[6];
-#pragma unroll
-    for (int s = 0; s < 6; s++) {
-      P[s] = nv[oidx(GP_PXX + s)];
-      W[s] = nv[oidx(GP_WXX + s)];
-    }
-    T ekin, Tt[6], kg, kb;
-    kappa_terms(rho, n, m, E, e, q, P, W, ekin, Tt, kg, kb);
-    acc.v[P_KGAS] += (double)kg;
-    acc.v[P_KBME] += (double)kb;
-    if (ph.eta >= 0.0) {
-      const T eta = (T)ph.eta;
-      const T et = E - ekin;
-      if (et > eta * E) {
-        e = et;
-        acc.v[P_SYNCG] += 1.0;
-      }
-      bool any = false;
-#pragma unroll
-      for (int d = 0; d < 3; d++) {
-        const int s = sym(d, d);
-        if (Tt[s] > eta * W[s]) {
-          P[s] = Tt[s];
-          any = true;
-        }
-      }
-      if (any) acc.v[P_SYNCB] += 1.0;
-    }
-    acc.v[P_OUTG] += outg;
-    acc.v[P_OUTB] += outb;
-
-    out.rho[c] = rho;
-    out.nb[c] = n;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-      out.o[oidx(GP_MX + d)][c] = m[d];
-      out.o[oidx(GP_QX + d)][c] = q[d];
-    }
-    out.o[oidx(GP_E)][c] = E;
-    out.o[oidx(GP_EINT)][c] = e;
-#pragma unroll
-    for (int s = 0; s < 6; s++) {
-      out.o[oidx(GP_PXX + s)][c] = P[s];
-      out.o[oidx(GP_WXX + s)][c] = W[s];
-    }
-    s_out[c] = (T)(rho + n);
-    cell_terms(acc, rho, n, m, E, e, q, P, W, gamma);
   }
-  block_reduce_store(acc, partials + (size_t)tl.lin * kNP);
 }
 
+// One cell of the Lagrangian stage and its end-of-step work.
 template <typename T>
-__global__ void __launch_bounds__(kTX* kTY) k_init_partials(Fields<T> cur, T* __restrict__ s_out, Grid g,
-                                                            Phys ph, double* __restrict__ partials) {
-  const TileId tl = xcd_tile((g.nx + kTX - 1) / kTX, (g.ny + kTY - 1) / kTY);
-  const int i = tl.tx * kTX + threadIdx.x;
-  const int j = tl.ty * kTY + threadIdx.y;
-  const int k = tl.tz;
-  CellAcc acc;
-  acc_init(acc);
-  if (i < g.nx && j < g.ny) {
-    const size_t c = i + (size_t)g.nx * (j + (size_t)g.ny * k);
-    const double rho = cur.rho[c], n = cur.nb[c];
-    T m[3], q[3], P[6], W[6];
+__device__ __forceinline__ void lagrangian_cell(CellAcc& acc, const Fields<T>& cur, const Fields<T>& eul,
+                                                const Fields<T>& out, gptr<const T> vtx, size_t vstride,
+                                                const Grid& g, const Phys& ph, double tau_d, int i, int j,
+                                                int k) {
+  const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
+  const double rd = tau_d / g.h;
+  const T r = (T)rd;
+  const T gamma = (T)ph.gamma;
+  const size_t xi[3] = {(size_t)bc_index(i - 1, g.nx, g.bc[0]), (size_t)i,
+                        (size_t)bc_index(i + 1, g.nx, g.bc[0])};
+  const size_t yj[3] = {nx * bc_index(j - 1, g.ny, g.bc[1]), nx * j,
+                        nx * bc_index(j + 1, g.ny, g.bc[1])};
+  const size_t zk[3] = {nxy * bc_index(k - 1, g.nz, g.bc[2]), nxy * k,
+                        nxy * bc_index(k + 1, g.nz, g.bc[2])};
+  const size_t c = xi[1] + yj[1] + zk[1];
+
+  // A+ / A- on the six faces: [axis][side], side 0 = minus face, 1 = plus face.
+  // Corner s = sx + 2 sy + 4 sz is vertex (i + sx, j + sy, k + sz); a face
+  // normal to d on side `side` has the 4 corners with s_d = side.
+  const size_t vx = g.nx + 1, vxy = (size_t)(g.nx + 1) * (g.ny + 1);
+  const size_t w0 = i + vx * j + vxy * k;
+  T apg[3][2], amg[3][2], apb[3][2], amb[3][2];
+#pragma unroll
+  for (int d = 0; d < 3; d++)
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      T pg = T(0), ng = T(0), pb = T(0), nb = T(0);
+#pragma unroll
+      for (int s = 0; s < 8; s++) {
+        if (((s >> d) & 1) != side) continue;
+        const size_t w = w0 + (s & 1) + vx * ((s >> 1) & 1) + vxy * ((s >> 2) & 1);
+        const T vgd = vtx[d * vstride + w], vbd = vtx[(3 + d) * vstride + w];
+        pg += fmax(vgd, T(0));
+        ng += fmin(vgd, T(0));
+        pb += fmax(vbd, T(0));
+        nb += fmin(vbd, T(0));
+      }
+      apg[d][side] = pg * T(0.25);
+      amg[d][side] = ng * T(0.25);
+      apb[d][side] = pb * T(0.25);
+      amb[d][side] = nb * T(0.25);
+    }
+
+  // neighbour indices along each axis
+  const size_t cmn[3] = {xi[0] + yj[1] + zk[1], xi[1] + yj[0] + zk[1], xi[1] + yj[1] + zk[0]};
+  const size_t cpl[3] = {xi[2] + yj[1] + zk[1], xi[1] + yj[2] + zk[1], xi[1] + yj[1] + zk[2]};
+  const int ci[3] = {i, j, k};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+
+  // densities at the 7 points: centre, then minus / plus neighbour per axis
+  double rh[7], nd[7];
+  rh[0] = cur.rho[c];
+  nd[0] = cur.nb[c];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    rh[1 + 2 * d] = cur.rho[cmn[d]];
+    rh[2 + 2 * d] = cur.rho[cpl[d]];
+    nd[1 + 2 * d] = cur.nb[cmn[d]];
+    nd[2 + 2 * d] = cur.nb[cpl[d]];
+  }
+  // explicit FP64 face fluxes of rho and n, and the boundary outflow
+  double divr = 0.0, divn = 0.0, outg = 0.0, outb = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const double Fp = face_flux(apg[d][1], amg[d][1], rh[0], rh[2 + 2 * d]);
+    const double Fm = face_flux(apg[d][0], amg[d][0], rh[1 + 2 * d], rh[0]);
+    const double Gp = face_flux(apb[d][1], amb[d][1], nd[0], nd[2 + 2 * d]);
+    const double Gm = face_flux(apb[d][0], amb[d][0], nd[1 + 2 * d], nd[0]);
+    divr += Fp - Fm;
+    divn += Gp - Gm;
+    if (g.bc[d] == GP_BC_OUTFLOW) {
+      if (ci[d] == nn[d] - 1) { outg += Fp; outb += Gp; }
+      if (ci[d] == 0) { outg -= Fm; outb -= Gm; }
+    }
+  }
+  const double rho = rh[0] - rd * divr;
+  const double n = nd[0] - rd * divn;
+
+  // other fields: 7-point stencil with the same face coefficients; the
+  // momenta are rebuilt as density times post-Eulerian velocity
+  T wcg = T(1), wcb = T(1), wpg[3], wmg[3], wpb[3], wmb[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    wcg -= r * (apg[d][1] - amg[d][0]);
+    wcb -= r * (apb[d][1] - amb[d][0]);
+    wpg[d] = -r * amg[d][1];
+    wmg[d] = r * apg[d][0];
+    wpb[d] = -r * amb[d][1];
+    wmb[d] = r * apb[d][0];
+  }
+  T nv[kNO];
+#pragma unroll
+  for (int f = 0; f < kNO; f++) {
+    const auto src = eul.o[f];
+    const bool gas = f < oidx(GP_N + 1);  // mx my mz E e
+    const bool gmom = f <= oidx(GP_MZ);
+    const bool bmom = f >= oidx(GP_QX) && f <= oidx(GP_QZ);
+    auto val = [&](int p, size_t idx) -> T {
+      const T x = src[idx];
+      return gmom ? (T)rh[p] * x : (bmom ? (T)nd[p] * x : x);
+    };
+    const T wc = gas ? wcg : wcb;
+    T v = wc * val(0, c);
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-      m[d] = cur.o[oidx(GP_MX + d)][c];
-      q[d] = cur.o[oidx(GP_QX + d)][c];
+      v += (gas ? wpg[d] : wpb[d]) * val(2 + 2 * d, cpl[d]);
+      v += (gas ? wmg[d] : wmb[d]) * val(1 + 2 * d, cmn[d]);
     }
-#pragma unroll
-    for (int s = 0; s < 6; s++) {
-      P[s] = cur.o[oidx(GP_PXX + s)][c];
-      W[s] = cur.o[oidx(GP_WXX + s)][c];
-    }
-    const T E = cur.o[oidx(GP_E)][c], e = cur.o[oidx(GP_EINT)][c];
-    T ekin, Tt[6], kg, kb;
-    kappa_terms(rho, n, m, E, e, q, P, W, ekin, Tt, kg, kb);
-    acc.v[P_KGAS] += (double)kg;
-    acc.v[P_KBME] += (double)kb;
-    s_out[c] = (T)(rho + n);
-    cell_terms(acc, rho, n, m, E, e, q, P, W, (T)ph.gamma);
+    nv[f] = v;
   }
-  block_reduce_store(acc, partials + (size_t)tl.lin * kNP);
+
+  // energy balance and correctness integrals
+  T m[3] = {nv[oidx(GP_MX)], nv[oidx(GP_MY)], nv[oidx(GP_MZ)]};
+  T q[3] = {nv[oidx(GP_QX)], nv[oidx(GP_QY)], nv[oidx(GP_QZ)]};
+  T E = nv[oidx(GP_E)], e = nv[oidx(GP_EINT)];
+  T P[6], W[6];
+#pragma unroll
+  for (int s = 0; s < 6; s++) {
+    P[s] = nv[oidx(GP_PXX + s)];
+    W[s] = nv[oidx(GP_WXX + s)];
+  }
+  T ekin, Tt[6], kg, kb;
+  kappa_terms(rho, n, m, E, e, q, P, W, ekin, Tt, kg, kb);
+  acc.v[P_KGAS] += (double)kg;
+  acc.v[P_KBME] += (double)kb;
+  if (ph.eta >= 0.0) {
+    const T eta = (T)ph.eta;
+    const T et = E - ekin;
+    if (et > eta * E) {
+      e = et;
+      acc.v[P_SYNCG] += 1.0;
+    }
+    bool any = false;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const int s = sym(d, d);
+      if (Tt[s] > eta * W[s]) {
+        P[s] = Tt[s];
+        any = true;
+      }
+    }
+    if (any) acc.v[P_SYNCB] += 1.0;
+  }
+  acc.v[P_OUTG] += outg;
+  acc.v[P_OUTB] += outb;
+
+  out.rho[c] = rho;
+  out.nb[c] = n;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    out.o[oidx(GP_MX + d)][c] = m[d];
+    out.o[oidx(GP_QX + d)][c] = q[d];
+  }
+  out.o[oidx(GP_E)][c] = E;
+  out.o[oidx(GP_EINT)][c] = e;
+#pragma unroll
+  for (int s = 0; s < 6; s++) {
+    out.o[oidx(GP_PXX + s)][c] = P[s];
+    out.o[oidx(GP_WXX + s)][c] = W[s];
+  }
+  cell_terms(acc, rho, n, m, E, e, q, P, W, gamma);
 }
 
 template <typename T>
-void launch_vertex(const Fields<T>& eul, T* vtx, size_t vstride, const Grid& g, hipStream_t st) {
-  dim3 block(kTX, kTY, 1);
-  dim3 grid(((g.nx + 1 + kTX - 1) / kTX) * ((g.ny + 1 + kTY - 1) / kTY) * (g.nz + 1), 1, 1);
-  k_vertex<T><<<grid, block, 0, st>>>(eul, vtx, g, vstride);
+__global__ void __launch_bounds__(kBlock, 3) k_lagrangian(const RunDev<T>* __restrict__ runs,
+                                                       const WorkItem* __restrict__ work, unsigned nwork,
+                                                       int parity, double* __restrict__ partials) {
+  const WorkRange wr = xcd_range(nwork);
+  for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
+    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const RunDev<T>& R = runs[run];
+    const int ntx = R.ntx, nty = R.nty;
+    const int i = (tile % ntx) * kTX + threadIdx.x;
+    const int j = ((tile / ntx) % nty) * kTY + threadIdx.y;
+    const int k = tile / (ntx * nty);
+    CellAcc acc;
+    acc_init(acc);
+    if (i < R.g.nx && j < R.g.ny)
+      lagrangian_cell<T>(acc, fields_state(R, parity), fields_eul(R), fields_next(R, parity), as_global((const T*)R.vtx), R.vstride,
+                         R.g, R.ph, R.sc->dt, i, j, k);
+    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + tile) * kNP);
+  }
+}
+
+// Diagnostics terms of one cell of a state that has not been advanced.
+template <typename T>
+__device__ __forceinline__ void init_cell(CellAcc& acc, const Fields<T>& cur, const Grid& g, const Phys& ph,
+                                          int i, int j, int k) {
+  const size_t c = i + (size_t)g.nx * (j + (size_t)g.ny * k);
+  const double rho = cur.rho[c], n = cur.nb[c];
+  T m[3], q[3], P[6], W[6];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    m[d] = cur.o[oidx(GP_MX + d)][c];
+    q[d] = cur.o[oidx(GP_QX + d)][c];
+  }
+#pragma unroll
+  for (int s = 0; s < 6; s++) {
+    P[s] = cur.o[oidx(GP_PXX + s)][c];
+    W[s] = cur.o[oidx(GP_WXX + s)][c];
+  }
+  const T E = cur.o[oidx(GP_E)][c], e = cur.o[oidx(GP_EINT)][c];
+  T ekin, Tt[6], kg, kb;
+  kappa_terms(rho, n, m, E, e, q, P, W, ekin, Tt, kg, kb);
+  acc.v[P_KGAS] += (double)kg;
+  acc.v[P_KBME] += (double)kb;
+  cell_terms(acc, rho, n, m, E, e, q, P, W, (T)ph.gamma);
 }
 
 template <typename T>
-void launch_lagrangian(const Fields<T>& cur, const Fields<T>& eul, const Fields<T>& out, const T* vtx,
-                       size_t vstride, T* s, const Grid& g, const Phys& ph, const DevScalars* sc,
-                       double* partials, hipStream_t st) {
-  dim3 block(kTX, kTY, 1);
-  dim3 grid(cell_blocks(g), 1, 1);
-  k_lagrangian<T><<<grid, block, 0, st>>>(cur, eul, out, vtx, vstride, s, g, ph, sc, partials);
+__global__ void __launch_bounds__(kBlock) k_init_partials(const RunDev<T>* __restrict__ runs,
+                                                          const WorkItem* __restrict__ work, unsigned nwork,
+                                                          int parity, double* __restrict__ partials) {
+  const WorkRange wr = xcd_range(nwork);
+  for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
+    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const RunDev<T>& R = runs[run];
+    const int ntx = R.ntx, nty = R.nty;
+    const int i = (tile % ntx) * kTX + threadIdx.x;
+    const int j = ((tile / ntx) % nty) * kTY + threadIdx.y;
+    const int k = tile / (ntx * nty);
+    CellAcc acc;
+    acc_init(acc);
+    if (i < R.g.nx && j < R.g.ny) init_cell<T>(acc, fields_state(R, parity), R.g, R.ph, i, j, k);
+    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + tile) * kNP);
+  }
 }
 
 template <typename T>
-void launch_init_partials(const Fields<T>& cur, T* s, const Grid& g, const Phys& ph, double* partials,
-                          hipStream_t st) {
-  dim3 block(kTX, kTY, 1);
-  dim3 grid(cell_blocks(g), 1, 1);
-  k_init_partials<T><<<grid, block, 0, st>>>(cur, s, g, ph, partials);
+void launch_vertex(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, unsigned nblocks, hipStream_t st) {
+  k_vertex<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork);
 }
-
-template void launch_vertex<double>(const Fields<double>&, double*, size_t, const Grid&, hipStream_t);
-template void launch_vertex<float>(const Fields<float>&, float*, size_t, const Grid&, hipStream_t);
-template void launch_lagrangian<double>(const Fields<double>&, const Fields<double>&, const Fields<double>&,
-                                        const double*, size_t, double*, const Grid&, const Phys&,
-                                        const DevScalars*, double*, hipStream_t);
-template void launch_lagrangian<float>(const Fields<float>&, const Fields<float>&, const Fields<float>&,
-                                       const float*, size_t, float*, const Grid&, const Phys&,
-                                       const DevScalars*, double*, hipStream_t);
-template void launch_init_partials<double>(const Fields<double>&, double*, const Grid&, const Phys&,
-                                           double*, hipStream_t);
-template void launch_init_partials<float>(const Fields<float>&, float*, const Grid&, const Phys&, double*,
-                                          hipStream_t);
+template <typename T>
+void launch_lagrangian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, double* partials,
+                       unsigned nblocks, hipStream_t st) {
+  k_lagrangian<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
+}
+template <typename T>
+void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity,
+                          double* partials, unsigned nblocks, hipStream_t st) {
+  k_init_partials<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
+}
+#define GP_INSTANTIATE(T)                                                                                  \
+  template void launch_vertex<T>(const RunDev<T>*, const WorkItem*, unsigned, unsigned, hipStream_t);       \
+  template void launch_lagrangian<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, unsigned,   \
+                                     hipStream_t);                                                          \
+  template void launch_init_partials<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, unsigned, \
+                                        hipStream_t);
+GP_INSTANTIATE(double)
+GP_INSTANTIATE(float)
+#undef GP_INSTANTIATE
 
 }  // namespace gp

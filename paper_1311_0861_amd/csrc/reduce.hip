@@ -38,22 +38,34 @@ __device__ void reduce_rows(const double* in, int r0, int r1, double* out) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_reduce_rows(const double* __restrict__ in, int nrows,
+// First level: workgroup b reduces partial rows [src_begin, src_end) into
+// scratch row b.
+__global__ void __launch_bounds__(kRedThreads) k_reduce_rows(const double* __restrict__ in,
+                                                             const RedItem* __restrict__ items,
                                                              double* __restrict__ out) {
-  const int chunk = (nrows + gridDim.x - 1) / gridDim.x;
-  const int r0 = min(nrows, (int)blockIdx.x * chunk), r1 = min(nrows, r0 + chunk);
-  reduce_rows(in, r0, r1, out + (size_t)blockIdx.x * kNP);
+  const RedItem it = items[blockIdx.x];
+  reduce_rows(in, (int)it.src_begin, (int)it.src_end, out + (size_t)blockIdx.x * kNP);
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restrict__ rows, int nrows,
-                                                          const double* __restrict__ epot, int nepot, Grid g,
-                                                          Phys ph, double epot_scale, int advanced,
-                                                          DevScalars* __restrict__ sc, gp_diag* __restrict__ ring) {
+// Mean of rho + n of run r (workgroup r), for the Poisson source.
+__global__ void __launch_bounds__(kRedThreads) k_mean(const double* __restrict__ rows,
+                                                      const FinDesc* __restrict__ fin) {
+  __shared__ double tot[kNP];
+  const FinDesc F = fin[blockIdx.x];
+  reduce_rows(rows, (int)F.soff, (int)(F.soff + F.nscr), tot);
+  if (threadIdx.x == 0) F.sc->shift = (tot[P_MGAS] + tot[P_MBME]) / (double)F.g.ncell;
+}
+
+// Second level: workgroup r finishes run r.
+__global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restrict__ rows,
+                                                          const double* __restrict__ epot,
+                                                          const FinDesc* __restrict__ fin, int advanced) {
   __shared__ double tot[kNP];
   __shared__ double ered[kRedThreads];
-  reduce_rows(rows, 0, nrows, tot);
+  const FinDesc F = fin[blockIdx.x];
+  reduce_rows(rows, (int)F.soff, (int)(F.soff + F.nscr), tot);
   double e = 0.0;
-  for (int b = threadIdx.x; b < nepot; b += kRedThreads) e += epot[b];
+  for (unsigned b = threadIdx.x; b < F.nep; b += kRedThreads) e += epot[F.eoff + b];
   ered[threadIdx.x] = e;
   __syncthreads();
   for (int w = kRedThreads / 2; w > 0; w >>= 1) {
@@ -61,6 +73,9 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
+  DevScalars* sc = F.sc;
+  const Grid& g = F.g;
+  const Phys& ph = F.ph;
 
   const double h = g.h, h3 = h * h * h;
   if (advanced) {
@@ -94,7 +109,7 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
   d.mom[2] = h3 * tot[P_MOMZ];
   d.e_gas = h3 * tot[P_EGAS];
   d.e_bme = h3 * tot[P_EBME];
-  d.e_pot = 0.5 * h3 * epot_scale * ered[0];
+  d.e_pot = 0.5 * h3 * F.epot_scale * ered[0];
   d.kappa_gas = h3 * tot[P_KGAS];
   d.kappa_bme = h3 * tot[P_KBME];
   d.outflow_gas = sc->outflow_gas;
@@ -103,16 +118,19 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
   d.n_sync_bme = advanced ? tot[P_SYNCB] : 0.0;
   d.err = sc->err;
   d.pad = 0u;
-  ring[sc->ndiag % kDiagCap] = d;
+  F.ring[sc->ndiag % kDiagCap] = d;
   sc->ndiag += 1;
 }
 
-void launch_finalize(const double* partials, int nrows, double* scratch, int nscratch,
-                     const double* epot_partials, int nepot, const Grid& g, const Phys& ph,
-                     double epot_scale, int advanced, DevScalars* sc, gp_diag* ring, hipStream_t st) {
-  k_reduce_rows<<<nscratch, kRedThreads, 0, st>>>(partials, nrows, scratch);
-  k_finalize<<<1, kRedThreads, 0, st>>>(scratch, nscratch, epot_partials, nepot, g, ph, epot_scale, advanced,
-                                       sc, ring);
+void launch_reduce(const double* partials, const RedItem* items, int nitems, double* scratch, const FinDesc* fin,
+                   int nruns, hipStream_t st) {
+  k_reduce_rows<<<nitems, kRedThreads, 0, st>>>(partials, items, scratch);
+  k_mean<<<nruns, kRedThreads, 0, st>>>(scratch, fin);
+}
+
+void launch_finalize(const double* scratch, const double* epot_partials, const FinDesc* fin, int nruns,
+                     int advanced, hipStream_t st) {
+  k_finalize<<<nruns, kRedThreads, 0, st>>>(scratch, epot_partials, fin, advanced);
 }
 
 template <typename D, typename S>

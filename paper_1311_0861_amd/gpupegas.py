@@ -25,7 +25,7 @@ FIELD_NAMES = [
     "Wxx", "Wxy", "Wxz", "Wyy", "Wyz", "Wzz",
 ]
 GP_PHI = 22
-KERNEL_NAMES = ["eulerian", "vertex", "lagrangian", "fft_x_fwd", "fft_y_fwd", "fft_z_green", "fft_y_inv",
+KERNEL_NAMES = ["eulerian", "vertex", "lagrangian", "reduce", "fft_x_fwd", "fft_y_fwd", "fft_z_green", "fft_y_inv",
                 "fft_x_inv", "finalize"]
 
 
@@ -95,6 +95,21 @@ def _load():
         "gp_status_str": ([i32], ctypes.c_char_p),
         "gp_last_error": ([vp], ctypes.c_char_p),
         "gp_algorithmic_bytes_per_cell": ([vp, i32], dbl),
+        "gp_set_launch": ([vp, i32, i32], i32),
+        "gp_get_launch": ([vp, i32, ctypes.POINTER(i32)], i32),
+        "gp_batch_create": ([ctypes.POINTER(gp_config), i32, vp, ctypes.POINTER(vp)], i32),
+        "gp_batch_destroy": ([vp], i32),
+        "gp_batch_set_field": ([vp, i32, i32, vp, i32, i32], i32),
+        "gp_batch_get_field": ([vp, i32, i32, vp, i32, i32], i32),
+        "gp_batch_step": ([vp, i32], i32),
+        "gp_batch_sync": ([vp], i32),
+        "gp_batch_get_diag": ([vp, i32, ctypes.POINTER(gp_diag), i32, ctypes.POINTER(i32)], i32),
+        "gp_batch_time_kernels": ([vp, i32, ctypes.POINTER(dbl), i32], i32),
+        "gp_batch_set_launch": ([vp, i32, i32], i32),
+        "gp_batch_get_launch": ([vp, i32, ctypes.POINTER(i32)], i32),
+        "gp_batch_algorithmic_bytes_per_cell": ([vp, i32], dbl),
+        "gp_batch_cells": ([vp], i64),
+        "gp_batch_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -106,9 +121,11 @@ def _load():
 lib = _load()
 
 
-def _check(sim, status):
+def _check(sim, status, batch=False):
     if status != GP_OK:
-        detail = lib.gp_last_error(sim).decode() if sim else ""
+        detail = ""
+        if sim:
+            detail = (lib.gp_batch_last_error(sim) if batch else lib.gp_last_error(sim)).decode()
         raise GpError(status, lib.gp_status_str(status).decode() + (" (" + detail + ")" if detail else ""))
 
 
@@ -184,12 +201,7 @@ def gp_get_diag(sim, max_records=4096):
     buf = (gp_diag * max_records)()
     cnt = ctypes.c_int32()
     _check(sim, lib.gp_get_diag(sim, buf, max_records, ctypes.byref(cnt)))
-    out = []
-    for r in buf[: cnt.value]:
-        d = {k: getattr(r, k) for k, _ in gp_diag._fields_ if k not in ("mom", "pad")}
-        d["mom_x"], d["mom_y"], d["mom_z"] = r.mom[0], r.mom[1], r.mom[2]
-        out.append(d)
-    return out
+    return _diag_dicts(buf, cnt.value)
 
 
 def gp_set_time(sim, t, step=0):
@@ -218,6 +230,86 @@ def gp_use_graph(sim, enable):
 
 def gp_algorithmic_bytes_per_cell(sim, kernel=-1):
     return float(lib.gp_algorithmic_bytes_per_cell(sim, int(kernel)))
+
+
+def gp_set_launch(sim, kernel, blocks):
+    _check(sim, lib.gp_set_launch(sim, int(kernel), int(blocks)))
+
+
+def gp_get_launch(sim, kernel):
+    v = ctypes.c_int32()
+    _check(sim, lib.gp_get_launch(sim, int(kernel), ctypes.byref(v)))
+    return v.value
+
+
+def _diag_dicts(buf, n):
+    out = []
+    for r in buf[:n]:
+        d = {k: getattr(r, k) for k, _ in gp_diag._fields_ if k not in ("mom", "pad")}
+        d["mom_x"], d["mom_y"], d["mom_z"] = r.mom[0], r.mom[1], r.mom[2]
+        out.append(d)
+    return out
+
+
+def gp_batch_create(cfgs, stream=None):
+    arr = (gp_config * len(cfgs))(*[c if isinstance(c, gp_config) else make_config(c) for c in cfgs])
+    h = ctypes.c_void_p()
+    _check(None, lib.gp_batch_create(arr, len(cfgs), stream, ctypes.byref(h)))
+    return h
+
+
+def gp_batch_destroy(b):
+    _check(None, lib.gp_batch_destroy(b))
+
+
+def gp_batch_set_field(b, run, field, src):
+    p, code, dev = _buffer(src)
+    _check(b, lib.gp_batch_set_field(b, int(run), int(field), p, code, dev), True)
+
+
+def gp_batch_get_field(b, run, field, dst):
+    p, code, dev = _buffer(dst)
+    _check(b, lib.gp_batch_get_field(b, int(run), int(field), p, code, dev), True)
+    return dst
+
+
+def gp_batch_step(b, nsteps=1):
+    _check(b, lib.gp_batch_step(b, int(nsteps)), True)
+
+
+def gp_batch_sync(b):
+    _check(b, lib.gp_batch_sync(b), True)
+
+
+def gp_batch_get_diag(b, run, max_records=4096):
+    buf = (gp_diag * max_records)()
+    cnt = ctypes.c_int32()
+    _check(b, lib.gp_batch_get_diag(b, int(run), buf, max_records, ctypes.byref(cnt)), True)
+    return _diag_dicts(buf, cnt.value)
+
+
+def gp_batch_time_kernels(b, nsteps):
+    ms = (ctypes.c_double * len(KERNEL_NAMES))()
+    _check(b, lib.gp_batch_time_kernels(b, int(nsteps), ms, len(KERNEL_NAMES)), True)
+    return dict(zip(KERNEL_NAMES, list(ms)))
+
+
+def gp_batch_set_launch(b, kernel, blocks):
+    _check(b, lib.gp_batch_set_launch(b, int(kernel), int(blocks)), True)
+
+
+def gp_batch_get_launch(b, kernel):
+    v = ctypes.c_int32()
+    _check(b, lib.gp_batch_get_launch(b, int(kernel), ctypes.byref(v)), True)
+    return v.value
+
+
+def gp_batch_algorithmic_bytes_per_cell(b, kernel=-1):
+    return float(lib.gp_batch_algorithmic_bytes_per_cell(b, int(kernel)))
+
+
+def gp_batch_cells(b):
+    return int(lib.gp_batch_cells(b))
 
 
 class Sim:
@@ -288,3 +380,79 @@ class Sim:
 
     def bytes_per_cell(self, kernel=-1):
         return gp_algorithmic_bytes_per_cell(self._h, kernel)
+
+    def set_launch(self, kernel, blocks):
+        gp_set_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel, blocks)
+
+    def get_launch(self, kernel):
+        return gp_get_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel)
+
+
+class Batch:
+    """An ensemble of independent runs advanced together (one precision)."""
+
+    def __init__(self, cfgs, stream=None):
+        import torch
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        self.cfgs = [dict(c) for c in cfgs]
+        self.shapes = [(int(c["n"][2]), int(c["n"][1]), int(c["n"][0])) for c in cfgs]
+        self._h = gp_batch_create(cfgs, ctypes.c_void_p(stream) if stream else None)
+
+    def close(self):
+        if self._h is not None:
+            gp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.cfgs)
+
+    def set_field(self, run, name, src):
+        import torch
+        if isinstance(src, torch.Tensor) and src.is_cuda:
+            torch.cuda.current_stream().synchronize()
+        gp_batch_set_field(self._h, run, FIELD_NAMES.index(name) if isinstance(name, str) else name, src)
+
+    def set_state(self, run, state):
+        for k, v in state.items():
+            self.set_field(run, k, v)
+
+    def get_field(self, run, name, out=None, device="cuda", dtype=None):
+        import torch
+        fid = GP_PHI if name == "phi" else (FIELD_NAMES.index(name) if isinstance(name, str) else name)
+        if out is None:
+            out = torch.empty(self.shapes[run], dtype=dtype or torch.float64, device=device)
+        return gp_batch_get_field(self._h, run, fid, out)
+
+    def get_state(self, run, device="cuda", dtype=None):
+        return {k: self.get_field(run, k, device=device, dtype=dtype) for k in FIELD_NAMES}
+
+    def step(self, n=1):
+        gp_batch_step(self._h, n)
+
+    def sync(self):
+        gp_batch_sync(self._h)
+
+    def diag(self, run):
+        return gp_batch_get_diag(self._h, run)
+
+    def time_kernels(self, nsteps):
+        return gp_batch_time_kernels(self._h, nsteps)
+
+    def set_launch(self, kernel, blocks):
+        gp_batch_set_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel, blocks)
+
+    def get_launch(self, kernel):
+        return gp_batch_get_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel)
+
+    def bytes_per_cell(self, kernel=-1):
+        return gp_batch_algorithmic_bytes_per_cell(self._h, kernel)
+
+    def cells(self):
+        return gp_batch_cells(self._h)

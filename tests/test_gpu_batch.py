@@ -1,0 +1,105 @@
+"""Ensemble (batching) form against standalone runs (GPU only).
+
+A batch advances independent runs of uneven grid sizes together (persistent
+per-stage launches over a (run, tile) work list, one FFT launch per grid size,
+graph-replayed steps).  Each member must equal the same run in its own sim
+bitwise, whatever persistent grid sizes are used."""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_state, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1311_0861_amd import gpupegas
+    return gpupegas
+
+
+@pytest.fixture(scope="module")
+def W():
+    from paper_1311_0861_amd import workloads
+    return workloads
+
+
+def _members(W, prec="fp64"):
+    out = [W.gaussian_blob(16), W.random_periodic(n=(16, 12, 8), seed=7),
+           W.gaussian_blob(16, seeds=(11, 12)), W.gaussian_blob(32),
+           W.gas_shock_tube(2, n=64, axis=1)]
+    for cfg, _ in out:
+        cfg["precision"] = prec
+    return out
+
+
+def _batch_state(b, r):
+    return {k: v.cpu().numpy() for k, v in b.get_state(r).items()}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_members_equal_standalone_runs(gp, W, prec):
+    say("batch vs standalone", prec)
+    members = _members(W, prec)
+    b = gp.Batch([c for c, _ in members])
+    for r, (_, st) in enumerate(members):
+        b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
+    b.step(12)
+    b.sync()
+    for r, (cfg, st) in enumerate(members):
+        s = gp.Sim(cfg)
+        s.set_state({k: v.to("cuda") for k, v in st.items()})
+        s.step(12)
+        ref = gpu_state(s)
+        got = _batch_state(b, r)
+        for f in ref:
+            np.testing.assert_array_equal(got[f], ref[f], err_msg="run %d field %s" % (r, f))
+        dg, ds = b.diag(r)[-1], s.diag()[-1]
+        assert dg["t"] == ds["t"] and dg["e_pot"] == ds["e_pot"] and dg["step"] == 12
+        s.close()
+
+
+def test_batch_result_independent_of_launch_size(gp, W):
+    say("launch size independence")
+    members = _members(W)
+    runs = []
+    for blocks in (0, 8, 24):
+        b = gp.Batch([c for c, _ in members])
+        for r, (_, st) in enumerate(members):
+            b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
+        for k in ("eulerian", "vertex", "lagrangian"):
+            b.set_launch(k, blocks)
+        b.step(5)
+        runs.append([_batch_state(b, r) for r in range(len(members))])
+        b.close()
+    for r in range(len(members)):
+        for f in runs[0][r]:
+            np.testing.assert_array_equal(runs[1][r][f], runs[0][r][f])
+            np.testing.assert_array_equal(runs[2][r][f], runs[0][r][f])
+
+
+def test_ensemble_members_radix3(gp, W):
+    """Members of the 48-run ensemble drawn so that all three grid sizes
+    (64, 96 with its radix-3 FFT, 128) appear, FP32, 4 steps."""
+    say("ensemble members with 64/96/128")
+    sizes = W.ensemble_sizes(48)
+    pick = []
+    for n in (64, 96, 128):
+        pick.append(sizes.index(n))
+    members = [W.ensemble_member(r) for r in pick]
+    b = gp.Batch([c for c, _ in members])
+    for r, (_, st) in enumerate(members):
+        b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
+    b.step(4)
+    b.sync()
+    for r, (cfg, st) in enumerate(members):
+        s = gp.Sim(cfg)
+        s.set_state({k: v.to("cuda") for k, v in st.items()})
+        s.step(4)
+        ref = gpu_state(s)
+        got = _batch_state(b, r)
+        for f in ref:
+            np.testing.assert_array_equal(got[f], ref[f], err_msg="member %d field %s" % (pick[r], f))
+        s.close()

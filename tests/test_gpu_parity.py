@@ -33,18 +33,20 @@ def _phi_rel(sim, orc):
     return float(np.abs(a - b).sum() / np.abs(b).sum())
 
 
-@pytest.mark.parametrize("case", ["blob16", "periodic_16x12x8", "blob32"])
+@pytest.mark.parametrize("case", ["blob16", "periodic_16x12x8", "blob32", "periodic_96x24x12"])
 def test_stage_by_stage_parity(gp, W, case):
     say("stage parity", case)
     if case == "blob16":
         cfg, st = W.gaussian_blob(16)
     elif case == "blob32":
         cfg, st = W.gaussian_blob(32)
+    elif case == "periodic_96x24x12":  # radix-3 FFT lengths on every axis
+        cfg, st = W.random_periodic(n=(96, 24, 12), seed=8)
     else:
         cfg, st = W.random_periodic(n=(16, 12, 8), seed=3)
     sim, orc = make_pair(cfg, st)
     # prologue: Phi^0 and tau^0
-    assert _phi_rel(sim, orc) < 1e-13
+    assert _phi_rel(sim, orc) < 1e-12  # FFT rounding grows with log N
     assert sim.time()[1] == pytest.approx(orc.dt(), rel=1e-13)
     for step in range(2):
         sim.stage(gp.GP_STAGE_EUL)
@@ -55,7 +57,7 @@ def test_stage_by_stage_parity(gp, W, case):
         assert_close_fields(gpu_state(sim), orc.get_state(), 1e-13, "lagrangian step %d" % step)
         sim.stage(gp.GP_STAGE_POISSON)
         orc.stage(2)
-        assert _phi_rel(sim, orc) < 1e-13
+        assert _phi_rel(sim, orc) < 1e-12  # FFT rounding grows with log N
         sim.stage(gp.GP_STAGE_FINALIZE)
         orc.stage(3)
         dg, do = sim.diag()[-1], orc.diag()[-1]
