@@ -36,7 +36,10 @@ def parse():
                     help="only run the library's plain copy kernel over MIB MiB of FP64 data "
                          "(calibrates HBM counters) and exit")
     ap.add_argument("--traffic", default=None,
-                    help="JSON with measured HBM bytes per launch of the dominant kernel")
+                    help="counter summary with the measured HBM bytes per launch of the dominant kernel "
+                         "(default: the one under profiles/ for this size and precision)")
+    ap.add_argument("--print-source-hash", action="store_true",
+                    help="print the hash of the library sources that traffic figures are tied to and exit")
     return ap.parse_args()
 
 
@@ -61,15 +64,46 @@ def copy_probe(mib):
     from paper_1311_0861_amd import gpupegas as gp
     from paper_1311_0861_amd import workloads as W
     ncell = mib * 1024 * 1024 // 8
-    nz = max(4, min(1024, ncell // (256 * 256)))
-    cfg = W.base_config((256, 256, nz), lo=(0.0, 0.0, 0.0), hi=(256.0, 256.0, float(nz)), G=0.0)
+    nz = max(1, min(1024, ncell // (1024 * 1024)))
+    cfg = W.base_config((1024, 1024, nz), lo=(0.0, 0.0, 0.0), hi=(1024.0, 1024.0, float(nz)), G=0.0)
     sim = gp.Sim(cfg)
-    src = torch.ones(nz, 256, 256, dtype=torch.float64, device="cuda")
+    src = torch.ones(nz, 1024, 1024, dtype=torch.float64, device="cuda")
     for _ in range(5):
         sim.set_field("rho", src)
     sim.sync()
-    print(json.dumps({"copy_probe_bytes_read": 8 * 256 * 256 * nz, "copy_probe_bytes_written": 8 * 256 * 256 * nz,
+    print(json.dumps({"copy_probe_bytes_read": 8 * 1024 * 1024 * nz, "copy_probe_bytes_written": 8 * 1024 * 1024 * nz,
                       "launches": 5}), flush=True)
+
+
+def library_source_hash():
+    """SHA-256 over the library's HIP sources and public header: a recorded
+    HBM-traffic figure is reported only for the kernels it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1311_0861_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    files.append(os.path.join(ROOT, "include", "gpupegas.h"))
+    for path in files:
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, n, precision, path=None):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (a line 'traffic: <kernel> <n> <precision> <bytes> <source hash>'), or
+    None when there is none for this kernel, size and library source."""
+    path = path or os.path.join(ROOT, "profiles", "hbm_traffic_two_disk_%d_%s.md" % (n, precision))
+    if not os.path.exists(path):
+        return None
+    want = library_source_hash()
+    with open(path) as f:
+        for line in f:
+            parts = line.strip().strip("`").split()
+            if len(parts) == 6 and parts[0] == "traffic:" and parts[1] == kernel and parts[2] == str(n) \
+                    and parts[3] == precision and parts[5] == want:
+                return int(parts[4])
+    return None
 
 
 def timed_steps(obj, steps, warmup):
@@ -181,8 +215,11 @@ def batch_form(args):
 
 def main():
     args = parse()
+    if args.print_source_hash:
+        print(library_source_hash())
+        return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (one process, one MI355X); "
+        print("bench.py: the benchmark runs on one GPU only (one process, one MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
@@ -224,12 +261,7 @@ def main():
     kid = gp.KERNEL_NAMES.index(dom)
     bpc = sim.bytes_per_cell(kid)
     achieved = bpc * ncell / (kt[dom] * 1e-3) / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            tr = json.load(f)
-        if tr.get("kernel") == dom and tr.get("n") == n and tr.get("precision") == args.precision:
-            traffic = tr.get("bytes_per_launch")
+    traffic = recorded_traffic(dom, n, args.precision, args.traffic)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernel_ms": round(kt[dom], 5), "bytes_per_cell": bpc}

@@ -108,9 +108,10 @@ struct WorkItem {
 
 // The hardware hands consecutive workgroups to the 8 XCDs in turn, and each
 // XCD has its own L2.  A persistent launch gives XCD x one contiguous range of
-// work items (tiles of one slab of z planes, in order); its workgroups stride
-// through that range together, so tiles sharing y/z halos run on the same XCD
-// close in time.  Which workgroup takes a tile never changes a result.
+// work items (a block of tiles that share halos, in the order the host lists
+// them); its workgroups stride through that range together, so tiles sharing
+// halos run on the same XCD close in time.  Which workgroup takes a tile never
+// changes a result.
 constexpr unsigned kNumXcd = 8;
 struct WorkRange {
   unsigned first, end, stride;

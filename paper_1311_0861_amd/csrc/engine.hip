@@ -570,7 +570,18 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   unsigned soff = 0;
   for (int r = 0; r < nruns; r++) {
     RunHost& R = b->runs[r];
-    for (unsigned t = 0; t < R.ntiles; t++) cw.push_back({r, (int)t});
+    // Cell tiles go in chunks of cz z planes; inside a chunk, tile columns in
+    // x-then-y order, each walked z fastest.  The workgroups of an XCD, which
+    // take consecutive items, then share one plane of a column while its z
+    // neighbours are read, and the x / y neighbour columns follow within a few
+    // dozen items, so the 7-point stencils re-read their halos from L2
+    // instead of HBM.  Partial rows stay indexed by tile, so the order changes
+    // no result.
+    const int cz = std::max(4, std::min(16, 64 / R.ntx));
+    for (int z0 = 0; z0 < R.g.nz; z0 += cz)
+      for (int ty = 0; ty < R.nty; ty++)
+        for (int tx = 0; tx < R.ntx; tx++)
+          for (int k = z0; k < std::min(z0 + cz, R.g.nz); k++) cw.push_back({r, tx + R.ntx * (ty + R.nty * k)});
     for (unsigned t = 0; t < R.nvtiles; t++) vw.push_back({r, (int)t});
     const unsigned nscr = std::max(1u, std::min(256u, R.ntiles / 64));
     const unsigned chunk = (R.ntiles + nscr - 1) / nscr;
