@@ -204,7 +204,7 @@ def batch_form(args):
     out = {"workload": "48 two-disk runs, sizes drawn from 64^3/96^3/128^3, FP32, one launch per stage",
            "cells": cells, "value": round(cells * args.form_steps / sec / 1e6, 2), "unit": "Mcell-updates/s",
            "steps": args.form_steps,
-           "launch": {k: b.get_launch(k) for k in ("eulerian", "vertex", "lagrangian")},
+           "launch": {k: b.get_launch(k) for k in gp.CELL_KERNELS},
            "kernels": {k: {"ms": round(v, 4),
                            "GB/s": round(b.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * cells / (v * 1e-3) / 1e9, 1)
                            if v > 0 else None} for k, v in kt.items()}}
@@ -269,7 +269,7 @@ def main():
                    "GB/s": round(sim.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * ncell / (v * 1e-3) / 1e9, 1)
                    if v > 0 else None} for k, v in kt.items()}
     step_bytes = sim.bytes_per_cell(-1)
-    launch = {k: sim.get_launch(k) for k in ("eulerian", "vertex", "lagrangian")}
+    launch = {k: sim.get_launch(k) for k in gp.CELL_KERNELS}
     sim.close()
 
     # ---- CPU oracle on a bounded sample of the same workload -----------------

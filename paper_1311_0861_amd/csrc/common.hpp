@@ -12,16 +12,21 @@ namespace gp {
 
 constexpr int kNF = 22;    // state fields
 constexpr int kNO = 20;    // fields other than rho and n (stored in the working precision)
-constexpr int kNP = 16;    // per-block partial-sum slots
 constexpr int kDiagCap = 4096;
 
-// Partial-sum slots written by the per-cell epilogues and read by the finalize.
+// Per-tile partial sums: one block of kNS slots per component (gas first,
+// then stars / dark matter), each written by that component's Lagrangian
+// kernel and combined by the fixed-order reductions.
 enum : int {
-  P_SPEED = 0,  // max signal speed (max, not sum)
-  P_MGAS, P_MBME, P_MOMX, P_MOMY, P_MOMZ, P_EGAS, P_EBME,
-  P_KGAS, P_KBME, P_OUTG, P_OUTB, P_SYNCG, P_SYNCB, P_ERR,
-  P_PAD
+  S_SPEED = 0,  // max signal speed (max, not sum)
+  S_MASS, S_MOMX, S_MOMY, S_MOMZ, S_ENERGY, S_KAPPA, S_OUTFLOW, S_NSYNC,
+  S_ERR,        // error bits (or, not sum)
+  kNS
 };
+constexpr int kGasSlots = 0;
+constexpr int kBmeSlots = kNS;
+constexpr int kNP = 2 * kNS;  // slots per partial row
+enum Component : int { COMP_GAS = 0, COMP_BME = 1 };
 
 // Latched device error bits (also reported per diagnostics record).
 enum : uint32_t {
@@ -157,6 +162,78 @@ __device__ __forceinline__ float rcp(float x) {
 template <typename T>
 __device__ __forceinline__ gptr<T> as_global(T* p) {
   return (gptr<T>)p;
+}
+
+// Addresses of a cell's 7-point stencil.  A tile lies in one z plane, so the
+// planes it touches (k-1, k, k+1 under a boundary rule) are the same for the
+// whole wave; each lane keeps 32-bit in-plane element offsets.  A load is a
+// wave-uniform plane base (scalar registers) plus a 32-bit lane byte offset,
+// i.e. one global load with a scalar base and no 64-bit address arithmetic in
+// vector registers.  Point p: 0 centre, 1 / 2 minus / plus x, 3 / 4 minus /
+// plus y, 5 / 6 minus / plus z.
+struct Stencil {
+  size_t z[3];     // element offsets of planes k-1, k, k+1
+  uint32_t xy[5];  // in-plane offsets of the centre, x-1, x+1, y-1, y+1
+};
+
+// wrap = true applies the periodic rule on every axis (the potential),
+// otherwise each axis follows its hydrodynamic boundary condition.
+__device__ __forceinline__ Stencil make_stencil(const Grid& g, int i, int j, int k, bool wrap) {
+  Stencil s;
+  const size_t nxy = (size_t)g.nx * g.ny;
+  const uint32_t nx = (uint32_t)g.nx;
+  const int im = wrap ? wrap_index(i - 1, g.nx) : bc_index(i - 1, g.nx, g.bc[0]);
+  const int ip = wrap ? wrap_index(i + 1, g.nx) : bc_index(i + 1, g.nx, g.bc[0]);
+  const int jm = wrap ? wrap_index(j - 1, g.ny) : bc_index(j - 1, g.ny, g.bc[1]);
+  const int jp = wrap ? wrap_index(j + 1, g.ny) : bc_index(j + 1, g.ny, g.bc[1]);
+  const int km = wrap ? wrap_index(k - 1, g.nz) : bc_index(k - 1, g.nz, g.bc[2]);
+  const int kp = wrap ? wrap_index(k + 1, g.nz) : bc_index(k + 1, g.nz, g.bc[2]);
+  s.z[0] = nxy * (size_t)km;
+  s.z[1] = nxy * (size_t)k;
+  s.z[2] = nxy * (size_t)kp;
+  s.xy[0] = (uint32_t)i + nx * (uint32_t)j;
+  s.xy[1] = (uint32_t)im + nx * (uint32_t)j;
+  s.xy[2] = (uint32_t)ip + nx * (uint32_t)j;
+  s.xy[3] = (uint32_t)i + nx * (uint32_t)jm;
+  s.xy[4] = (uint32_t)i + nx * (uint32_t)jp;
+  return s;
+}
+
+// Element at plane offset z (uniform) and in-plane offset xy (per lane).
+template <typename E>
+__device__ __forceinline__ E ld_at(gptr<const E> base, size_t z, uint32_t xy) {
+  const gptr<const char> plane = (gptr<const char>)(base + z);
+  return *(gptr<const E>)(plane + xy * (uint32_t)sizeof(E));
+}
+template <typename E>
+__device__ __forceinline__ void st_at(gptr<E> base, size_t z, uint32_t xy, E v) {
+  const gptr<char> plane = (gptr<char>)(base + z);
+  *(gptr<E>)(plane + xy * (uint32_t)sizeof(E)) = v;
+}
+// Stencil point P (compile-time) of an array.
+template <int P, typename E>
+__device__ __forceinline__ E ld_pt(gptr<const E> base, const Stencil& s) {
+  if constexpr (P == 0) return ld_at(base, s.z[1], s.xy[0]);
+  if constexpr (P >= 1 && P <= 4) return ld_at(base, s.z[1], s.xy[P]);
+  if constexpr (P == 5) return ld_at(base, s.z[0], s.xy[0]);
+  return ld_at(base, s.z[2], s.xy[0]);
+}
+
+// Tile coordinates of a cell work item: lane (threadIdx.x, threadIdx.y) of
+// tile t covers cell (i, j) of plane k.
+struct TileCell {
+  int i, j, k;
+  bool inside;
+};
+template <typename R>
+__device__ __forceinline__ TileCell tile_cell(const R& run, int tile) {
+  TileCell c;
+  const int ntx = run.ntx, nty = run.nty;
+  c.i = (tile % ntx) * kTX + (int)threadIdx.x;
+  c.j = ((tile / ntx) % nty) * kTY + (int)threadIdx.y;
+  c.k = tile / (ntx * nty);
+  c.inside = c.i < run.g.nx && c.j < run.g.ny;
+  return c;
 }
 
 template <typename T>

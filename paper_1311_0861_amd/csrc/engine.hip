@@ -36,8 +36,8 @@ using namespace gp;
 
 namespace {
 
-constexpr int kTunedKernels = 3;  // Eulerian, vertex, Lagrangian
-const int kTunedIds[kTunedKernels] = {GP_K_EUL, GP_K_VERTEX, GP_K_LAG};
+constexpr int kTunedKernels = 5;  // the per-cell kernels
+const int kTunedIds[kTunedKernels] = {GP_K_EUL_GAS, GP_K_EUL_BME, GP_K_VERTEX, GP_K_LAG_GAS, GP_K_LAG_BME};
 
 struct RunHost {
   gp_config cfg{};
@@ -247,9 +247,19 @@ template <typename T>
 void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
   switch (k) {
-    case GP_K_EUL: launch_eulerian<T>(runs, b->cell_work, b->ncell_work, b->parity, nblocks, b->st); break;
+    case GP_K_EUL_GAS:
+      launch_eulerian<T>(runs, b->cell_work, b->ncell_work, b->parity, COMP_GAS, nblocks, b->st);
+      break;
+    case GP_K_EUL_BME:
+      launch_eulerian<T>(runs, b->cell_work, b->ncell_work, b->parity, COMP_BME, nblocks, b->st);
+      break;
     case GP_K_VERTEX: launch_vertex<T>(runs, b->vtx_work, b->nvtx_work, nblocks, b->st); break;
-    case GP_K_LAG: launch_lagrangian<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, nblocks, b->st);
+    case GP_K_LAG_GAS:
+      launch_lagrangian<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, COMP_GAS, nblocks, b->st);
+      break;
+    case GP_K_LAG_BME:
+      launch_lagrangian<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, COMP_BME, nblocks, b->st);
+      break;
   }
 }
 
@@ -299,11 +309,13 @@ void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
   };
   switch (stage) {
     case GP_STAGE_EUL:
-      cell(GP_K_EUL);
+      cell(GP_K_EUL_GAS);
+      cell(GP_K_EUL_BME);
       break;
     case GP_STAGE_LAG:
       cell(GP_K_VERTEX);
-      cell(GP_K_LAG);
+      cell(GP_K_LAG_GAS);
+      cell(GP_K_LAG_BME);
       if (allow_tune && b->tune) b->tuned = true;
       b->parity ^= 1;
       enqueue_reduce(b, tm);
@@ -320,7 +332,7 @@ void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
 template <typename T>
 void enqueue_prologue(gp_batch* b) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
-  launch_init_partials<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, b->blocks[GP_K_LAG], b->st);
+  launch_init_partials<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, b->blocks[GP_K_LAG_BME], b->st);
   enqueue_reduce(b, nullptr);
   enqueue_poisson<T>(b, nullptr);
   enqueue_finalize(b, 0, nullptr);
@@ -678,8 +690,10 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(b, e, "engine upload");
   for (int k = 0; k < GP_NKERNELS; k++) b->blocks[k] = 0;
-  b->blocks[GP_K_EUL] = b->ncell_work;
-  b->blocks[GP_K_LAG] = b->ncell_work;
+  b->blocks[GP_K_EUL_GAS] = b->ncell_work;
+  b->blocks[GP_K_EUL_BME] = b->ncell_work;
+  b->blocks[GP_K_LAG_GAS] = b->ncell_work;
+  b->blocks[GP_K_LAG_BME] = b->ncell_work;
   b->blocks[GP_K_VERTEX] = b->nvtx_work;
   return GP_OK;
 }
@@ -853,16 +867,24 @@ double engine_bytes_per_cell(const gp_batch* b, int32_t kernel) {
     vr += (double)(R.g.nx + 1) * (R.g.ny + 1) * (R.g.nz + 1);
   }
   vr /= cells;  // vertices per cell
-  const double eul = 2 * 8.0 + 20 * es + es + 20 * es;  // read rho, n, 20 fields, Phi; write 20
-  const double vtx = 6 * es + 6 * es * vr;              // read 6 velocities; write 6 per vertex
-  const double lag = 2 * 8.0 + 20 * es + 6 * es * vr + 2 * 8.0 + 20 * es;  // + corners; write 22
+  // Eulerian: read the density, the component's fields and Phi; write its fields
+  const double eul_gas = 8.0 + 5 * es + es + 5 * es;
+  const double eul_bme = 8.0 + 15 * es + es + 15 * es;
+  const double vtx = 6 * es + 6 * es * vr;  // read 6 velocities; write 6 per vertex
+  // Lagrangian: read the density, the post-Eulerian fields and 3 corner
+  // velocity components; write the density and the fields
+  const double lag_gas = 8.0 + 5 * es + 3 * es * vr + 8.0 + 5 * es;
+  const double lag_bme = 8.0 + 15 * es + 3 * es * vr + 8.0 + 15 * es;
   switch (kernel) {
-    case GP_K_EUL: return eul;
+    case GP_K_EUL_GAS: return eul_gas;
+    case GP_K_EUL_BME: return eul_bme;
     case GP_K_VERTEX: return vtx;
-    case GP_K_LAG: return lag;
+    case GP_K_LAG_GAS: return lag_gas;
+    case GP_K_LAG_BME: return lag_bme;
+    case GP_K_REDUCE:
     case GP_K_FINALIZE: return 0.0;
     case -1: {
-      double t = eul + vtx + lag;
+      double t = eul_gas + eul_bme + vtx + lag_gas + lag_bme;
       for (int k = GP_K_FFT_X_FWD; k <= GP_K_FFT_X_INV; k++) t += fft_bytes_per_cell(b, k);
       return t;
     }

@@ -13,37 +13,58 @@
 // not touched by this stage.  The momentum slots of the output hold the
 // post-Eulerian velocities v' = m'/rho and u' = q'/n, which is what the
 // Lagrangian stage advects with (it rebuilds m' = rho v' where it needs it).
+//
+// The two components only share the potential, so each has its own kernel:
+// the gas kernel touches 5 + 1 arrays per stencil point, the stars / dark
+// matter kernel 10 + 1, and each holds half the live state of a joint one,
+// which buys occupancy for these latency-bound stencils.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace gp {
 
+// Gravity acceleration -grad Phi at a cell (zero when G = 0): central
+// differences of the periodic potential.
 template <typename T>
-struct Prim {
+__device__ __forceinline__ void gravity(gptr<const T> phi, const Grid& g, double G, int i, int j, int k,
+                                        T grad[3]) {
+  grad[0] = grad[1] = grad[2] = T(0);
+  if (G == 0.0) return;
+  const Stencil w = make_stencil(g, i, j, k, true);
+  const T r2h = (T)(0.5 / g.h);
+  grad[0] = (ld_pt<2>(phi, w) - ld_pt<1>(phi, w)) * r2h;
+  grad[1] = (ld_pt<4>(phi, w) - ld_pt<3>(phi, w)) * r2h;
+  grad[2] = (ld_pt<6>(phi, w) - ld_pt<5>(phi, w)) * r2h;
+}
+
+// ---------------------------------------------------------------- gas ----
+
+template <typename T>
+struct GasPrim {
   T rho, v[3], p;
-  T n, u[3], P[6];
 };
 
 template <typename T>
-__device__ __forceinline__ void load_prim(const Fields<T>& s, size_t c, T gm1, Prim<T>& q) {
-  q.rho = (T)s.rho[c];
-  q.n = (T)s.nb[c];
-  const T ir = rcp(q.rho), in = rcp(q.n);
+struct GasIn {
+  gptr<const double> rho;
+  gptr<const T> m[3], E, e;
+};
+
+template <int P, typename T>
+__device__ __forceinline__ GasPrim<T> load_gas(const GasIn<T>& in, const Stencil& s, T gm1) {
+  GasPrim<T> q;
+  q.rho = (T)ld_pt<P>(in.rho, s);
+  const T ir = rcp(q.rho);
 #pragma unroll
-  for (int d = 0; d < 3; d++) {
-    q.v[d] = s.o[oidx(GP_MX + d)][c] * ir;
-    q.u[d] = s.o[oidx(GP_QX + d)][c] * in;
-  }
-  q.p = gm1 * s.o[oidx(GP_EINT)][c];
-#pragma unroll
-  for (int m = 0; m < 6; m++) q.P[m] = s.o[oidx(GP_PXX + m)][c];
+  for (int d = 0; d < 3; d++) q.v[d] = ld_pt<P>(in.m[d], s) * ir;
+  q.p = gm1 * ld_pt<P>(in.e, s);
+  return q;
 }
 
 // Sec. 2.1: V and P at a face between left and right states; z is the
 // acoustic impedance sqrt(gamma (pL + pR) rhoL rhoR / (rhoL + rhoR)).
 template <typename T>
-__device__ __forceinline__ void gas_face(const Prim<T>& L, const Prim<T>& R, int d, T gamma, T& V,
-                                         T& P) {
+__device__ __forceinline__ void gas_face(const GasPrim<T>& L, const GasPrim<T>& R, int d, T gamma, T& V, T& P) {
   const T pl = L.p, pr = R.p;
   const T z = sqrt(gamma * (pl + pr) * L.rho * R.rho * rcp(L.rho + R.rho));
   const T rz = rcp(z);
@@ -51,12 +72,87 @@ __device__ __forceinline__ void gas_face(const Prim<T>& L, const Prim<T>& R, int
   P = T(0.5) * (pl + pr) + T(0.5) * (L.v[d] - R.v[d]) * z;
 }
 
+template <int D, typename T>
+__device__ __forceinline__ void gas_axis(const GasIn<T>& in, const Stencil& s, const GasPrim<T>& C, T gamma,
+                                         T gm1, T& dP, T& dPV, T& dV) {
+  T Vm, Pm, Vp, Pp;
+  const GasPrim<T> L = load_gas<1 + 2 * D>(in, s, gm1);
+  const GasPrim<T> R = load_gas<2 + 2 * D>(in, s, gm1);
+  gas_face(L, C, D, gamma, Vm, Pm);
+  gas_face(C, R, D, gamma, Vp, Pp);
+  dP = Pp - Pm;
+  dPV += Pp * Vp - Pm * Vm;
+  dV += Vp - Vm;
+}
+
+template <typename T>
+__device__ __forceinline__ void eul_gas_cell(const RunDev<T>& R, int parity, double tau_d, int i, int j, int k) {
+  const Grid& g = R.g;
+  const T tau = (T)tau_d, r = (T)(tau_d / g.h);
+  const T gamma = (T)R.ph.gamma, gm1 = gamma - T(1);
+  const Stencil s = make_stencil(g, i, j, k, false);
+  GasIn<T> in;
+  in.rho = as_global((const double*)R.dens[parity][0]);
+#pragma unroll
+  for (int d = 0; d < 3; d++) in.m[d] = as_global((const T*)R.cur[oidx(GP_MX + d)]);
+  in.E = as_global((const T*)R.cur[oidx(GP_E)]);
+  in.e = as_global((const T*)R.cur[oidx(GP_EINT)]);
+
+  T grad[3];
+  gravity<T>(as_global((const T*)R.phi), g, R.ph.G, i, j, k, grad);
+  const GasPrim<T> C = load_gas<0>(in, s, gm1);
+  T dP[3], dPV = T(0), dV = T(0);
+  gas_axis<0>(in, s, C, gamma, gm1, dP[0], dPV, dV);
+  gas_axis<1>(in, s, C, gamma, gm1, dP[1], dPV, dV);
+  gas_axis<2>(in, s, C, gamma, gm1, dP[2], dPV, dV);
+
+  // momentum slots receive v' = m' / rho
+  T m[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) m[d] = ld_pt<0>(in.m[d], s);
+  const T irho = rcp(C.rho);
+  const size_t z = s.z[1];
+  const uint32_t xy = s.xy[0];
+#pragma unroll
+  for (int d = 0; d < 3; d++)
+    st_at(as_global((T*)R.tmp[oidx(GP_MX + d)]), z, xy, (m[d] - r * dP[d] - tau * C.rho * grad[d]) * irho);
+  st_at(as_global((T*)R.tmp[oidx(GP_E)]), z, xy,
+        ld_pt<0>(in.E, s) - r * dPV - tau * (m[0] * grad[0] + m[1] * grad[1] + m[2] * grad[2]));
+  const T e = ld_pt<0>(in.e, s);
+  st_at(as_global((T*)R.tmp[oidx(GP_EINT)]), z, xy, e - r * gm1 * e * dV);
+}
+
+// ------------------------------------------------- stars / dark matter ----
+
+template <typename T>
+struct BmePrim {
+  T n, u[3], P[6];
+};
+
+template <typename T>
+struct BmeIn {
+  gptr<const double> n;
+  gptr<const T> q[3], P[6], W[6];
+};
+
+template <int Pt, typename T>
+__device__ __forceinline__ BmePrim<T> load_bme(const BmeIn<T>& in, const Stencil& s) {
+  BmePrim<T> q;
+  q.n = (T)ld_pt<Pt>(in.n, s);
+  const T in_ = rcp(q.n);
+#pragma unroll
+  for (int d = 0; d < 3; d++) q.u[d] = ld_pt<Pt>(in.q[d], s) * in_;
+#pragma unroll
+  for (int m = 0; m < 6; m++) q.P[m] = ld_pt<Pt>(in.P[m], s);
+  return q;
+}
+
 // Sec. 2.2: interface state of the BME Eulerian system for normal axis D
 // (the printed x-normal formulas with the transverse axes a, b in place of
 // y, z).  Bracketed coefficients use the arithmetic means of n, Pi_DD, Pi_Da,
 // Pi_Db.  us[i] = u*_i, ps[i] = Pi*_{D i} in lab components.
 template <typename T, int D>
-__device__ __forceinline__ void bme_face(const Prim<T>& L, const Prim<T>& R, T us[3], T ps[3]) {
+__device__ __forceinline__ void bme_face(const BmePrim<T>& L, const BmePrim<T>& R, T us[3], T ps[3]) {
   constexpr int A_ = (D + 1) % 3, B_ = (D + 2) % 3;
   constexpr int sDD = sym(D, D), sDA = sym(D, A_), sDB = sym(D, B_);
   const T sqrt3 = T(1.7320508075688772935);
@@ -86,127 +182,115 @@ __device__ __forceinline__ void bme_face(const Prim<T>& L, const Prim<T>& R, T u
 }
 
 // Contributions of the two faces normal to axis D of the centre cell.
-template <typename T, int D>
-__device__ __forceinline__ void axis_terms(const Fields<T>& in, size_t cm, size_t cp, const Prim<T>& C,
-                                           T gamma, T gm1, T& dP, T& dPV, T& dV, T dq[3], T dW[6],
-                                           T dPi[6]) {
-  Prim<T> N;
-  T Vm, Pm, Vp, Pp, usm[3], psm[3], usp[3], psp[3];
-  load_prim(in, cm, gm1, N);
-  gas_face(N, C, D, gamma, Vm, Pm);
-  bme_face<T, D>(N, C, usm, psm);
-  load_prim(in, cp, gm1, N);
-  gas_face(C, N, D, gamma, Vp, Pp);
-  bme_face<T, D>(C, N, usp, psp);
-  dP = Pp - Pm;
-  dPV += Pp * Vp - Pm * Vm;
-  dV += Vp - Vm;
+template <int D, typename T>
+__device__ __forceinline__ void bme_axis(const BmeIn<T>& in, const Stencil& s, const BmePrim<T>& C, T dq[3],
+                                         T dW[6], T dPi[6]) {
+  T usm[3], psm[3], usp[3], psp[3];
+  {
+    const BmePrim<T> L = load_bme<1 + 2 * D>(in, s);
+    bme_face<T, D>(L, C, usm, psm);
+  }
+  {
+    const BmePrim<T> R = load_bme<2 + 2 * D>(in, s);
+    bme_face<T, D>(C, R, usp, psp);
+  }
 #pragma unroll
   for (int i = 0; i < 3; i++) dq[i] += psp[i] - psm[i];
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
     for (int j = i; j < 3; j++) {
-      const int s = sym(i, j);
-      dW[s] += (psp[j] * usp[i] + psp[i] * usp[j]) - (psm[j] * usm[i] + psm[i] * usm[j]);
-      dPi[s] += C.P[sym(j, D)] * (usp[i] - usm[i]) + C.P[sym(i, D)] * (usp[j] - usm[j]);
+      const int m = sym(i, j);
+      dW[m] += (psp[j] * usp[i] + psp[i] * usp[j]) - (psm[j] * usm[i] + psm[i] * usm[j]);
+      dPi[m] += C.P[sym(j, D)] * (usp[i] - usm[i]) + C.P[sym(i, D)] * (usp[j] - usm[j]);
     }
 }
 
-// One cell of the Eulerian stage; tau_d is the step, (i, j, k) the cell.
 template <typename T>
-__device__ __forceinline__ void eulerian_cell(const Fields<T>& in, const Fields<T>& out,
-                                              gptr<const T> phi, const Grid& g, const Phys& ph,
-                                              double tau_d, int i, int j, int k) {
-  const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
-  const size_t c = i + nx * j + nxy * k;
+__device__ __forceinline__ void eul_bme_cell(const RunDev<T>& R, int parity, double tau_d, int i, int j, int k) {
+  const Grid& g = R.g;
   const T tau = (T)tau_d, r = (T)(tau_d / g.h);
-  const T gamma = (T)ph.gamma, gm1 = gamma - T(1);
-
-  // neighbour cells under the hydrodynamic boundary rule
-  const size_t im = bc_index(i - 1, g.nx, g.bc[0]), ip = bc_index(i + 1, g.nx, g.bc[0]);
-  const size_t jm = bc_index(j - 1, g.ny, g.bc[1]), jp = bc_index(j + 1, g.ny, g.bc[1]);
-  const size_t km = bc_index(k - 1, g.nz, g.bc[2]), kp = bc_index(k + 1, g.nz, g.bc[2]);
-  const size_t row = nx * j + nxy * k;
-
-  // gravity: central difference of the periodic potential
-  T grad[3] = {T(0), T(0), T(0)};
-  if (ph.G != 0.0) {
-    const T r2h = (T)(0.5 / g.h);
-    const size_t wim = wrap_index(i - 1, g.nx), wip = wrap_index(i + 1, g.nx);
-    const size_t wjm = wrap_index(j - 1, g.ny), wjp = wrap_index(j + 1, g.ny);
-    const size_t wkm = wrap_index(k - 1, g.nz), wkp = wrap_index(k + 1, g.nz);
-    grad[0] = (phi[row + wip] - phi[row + wim]) * r2h;
-    grad[1] = (phi[i + nx * wjp + nxy * k] - phi[i + nx * wjm + nxy * k]) * r2h;
-    grad[2] = (phi[i + nx * j + nxy * wkp] - phi[i + nx * j + nxy * wkm]) * r2h;
+  const Stencil s = make_stencil(g, i, j, k, false);
+  BmeIn<T> in;
+  in.n = as_global((const double*)R.dens[parity][1]);
+#pragma unroll
+  for (int d = 0; d < 3; d++) in.q[d] = as_global((const T*)R.cur[oidx(GP_QX + d)]);
+#pragma unroll
+  for (int m = 0; m < 6; m++) {
+    in.P[m] = as_global((const T*)R.cur[oidx(GP_PXX + m)]);
+    in.W[m] = as_global((const T*)R.cur[oidx(GP_WXX + m)]);
   }
 
-  Prim<T> C;
-  load_prim(in, c, gm1, C);
-  T dP[3], dPV = T(0), dV = T(0);
+  T grad[3];
+  gravity<T>(as_global((const T*)R.phi), g, R.ph.G, i, j, k, grad);
+  const BmePrim<T> C = load_bme<0>(in, s);
   T dq[3] = {T(0), T(0), T(0)};
   T dW[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
   T dPi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  axis_terms<T, 0>(in, row + im, row + ip, C, gamma, gm1, dP[0], dPV, dV, dq, dW, dPi);
-  axis_terms<T, 1>(in, i + nx * jm + nxy * k, i + nx * jp + nxy * k, C, gamma, gm1, dP[1], dPV, dV,
-                   dq, dW, dPi);
-  axis_terms<T, 2>(in, i + nx * j + nxy * km, i + nx * j + nxy * kp, C, gamma, gm1, dP[2], dPV, dV,
-                   dq, dW, dPi);
+  bme_axis<0>(in, s, C, dq, dW, dPi);
+  bme_axis<1>(in, s, C, dq, dW, dPi);
+  bme_axis<2>(in, s, C, dq, dW, dPi);
 
-  // gas (momentum slots receive v' = m' / rho)
-  T m[3];
-#pragma unroll
-  for (int d = 0; d < 3; d++) m[d] = in.o[oidx(GP_MX + d)][c];
-  const T irho = rcp(C.rho), inb = rcp(C.n);
-#pragma unroll
-  for (int d = 0; d < 3; d++) out.o[oidx(GP_MX + d)][c] = (m[d] - r * dP[d] - tau * C.rho * grad[d]) * irho;
-  out.o[oidx(GP_E)][c] =
-      in.o[oidx(GP_E)][c] - r * dPV - tau * (m[0] * grad[0] + m[1] * grad[1] + m[2] * grad[2]);
-  const T e = in.o[oidx(GP_EINT)][c];
-  out.o[oidx(GP_EINT)][c] = e - r * gm1 * e * dV;
-
-  // stars / dark matter (momentum slots receive u' = q' / n)
+  // momentum slots receive u' = q' / n
   T q[3];
 #pragma unroll
-  for (int d = 0; d < 3; d++) q[d] = in.o[oidx(GP_QX + d)][c];
+  for (int d = 0; d < 3; d++) q[d] = ld_pt<0>(in.q[d], s);
+  const T inb = rcp(C.n);
+  const size_t z = s.z[1];
+  const uint32_t xy = s.xy[0];
 #pragma unroll
-  for (int d = 0; d < 3; d++) out.o[oidx(GP_QX + d)][c] = (q[d] - r * dq[d] - tau * C.n * grad[d]) * inb;
+  for (int d = 0; d < 3; d++)
+    st_at(as_global((T*)R.tmp[oidx(GP_QX + d)]), z, xy, (q[d] - r * dq[d] - tau * C.n * grad[d]) * inb);
 #pragma unroll
   for (int a = 0; a < 3; a++)
 #pragma unroll
     for (int b = a; b < 3; b++) {
-      const int s = sym(a, b);
-      out.o[oidx(GP_WXX + s)][c] =
-          in.o[oidx(GP_WXX + s)][c] - r * dW[s] - tau * (q[a] * grad[b] + q[b] * grad[a]);
-      out.o[oidx(GP_PXX + s)][c] = C.P[s] - r * dPi[s];
+      const int m = sym(a, b);
+      st_at(as_global((T*)R.tmp[oidx(GP_WXX + m)]), z, xy,
+            ld_pt<0>(in.W[m], s) - r * dW[m] - tau * (q[a] * grad[b] + q[b] * grad[a]));
+      st_at(as_global((T*)R.tmp[oidx(GP_PXX + m)]), z, xy, C.P[m] - r * dPi[m]);
     }
 }
 
-// Persistent launch over the (run, tile) work list of a batch.
+// ------------------------------------------------------------ launches ----
+
+// Persistent launches over the (run, tile) work list of a batch.
 template <typename T>
-__global__ void __launch_bounds__(kBlock, 3) k_eulerian(const RunDev<T>* __restrict__ runs,
-                                                     const WorkItem* __restrict__ work, unsigned nwork,
-                                                     int parity) {
+__global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict__ runs,
+                                                    const WorkItem* __restrict__ work, unsigned nwork, int parity) {
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
     const int run = uniform(work[w].run), tile = uniform(work[w].tile);
     const RunDev<T>& R = runs[run];
-    const int ntx = R.ntx, nty = R.nty;
-    const int i = (tile % ntx) * kTX + threadIdx.x;
-    const int j = ((tile / ntx) % nty) * kTY + threadIdx.y;
-    const int k = tile / (ntx * nty);
-    if (i < R.g.nx && j < R.g.ny)
-      eulerian_cell<T>(fields_state(R, parity), fields_eul(R), as_global((const T*)R.phi), R.g, R.ph, R.sc->dt, i, j, k);
+    const TileCell c = tile_cell(R, tile);
+    if (c.inside) eul_gas_cell<T>(R, parity, R.sc->dt, c.i, c.j, c.k);
   }
 }
 
 template <typename T>
-void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, unsigned nblocks,
-                     hipStream_t st) {
-  k_eulerian<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+__global__ void __launch_bounds__(kBlock) k_eul_bme(const RunDev<T>* __restrict__ runs,
+                                                    const WorkItem* __restrict__ work, unsigned nwork, int parity) {
+  const WorkRange wr = xcd_range(nwork);
+  for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
+    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const RunDev<T>& R = runs[run];
+    const TileCell c = tile_cell(R, tile);
+    if (c.inside) eul_bme_cell<T>(R, parity, R.sc->dt, c.i, c.j, c.k);
+  }
 }
 
-template void launch_eulerian<double>(const RunDev<double>*, const WorkItem*, unsigned, int, unsigned, hipStream_t);
-template void launch_eulerian<float>(const RunDev<float>*, const WorkItem*, unsigned, int, unsigned, hipStream_t);
+template <typename T>
+void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, int comp,
+                     unsigned nblocks, hipStream_t st) {
+  if (comp == COMP_GAS)
+    k_eul_gas<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+  else
+    k_eul_bme<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+}
+
+template void launch_eulerian<double>(const RunDev<double>*, const WorkItem*, unsigned, int, int, unsigned,
+                                      hipStream_t);
+template void launch_eulerian<float>(const RunDev<float>*, const WorkItem*, unsigned, int, int, unsigned,
+                                     hipStream_t);
 
 }  // namespace gp

@@ -8,20 +8,20 @@ namespace gp {
 // All per-cell stages are persistent launches of `nblocks` workgroups over a
 // (run, tile) work list; runs[] are the device descriptors of the batch.
 
-// ---- Eulerian stage --------------------------------------------------------
+// ---- Eulerian stage (comp = COMP_GAS or COMP_BME) --------------------------
 template <typename T>
-void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, unsigned nblocks,
-                     hipStream_t st);
+void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, int comp,
+                     unsigned nblocks, hipStream_t st);
 
 // ---- Lagrangian stage + energy balance + diagnostics partials -------------
 // Corner velocities from the post-Eulerian velocities (vertex work list).
 template <typename T>
 void launch_vertex(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, unsigned nblocks, hipStream_t st);
-// New state into cur / dens[parity ^ 1] and one kNP-slot partial row per tile
-// (row R.row0 + tile).
+// New state of component comp into cur / dens[parity ^ 1], and that
+// component's kNS slots of the partial row of each tile (row R.row0 + tile).
 template <typename T>
 void launch_lagrangian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, double* partials,
-                       unsigned nblocks, hipStream_t st);
+                       int comp, unsigned nblocks, hipStream_t st);
 // Partial rows of a state that has not been advanced (prologue).
 template <typename T>
 void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity,

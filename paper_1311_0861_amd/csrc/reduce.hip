@@ -14,11 +14,12 @@
 namespace gp {
 
 constexpr int kRedThreads = 256;
-constexpr int kLanesPerSlot = kRedThreads / kNP;  // 16 lanes per partial slot
+constexpr int kLanesPerSlot = kRedThreads / kNP;  // lanes per partial slot (the rest idle)
 
 __device__ __forceinline__ double combine(int slot, double a, double b) {
-  if (slot == P_SPEED) return fmax(a, b);
-  if (slot == P_ERR) return (double)((uint32_t)a | (uint32_t)b);
+  const int s = slot % kNS;
+  if (s == S_SPEED) return fmax(a, b);
+  if (s == S_ERR) return (double)((uint32_t)a | (uint32_t)b);
   return a + b;
 }
 
@@ -27,7 +28,8 @@ __device__ void reduce_rows(const double* in, int r0, int r1, double* out) {
   __shared__ double red[kRedThreads];
   const int slot = threadIdx.x % kNP, lane = threadIdx.x / kNP;
   double v = 0.0;
-  for (int r = r0 + lane; r < r1; r += kLanesPerSlot) v = combine(slot, v, in[(size_t)r * kNP + slot]);
+  if (lane < kLanesPerSlot)
+    for (int r = r0 + lane; r < r1; r += kLanesPerSlot) v = combine(slot, v, in[(size_t)r * kNP + slot]);
   red[threadIdx.x] = v;
   __syncthreads();
   if (threadIdx.x < kNP) {
@@ -53,7 +55,7 @@ __global__ void __launch_bounds__(kRedThreads) k_mean(const double* __restrict__
   __shared__ double tot[kNP];
   const FinDesc F = fin[blockIdx.x];
   reduce_rows(rows, (int)F.soff, (int)(F.soff + F.nscr), tot);
-  if (threadIdx.x == 0) F.sc->shift = (tot[P_MGAS] + tot[P_MBME]) / (double)F.g.ncell;
+  if (threadIdx.x == 0) F.sc->shift = (tot[kGasSlots + S_MASS] + tot[kBmeSlots + S_MASS]) / (double)F.g.ncell;
 }
 
 // Second level: workgroup r finishes run r.
@@ -78,18 +80,20 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
   const Phys& ph = F.ph;
 
   const double h = g.h, h3 = h * h * h;
+  constexpr int G = kGasSlots, B = kBmeSlots;
+  const double speed = fmax(tot[G + S_SPEED], tot[B + S_SPEED]);
   if (advanced) {
-    sc->outflow_gas += sc->dt * h * h * tot[P_OUTG];
-    sc->outflow_bme += sc->dt * h * h * tot[P_OUTB];
+    sc->outflow_gas += sc->dt * h * h * tot[G + S_OUTFLOW];
+    sc->outflow_bme += sc->dt * h * h * tot[B + S_OUTFLOW];
     sc->t += sc->dt;
     sc->step += 1;
   }
-  uint32_t err = (uint32_t)tot[P_ERR];
+  uint32_t err = (uint32_t)tot[G + S_ERR] | (uint32_t)tot[B + S_ERR];
   double dt;
   if (ph.fixed_dt > 0.0) {
     dt = ph.fixed_dt;
-  } else if (tot[P_SPEED] > 0.0) {
-    dt = ph.cfl * h / tot[P_SPEED];
+  } else if (speed > 0.0) {
+    dt = ph.cfl * h / speed;
   } else {
     dt = 0.0;
     err |= ERR_NOSPEED;
@@ -102,20 +106,18 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
   d.step = sc->step;
   d.t = sc->t;
   d.dt = dt;
-  d.mass_gas = h3 * tot[P_MGAS];
-  d.mass_bme = h3 * tot[P_MBME];
-  d.mom[0] = h3 * tot[P_MOMX];
-  d.mom[1] = h3 * tot[P_MOMY];
-  d.mom[2] = h3 * tot[P_MOMZ];
-  d.e_gas = h3 * tot[P_EGAS];
-  d.e_bme = h3 * tot[P_EBME];
+  d.mass_gas = h3 * tot[G + S_MASS];
+  d.mass_bme = h3 * tot[B + S_MASS];
+  for (int a = 0; a < 3; a++) d.mom[a] = h3 * (tot[G + S_MOMX + a] + tot[B + S_MOMX + a]);
+  d.e_gas = h3 * tot[G + S_ENERGY];
+  d.e_bme = h3 * tot[B + S_ENERGY];
   d.e_pot = 0.5 * h3 * F.epot_scale * ered[0];
-  d.kappa_gas = h3 * tot[P_KGAS];
-  d.kappa_bme = h3 * tot[P_KBME];
+  d.kappa_gas = h3 * tot[G + S_KAPPA];
+  d.kappa_bme = h3 * tot[B + S_KAPPA];
   d.outflow_gas = sc->outflow_gas;
   d.outflow_bme = sc->outflow_bme;
-  d.n_sync_gas = advanced ? tot[P_SYNCG] : 0.0;
-  d.n_sync_bme = advanced ? tot[P_SYNCB] : 0.0;
+  d.n_sync_gas = advanced ? tot[G + S_NSYNC] : 0.0;
+  d.n_sync_bme = advanced ? tot[B + S_NSYNC] : 0.0;
   d.err = sc->err;
   d.pad = 0u;
   F.ring[sc->ndiag % kDiagCap] = d;

@@ -69,7 +69,7 @@ def test_batch_result_independent_of_launch_size(gp, W):
         b = gp.Batch([c for c, _ in members])
         for r, (_, st) in enumerate(members):
             b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
-        for k in ("eulerian", "vertex", "lagrangian"):
+        for k in gp.CELL_KERNELS:
             b.set_launch(k, blocks)
         b.step(5)
         runs.append([_batch_state(b, r) for r in range(len(members))])
