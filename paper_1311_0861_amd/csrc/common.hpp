@@ -103,7 +103,7 @@ struct RunDev {
   DevScalars* sc;
   unsigned row0;       // first row of this run in the partial-sum table
   int ntx, nty;        // cell tiles per plane and per column
-  int vntx, vnty;      // unused (vertices go in flat order)
+  int cz, nkc;         // z planes per column chunk, chunks per column
 };
 
 struct WorkItem {

@@ -51,8 +51,8 @@ struct RunHost {
   void* phi = nullptr;
   DevScalars* sc = nullptr;
   gp_diag* ring = nullptr;
-  unsigned row0 = 0, ntiles = 0, nvtiles = 0;
-  int ntx = 0, nty = 0, vntx = 0, vnty = 0;
+  unsigned row0 = 0, ntiles = 0, nvtiles = 0, ncols = 0;
+  int ntx = 0, nty = 0, cz = 0, nkc = 0;
   int cls = 0, slot = 0;  // size class and position inside it
 };
 
@@ -90,8 +90,10 @@ struct gp_batch {
   std::vector<std::pair<void*, size_t>> allocs;
 
   void* runs_dev = nullptr;  // RunDev<T>[nruns]
-  WorkItem* cell_work = nullptr;
+  WorkItem* cell_work = nullptr;  // plane tiles (Eulerian)
   unsigned ncell_work = 0;
+  WorkItem* col_work = nullptr;   // tile columns by z chunk (Lagrangian, partial rows)
+  unsigned ncol_work = 0;
   WorkItem* vtx_work = nullptr;
   unsigned nvtx_work = 0;
   double* partials = nullptr;
@@ -255,15 +257,19 @@ void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
       break;
     case GP_K_VERTEX: launch_vertex<T>(runs, b->vtx_work, b->nvtx_work, nblocks, b->st); break;
     case GP_K_LAG_GAS:
-      launch_lagrangian<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, COMP_GAS, nblocks, b->st);
+      launch_lagrangian<T>(runs, b->col_work, b->ncol_work, b->parity, b->partials, COMP_GAS, nblocks, b->st);
       break;
     case GP_K_LAG_BME:
-      launch_lagrangian<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, COMP_BME, nblocks, b->st);
+      launch_lagrangian<T>(runs, b->col_work, b->ncol_work, b->parity, b->partials, COMP_BME, nblocks, b->st);
       break;
   }
 }
 
-unsigned work_count(const gp_batch* b, int k) { return k == GP_K_VERTEX ? b->nvtx_work : b->ncell_work; }
+unsigned work_count(const gp_batch* b, int k) {
+  if (k == GP_K_VERTEX) return b->nvtx_work;
+  if (k == GP_K_LAG_GAS || k == GP_K_LAG_BME) return b->ncol_work;
+  return b->ncell_work;
+}
 
 // Time the persistent grid-size candidates of kernel k and keep the fastest.
 // Every per-cell stage is idempotent with respect to its inputs (none of them
@@ -332,7 +338,7 @@ void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
 template <typename T>
 void enqueue_prologue(gp_batch* b) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
-  launch_init_partials<T>(runs, b->cell_work, b->ncell_work, b->parity, b->partials, b->blocks[GP_K_LAG_BME], b->st);
+  launch_init_partials<T>(runs, b->col_work, b->ncol_work, b->parity, b->partials, b->blocks[GP_K_LAG_BME], b->st);
   enqueue_reduce(b, nullptr);
   enqueue_poisson<T>(b, nullptr);
   enqueue_finalize(b, 0, nullptr);
@@ -442,8 +448,8 @@ RunDev<T> make_rundev(const RunHost& r) {
   d.row0 = r.row0;
   d.ntx = r.ntx;
   d.nty = r.nty;
-  d.vntx = r.vntx;
-  d.vnty = r.vnty;
+  d.cz = r.cz;
+  d.nkc = r.nkc;
   return d;
 }
 
@@ -485,11 +491,15 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     R.ntx = (R.g.nx + kTX - 1) / kTX;
     R.nty = (R.g.ny + kTY - 1) / kTY;
     R.ntiles = (unsigned)(R.ntx * R.nty * R.g.nz);
-    R.vntx = 0;  // vertices go in flat order, kBlock per work item
-    R.vnty = 0;
+    // Lagrangian column items: a tile column split into chunks of cz planes,
+    // as many as it takes to give the launch some 2048 items per run
+    // (chunks of 4 to 16 planes)
+    R.cz = (int)std::max<long>(4, std::min<long>(16, (long)R.ntx * R.nty * R.g.nz / 2048));
+    R.nkc = (R.g.nz + R.cz - 1) / R.cz;
+    R.ncols = (unsigned)(R.ntx * R.nty * R.nkc);
     R.nvtiles = (unsigned)(((size_t)(R.g.nx + 1) * (R.g.ny + 1) * (R.g.nz + 1) + kBlock - 1) / kBlock);
     R.row0 = row;
-    row += R.ntiles;
+    row += R.ncols;
     const auto key = std::make_tuple(R.g.nx, R.g.ny, R.g.nz, R.g.h, R.ph.G);
     auto it = cls_of.find(key);
     if (it == cls_of.end()) {
@@ -576,7 +586,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   b->epot = static_cast<double*>(dalloc(b, std::max(1u, eoff) * sizeof(double), &st));
 
   // work lists, partial rows, reduction items, finalize descriptors
-  std::vector<WorkItem> cw, vw;
+  std::vector<WorkItem> cw, vw, colw;
   std::vector<RedItem> items;
   std::vector<FinDesc> fins;
   unsigned soff = 0;
@@ -595,10 +605,13 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
         for (int tx = 0; tx < R.ntx; tx++)
           for (int k = z0; k < std::min(z0 + cz, R.g.nz); k++) cw.push_back({r, tx + R.ntx * (ty + R.nty * k)});
     for (unsigned t = 0; t < R.nvtiles; t++) vw.push_back({r, (int)t});
-    const unsigned nscr = std::max(1u, std::min(256u, R.ntiles / 64));
-    const unsigned chunk = (R.ntiles + nscr - 1) / nscr;
+    // column items, x fastest, then y, then the z chunk: the columns whose
+    // rings overlap run side by side
+    for (unsigned c = 0; c < R.ncols; c++) colw.push_back({r, (int)c});
+    const unsigned nscr = std::max(1u, std::min(256u, R.ncols / 16));
+    const unsigned chunk = (R.ncols + nscr - 1) / nscr;
     for (unsigned c = 0; c < nscr; c++) {
-      const unsigned a = std::min(R.ntiles, c * chunk), e = std::min(R.ntiles, a + chunk);
+      const unsigned a = std::min(R.ncols, c * chunk), e = std::min(R.ncols, a + chunk);
       items.push_back({R.row0 + a, R.row0 + e});
     }
     FinDesc fd{};
@@ -616,9 +629,11 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     soff += nscr;
   }
   b->ncell_work = (unsigned)cw.size();
+  b->ncol_work = (unsigned)colw.size();
   b->nvtx_work = (unsigned)vw.size();
   b->nred = (int)items.size();
   b->cell_work = static_cast<WorkItem*>(dalloc(b, cw.size() * sizeof(WorkItem), &st));
+  b->col_work = static_cast<WorkItem*>(dalloc(b, colw.size() * sizeof(WorkItem), &st));
   b->vtx_work = static_cast<WorkItem*>(dalloc(b, vw.size() * sizeof(WorkItem), &st));
   b->partials = static_cast<double*>(dalloc(b, (size_t)row * kNP * sizeof(double), &st));
   b->red_items = static_cast<RedItem*>(dalloc(b, items.size() * sizeof(RedItem), &st));
@@ -635,6 +650,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
   };
   put(b->cell_work, cw.data(), cw.size() * sizeof(WorkItem));
+  put(b->col_work, colw.data(), colw.size() * sizeof(WorkItem));
   put(b->vtx_work, vw.data(), vw.size() * sizeof(WorkItem));
   put(b->red_items, items.data(), items.size() * sizeof(RedItem));
   put(b->fin, fins.data(), fins.size() * sizeof(FinDesc));
@@ -692,8 +708,8 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   for (int k = 0; k < GP_NKERNELS; k++) b->blocks[k] = 0;
   b->blocks[GP_K_EUL_GAS] = b->ncell_work;
   b->blocks[GP_K_EUL_BME] = b->ncell_work;
-  b->blocks[GP_K_LAG_GAS] = b->ncell_work;
-  b->blocks[GP_K_LAG_BME] = b->ncell_work;
+  b->blocks[GP_K_LAG_GAS] = b->ncol_work;
+  b->blocks[GP_K_LAG_BME] = b->ncol_work;
   b->blocks[GP_K_VERTEX] = b->nvtx_work;
   return GP_OK;
 }

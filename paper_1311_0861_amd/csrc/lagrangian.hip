@@ -194,56 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex(const RunDev<T>* __restrict__
   }
 }
 
-// ---- Lagrangian cell update -------------------------------------------------
-
-// Corners of cell (i, j, k): vertex planes k and k+1 (uniform) and the four
-// in-plane vertices (i, j), (i+1, j), (i, j+1), (i+1, j+1).
-struct VtxStencil {
-  size_t z[2];
-  uint32_t xy[4];
-};
-
-__device__ __forceinline__ VtxStencil make_vtx_stencil(const Grid& g, int i, int j, int k) {
-  VtxStencil v;
-  const uint32_t vx = (uint32_t)g.nx + 1;
-  const size_t vxy = (size_t)vx * (size_t)(g.ny + 1);
-  v.z[0] = vxy * (size_t)k;
-  v.z[1] = vxy * (size_t)(k + 1);
-  v.xy[0] = (uint32_t)i + vx * (uint32_t)j;
-  v.xy[1] = v.xy[0] + 1u;
-  v.xy[2] = v.xy[0] + vx;
-  v.xy[3] = v.xy[2] + 1u;
-  return v;
-}
-
-// A+ / A- of the six faces from the corner velocities of one component
-// (components c0 .. c0+2 of the corner array): [axis][side], side 0 = minus
-// face, 1 = plus face.  Corner s = sx + 2 sy + 4 sz is vertex (i + sx, j + sy,
-// k + sz); a face normal to d on side `side` has the 4 corners with
-// s_d = side, summed in increasing s -- the same order from both cells that
-// share the face.
-template <typename T>
-__device__ __forceinline__ void face_coeffs(gptr<const T> vtx, size_t vstride, int c0, const VtxStencil& V,
-                                            T ap[3][2], T am[3][2]) {
-#pragma unroll
-  for (int d = 0; d < 3; d++) {
-    const gptr<const T> comp = vtx + (size_t)(c0 + d) * vstride;
-    T pos[2] = {T(0), T(0)}, neg[2] = {T(0), T(0)};
-#pragma unroll
-    for (int s = 0; s < 8; s++) {
-      const int sx = s & 1, sy = (s >> 1) & 1, sz = (s >> 2) & 1;
-      const T v = ld_at(comp, V.z[sz], V.xy[sx + 2 * sy]);
-      const int side = d == 0 ? sx : (d == 1 ? sy : sz);
-      pos[side] += fmax(v, T(0));
-      neg[side] += fmin(v, T(0));
-    }
-#pragma unroll
-    for (int side = 0; side < 2; side++) {
-      ap[d][side] = pos[side] * T(0.25);
-      am[d][side] = neg[side] * T(0.25);
-    }
-  }
-}
+// ---- Lagrangian flux update -------------------------------------------------
 
 // Face flux of an FP64 density; both cells sharing the face evaluate exactly
 // this expression with the same operands.
@@ -291,22 +242,10 @@ __device__ __forceinline__ Weights<T> flux_weights(const T ap[3][2], const T am[
   return w;
 }
 
-// Flux update of one field from its post-Eulerian 7-point values; a momentum
-// slot holds a velocity and is multiplied by the density of the same point.
-template <bool kMom, typename T>
-__device__ __forceinline__ T advect(gptr<const T> f, const Stencil& s, const Weights<T>& w, const double dn[7]) {
-  T x[7];
-  x[0] = ld_pt<0>(f, s);
-  x[1] = ld_pt<1>(f, s);
-  x[2] = ld_pt<2>(f, s);
-  x[3] = ld_pt<3>(f, s);
-  x[4] = ld_pt<4>(f, s);
-  x[5] = ld_pt<5>(f, s);
-  x[6] = ld_pt<6>(f, s);
-  if constexpr (kMom) {
-#pragma unroll
-    for (int p = 0; p < 7; p++) x[p] *= (T)dn[p];
-  }
+// Flux update of one field from its 7 post-Eulerian point values x[] (point
+// order: centre, minus / plus x, y, z).
+template <typename T>
+__device__ __forceinline__ T advect7(const T x[7], const Weights<T>& w) {
   T v = w.c * x[0];
 #pragma unroll
   for (int d = 0; d < 3; d++) {
@@ -316,38 +255,56 @@ __device__ __forceinline__ T advect(gptr<const T> f, const Stencil& s, const Wei
   return v;
 }
 
-__device__ __forceinline__ void load_density(double dn[7], gptr<const double> f, const Stencil& s) {
-  dn[0] = ld_pt<0>(f, s);
-  dn[1] = ld_pt<1>(f, s);
-  dn[2] = ld_pt<2>(f, s);
-  dn[3] = ld_pt<3>(f, s);
-  dn[4] = ld_pt<4>(f, s);
-  dn[5] = ld_pt<5>(f, s);
-  dn[6] = ld_pt<6>(f, s);
+// ---- column kernels ---------------------------------------------------------
+//
+// A workgroup owns a 64 x 4 tile of cells and walks a chunk of z planes.  For
+// plane k the tile of every advected field, with a one-cell ring of x / y
+// neighbours, sits in LDS; the z neighbours (planes k-1 and k+1) stay in
+// registers from one plane to the next, and the corner velocities of vertex
+// planes k and k+1 sit in a double-buffered LDS tile.  Each plane of a field
+// is thus read from memory once per tile plus its ring, in coalesced rows,
+// instead of 7 times through the cache hierarchy.
+
+constexpr int kLX = kTX + 2, kLY = kTY + 2;  // plane tile with its neighbour ring
+constexpr int kVX = kTX + 1, kVY = kTY + 1;  // vertex tile of a cell tile
+constexpr int kRing = 2 * kLX + 2 * kTY;     // ring cells of a plane tile
+constexpr int kVTile = 3 * kVX * kVY;        // corner values staged per vertex plane
+constexpr int kVPer = (kVTile + kBlock - 1) / kBlock;
+
+// Advected fields of a component (after the density), its corner velocity
+// components and density slot.
+template <int C>
+struct Comp;
+template <>
+struct Comp<COMP_GAS> {
+  static constexpr int kNF = 5;  // m_x m_y m_z E e
+  static constexpr int kFirst = GP_MX;
+  static constexpr int kVel = 0;
+  static constexpr int kDens = 0;
+};
+template <>
+struct Comp<COMP_BME> {
+  static constexpr int kNF = 15;  // q_x q_y q_z, Pi (6), W (6)
+  static constexpr int kFirst = GP_QX;
+  static constexpr int kVel = 3;
+  static constexpr int kDens = 1;
+};
+
+// Source cell of tile position x for the LDS tile: the boundary rule on the
+// one-cell ring outside the grid (x = -1 or x = n); positions further out are
+// never read and take any valid cell.
+__device__ __forceinline__ int ring_src(int x, int n, int bc) {
+  if (x < 0 || x == n) return bc_index(x, n, bc);
+  return x < n ? x : n - 1;
 }
 
-// Gas: rho, m, E, e of cell (i, j, k).
+// Gas epilogue: kappa, energy balance, stores and diagnostics of a cell.
 template <typename T>
-__device__ __forceinline__ void lag_gas_cell(Acc& acc, const RunDev<T>& R, int parity, double tau_d, int i, int j,
-                                             int k) {
-  const Grid& g = R.g;
-  const double rd = tau_d / g.h;
-  const Stencil s = make_stencil(g, i, j, k, false);
-  T ap[3][2], am[3][2];
-  face_coeffs(as_global((const T*)R.vtx), R.vstride, 0, make_vtx_stencil(g, i, j, k), ap, am);
-  double dn[7];
-  load_density(dn, as_global((const double*)R.dens[parity][0]), s);
-  double outg;
-  const double rho = advect_density(dn, ap, am, rd, g, i, j, k, outg);
-  const Weights<T> w = flux_weights(ap, am, (T)rd);
-
-  T m[3];
-#pragma unroll
-  for (int d = 0; d < 3; d++) m[d] = advect<true>(as_global((const T*)R.tmp[oidx(GP_MX + d)]), s, w, dn);
-  const T E = advect<false>(as_global((const T*)R.tmp[oidx(GP_E)]), s, w, dn);
-  T e = advect<false>(as_global((const T*)R.tmp[oidx(GP_EINT)]), s, w, dn);
-
-  // correctness integral, then the energy balance
+__device__ __forceinline__ void gas_finish(Acc& acc, const RunDev<T>& R, int parity, size_t z, uint32_t xy,
+                                           double rho, const T nv[5], double out) {
+  T m[3] = {nv[0], nv[1], nv[2]};
+  const T E = nv[3];
+  T e = nv[4];
   T ekin;
   acc.v[S_KAPPA] += (double)gas_kappa(rho, m, E, e, ekin);
   if (R.ph.eta >= 0.0) {
@@ -357,10 +314,7 @@ __device__ __forceinline__ void lag_gas_cell(Acc& acc, const RunDev<T>& R, int p
       acc.v[S_NSYNC] += 1.0;
     }
   }
-  acc.v[S_OUTFLOW] += outg;
-
-  const size_t z = s.z[1];
-  const uint32_t xy = s.xy[0];
+  acc.v[S_OUTFLOW] += out;
   st_at(as_global(R.dens[parity ^ 1][0]), z, xy, rho);
 #pragma unroll
   for (int d = 0; d < 3; d++) st_at(as_global(R.cur[oidx(GP_MX + d)]), z, xy, m[d]);
@@ -369,88 +323,266 @@ __device__ __forceinline__ void lag_gas_cell(Acc& acc, const RunDev<T>& R, int p
   gas_terms(acc, rho, m, E, e, (T)R.ph.gamma);
 }
 
-// Stars / dark matter: n, q, Pi, W of cell (i, j, k).
-template <typename T>
-__device__ __forceinline__ void lag_bme_cell(Acc& acc, const RunDev<T>& R, int parity, double tau_d, int i, int j,
-                                             int k) {
-  const Grid& g = R.g;
-  const double rd = tau_d / g.h;
-  const Stencil s = make_stencil(g, i, j, k, false);
-  T ap[3][2], am[3][2];
-  face_coeffs(as_global((const T*)R.vtx), R.vstride, 3, make_vtx_stencil(g, i, j, k), ap, am);
-  double dn[7];
-  load_density(dn, as_global((const double*)R.dens[parity][1]), s);
-  double outb;
-  const double n = advect_density(dn, ap, am, rd, g, i, j, k, outb);
-  const Weights<T> w = flux_weights(ap, am, (T)rd);
-
-  T q[3], P[6], W[6];
+// Stars / dark matter epilogue, streamed over the six stress / energy pairs
+// (next(m, P_m, W_m) forms pair m): kappa, the energy balance of each
+// diagonal stress, stores and diagnostics of a cell.
+template <typename T, typename Next>
+__device__ __forceinline__ void bme_stream(Acc& acc, const RunDev<T>& R, int parity, size_t z, uint32_t xy,
+                                           double n, const T q[3], double out, Next next) {
+  const T rn = T(n);
+  const T eta = (T)R.ph.eta;
+  const bool balance = R.ph.eta >= 0.0;
+  T kb = T(0), sp = T(0), wtr = T(0);
+  bool any = false, fin = isfinite(n), stress_ok = true;
 #pragma unroll
-  for (int d = 0; d < 3; d++) q[d] = advect<true>(as_global((const T*)R.tmp[oidx(GP_QX + d)]), s, w, dn);
+  for (int d = 0; d < 3; d++) fin = fin && isfinite(q[d]);
 #pragma unroll
-  for (int m = 0; m < 6; m++) {
-    P[m] = advect<false>(as_global((const T*)R.tmp[oidx(GP_PXX + m)]), s, w, dn);
-    W[m] = advect<false>(as_global((const T*)R.tmp[oidx(GP_WXX + m)]), s, w, dn);
-  }
-
-  // correctness integral, then the energy balance of each diagonal stress
-  T Tt[6];
-  acc.v[S_KAPPA] += (double)bme_kappa(n, q, P, W, Tt);
-  if (R.ph.eta >= 0.0) {
-    const T eta = (T)R.ph.eta;
-    bool any = false;
+  for (int a = 0; a < 3; a++)
 #pragma unroll
-    for (int d = 0; d < 3; d++) {
-      const int m = sym(d, d);
-      if (Tt[m] > eta * W[m]) {
-        P[m] = Tt[m];
-        any = true;
+    for (int b = a; b < 3; b++) {
+      const int m = sym(a, b);
+      T P, W;
+      next(m, P, W);
+      const T Tt = W - q[a] * q[b] / rn;
+      kb += fabs(Tt - P);
+      if (a == b) {
+        if (balance && Tt > eta * W) {
+          P = Tt;
+          any = true;
+        }
+        sp = fmax(sp, fabs(q[a] / rn) + sqrt(fmax(T(3) * P / rn, T(0))));
+        stress_ok = stress_ok && (P > T(0));
+        wtr += W;
       }
+      fin = fin && isfinite(P) && isfinite(W);
+      st_at(as_global(R.cur[oidx(GP_PXX + m)]), z, xy, P);
+      st_at(as_global(R.cur[oidx(GP_WXX + m)]), z, xy, W);
     }
-    if (any) acc.v[S_NSYNC] += 1.0;
-  }
-  acc.v[S_OUTFLOW] += outb;
-
-  const size_t z = s.z[1];
-  const uint32_t xy = s.xy[0];
+  acc.v[S_KAPPA] += (double)kb;
+  if (any) acc.v[S_NSYNC] += 1.0;
+  acc.v[S_OUTFLOW] += out;
   st_at(as_global(R.dens[parity ^ 1][1]), z, xy, n);
 #pragma unroll
   for (int d = 0; d < 3; d++) st_at(as_global(R.cur[oidx(GP_QX + d)]), z, xy, q[d]);
+  acc.v[S_SPEED] = fmax(acc.v[S_SPEED], (double)sp);
+  acc.v[S_MASS] += n;
 #pragma unroll
-  for (int m = 0; m < 6; m++) {
-    st_at(as_global(R.cur[oidx(GP_PXX + m)]), z, xy, P[m]);
-    st_at(as_global(R.cur[oidx(GP_WXX + m)]), z, xy, W[m]);
+  for (int d = 0; d < 3; d++) acc.v[S_MOMX + d] += (double)q[d];
+  acc.v[S_ENERGY] += 0.5 * (double)wtr;
+  uint32_t err = 0u;
+  if (!fin) err |= ERR_NONFINITE;
+  if (!(n > 0.0)) err |= ERR_DENSITY;
+  if (!stress_ok) err |= ERR_STRESS;
+  acc.err |= err;
+}
+
+// Per-cell inputs of the flux update: the face coefficients, weights and the
+// 7-point density of the centre cell.
+template <typename T>
+struct CellFlux {
+  T ap[3][2], am[3][2];
+  Weights<T> w;
+  double dn[7];
+};
+
+// The 7 post-Eulerian values of field f at the centre cell (x / y ring and
+// centre from the LDS tile, z neighbours from registers).
+template <typename T, int NF>
+__device__ __forceinline__ T field_update(const T (&tile)[NF][kLY][kLX], int f, int lx, int ly, T zm, T zp,
+                                          const CellFlux<T>& cf, bool mom) {
+  T x[7];
+  x[0] = tile[f][ly + 1][lx + 1];
+  x[1] = tile[f][ly + 1][lx];
+  x[2] = tile[f][ly + 1][lx + 2];
+  x[3] = tile[f][ly][lx + 1];
+  x[4] = tile[f][ly + 2][lx + 1];
+  x[5] = zm;
+  x[6] = zp;
+  if (mom) {  // momentum slots hold velocities
+#pragma unroll
+    for (int p = 0; p < 7; p++) x[p] *= (T)cf.dn[p];
   }
-  bme_terms(acc, n, q, P, W);
+  return advect7(x, cf.w);
+}
+
+// Waves per SIMD the register budget aims at (the stars / DM tiles take
+// 67 KB of LDS per workgroup in FP64, which allows two workgroups per CU).
+template <int C>
+constexpr int lag_waves() {
+  return C == COMP_GAS ? 3 : 2;
 }
 
 template <int C, typename T>
-__global__ void __launch_bounds__(kBlock) k_lagrangian(const RunDev<T>* __restrict__ runs,
+__global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const RunDev<T>* __restrict__ runs,
                                                        const WorkItem* __restrict__ work, unsigned nwork,
                                                        int parity, double* __restrict__ partials) {
+  using K = Comp<C>;
+  constexpr int NF = K::kNF;
+  constexpr int O0 = K::kFirst < GP_N ? K::kFirst - 1 : K::kFirst - 2;  // first "other" slot
+  __shared__ double s_dn[kLY][kLX];
+  __shared__ T s_f[NF][kLY][kLX];
+  __shared__ T s_v[2][kVTile];
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + kTX * ly;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const int run = uniform(work[w].run), item = uniform(work[w].tile);
     const RunDev<T>& R = runs[run];
-    const TileCell c = tile_cell(R, tile);
+    const Grid& g = R.g;
+    const int tx = item % R.ntx, ty = (item / R.ntx) % R.nty, kc = item / (R.ntx * R.nty);
+    const int i0 = tx * kTX, j0 = ty * kTY, k0 = kc * R.cz, k1 = min(k0 + R.cz, g.nz);
+    const int i = i0 + lx, j = j0 + ly;
+    const bool active = i < g.nx && j < g.ny;
+    const uint32_t nx = (uint32_t)g.nx;
+    const size_t nxy = (size_t)g.nx * g.ny;
+    const uint32_t xy_c = (uint32_t)ring_src(i, g.nx, g.bc[0]) + nx * (uint32_t)ring_src(j, g.ny, g.bc[1]);
+    // ring cell of this thread (threads tid < kRing): rows -1 and kTY, then
+    // columns -1 and kTX; (hr, hc) is its LDS position
+    const bool ring = tid < kRing;
+    int hr, hc;
+    if (tid < kLX) {
+      hr = 0;
+      hc = tid;
+    } else if (tid < 2 * kLX) {
+      hr = kLY - 1;
+      hc = tid - kLX;
+    } else if (tid < 2 * kLX + kTY) {
+      hr = 1 + tid - 2 * kLX;
+      hc = 0;
+    } else {
+      hr = 1 + min(tid - 2 * kLX - kTY, kTY - 1);
+      hc = kLX - 1;
+    }
+    const uint32_t xy_h =
+        (uint32_t)ring_src(i0 + hc - 1, g.nx, g.bc[0]) + nx * (uint32_t)ring_src(j0 + hr - 1, g.ny, g.bc[1]);
+    // corner values this thread stages per vertex plane: element e of the
+    // vertex tile is component e / (kVX kVY), row and column within it
+    const uint32_t vx = nx + 1;
+    const size_t vxy = (size_t)vx * (size_t)(g.ny + 1);
+    size_t voff[kVPer];
+#pragma unroll
+    for (int q = 0; q < kVPer; q++) {
+      const int e = min(tid + q * kBlock, kVTile - 1);
+      const int d = e / (kVX * kVY), rem = e % (kVX * kVY);
+      const int I = min(i0 + rem % kVX, g.nx), J = min(j0 + rem / kVX, g.ny);
+      voff[q] = (size_t)(K::kVel + d) * R.vstride + (size_t)I + (size_t)vx * (size_t)J;
+    }
+    const gptr<const T> vtx = as_global((const T*)R.vtx);
+    const gptr<const double> din = as_global((const double*)R.dens[parity][K::kDens]);
+    auto fin = [&](int f) { return as_global((const T*)R.tmp[O0 + f]); };
+    auto plane = [&](int k) -> size_t { return nxy * (size_t)bc_index(k, g.nz, g.bc[2]); };
+    auto stage_vertices = [&](int kv, T* dst) {
+      T v[kVPer];
+#pragma unroll
+      for (int q = 0; q < kVPer; q++)
+        if (tid + q * kBlock < kVTile) v[q] = vtx[vxy * (size_t)kv + voff[q]];
+#pragma unroll
+      for (int q = 0; q < kVPer; q++)
+        if (tid + q * kBlock < kVTile) dst[tid + q * kBlock] = v[q];
+    };
+
+    // prologue: plane k0 - 1 goes to the LDS centre slots (each plane's z-
+    // neighbours are read back from there), plane k0 to registers
+    double dc, dp;
+    T fc[NF], fp[NF];
+    {
+      const size_t zm = plane(k0 - 1), z0 = nxy * (size_t)k0;
+      s_dn[ly + 1][lx + 1] = ld_at(din, zm, xy_c);
+#pragma unroll
+      for (int f = 0; f < NF; f++) s_f[f][ly + 1][lx + 1] = ld_at(fin(f), zm, xy_c);
+      dc = ld_at(din, z0, xy_c);
+#pragma unroll
+      for (int f = 0; f < NF; f++) fc[f] = ld_at(fin(f), z0, xy_c);
+    }
+    stage_vertices(k0, s_v[k0 & 1]);
+
     Acc acc;
     acc_init(acc);
-    if (c.inside) {
-      if constexpr (C == COMP_GAS)
-        lag_gas_cell<T>(acc, R, parity, R.sc->dt, c.i, c.j, c.k);
-      else
-        lag_bme_cell<T>(acc, R, parity, R.sc->dt, c.i, c.j, c.k);
+    const double rd = R.sc->dt / g.h;
+    const T r = (T)rd;
+    for (int k = k0; k < k1; k++) {
+      const size_t zk = nxy * (size_t)k, zp = plane(k + 1);
+      // the previous centres become the z- neighbours (each thread reads back
+      // its own slot); this plane's ring and centres go into LDS, the next
+      // vertex plane too, and the next plane of the column (z+ neighbours)
+      // into registers
+      const double dm = s_dn[ly + 1][lx + 1];
+      T fm[NF];
+#pragma unroll
+      for (int f = 0; f < NF; f++) fm[f] = s_f[f][ly + 1][lx + 1];
+      if (ring) {
+        s_dn[hr][hc] = ld_at(din, zk, xy_h);
+#pragma unroll
+        for (int f = 0; f < NF; f++) s_f[f][hr][hc] = ld_at(fin(f), zk, xy_h);
+      }
+      s_dn[ly + 1][lx + 1] = dc;
+#pragma unroll
+      for (int f = 0; f < NF; f++) s_f[f][ly + 1][lx + 1] = fc[f];
+      stage_vertices(k + 1, s_v[(k + 1) & 1]);
+      dp = ld_at(din, zp, xy_c);
+#pragma unroll
+      for (int f = 0; f < NF; f++) fp[f] = ld_at(fin(f), zp, xy_c);
+      __syncthreads();
+
+      if (active) {
+        CellFlux<T> cf;
+        // A+ / A- of the six faces from the corners in vertex planes k, k+1
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+          T pos[2] = {T(0), T(0)}, neg[2] = {T(0), T(0)};
+#pragma unroll
+          for (int s = 0; s < 8; s++) {
+            const int sx = s & 1, sy = (s >> 1) & 1, sz = (s >> 2) & 1;
+            const T v = s_v[(k + sz) & 1][d * kVX * kVY + (ly + sy) * kVX + lx + sx];
+            const int side = d == 0 ? sx : (d == 1 ? sy : sz);
+            pos[side] += fmax(v, T(0));
+            neg[side] += fmin(v, T(0));
+          }
+#pragma unroll
+          for (int side = 0; side < 2; side++) {
+            cf.ap[d][side] = pos[side] * T(0.25);
+            cf.am[d][side] = neg[side] * T(0.25);
+          }
+        }
+        cf.dn[0] = dc;
+        cf.dn[1] = s_dn[ly + 1][lx];
+        cf.dn[2] = s_dn[ly + 1][lx + 2];
+        cf.dn[3] = s_dn[ly][lx + 1];
+        cf.dn[4] = s_dn[ly + 2][lx + 1];
+        cf.dn[5] = dm;
+        cf.dn[6] = dp;
+        double out;
+        const double dnew = advect_density(cf.dn, cf.ap, cf.am, rd, g, i, j, k, out);
+        cf.w = flux_weights(cf.ap, cf.am, r);
+        const uint32_t xy = (uint32_t)i + nx * (uint32_t)j;
+        if constexpr (C == COMP_GAS) {
+          T nv[NF];
+#pragma unroll
+          for (int f = 0; f < NF; f++) nv[f] = field_update<T, NF>(s_f, f, lx, ly, fm[f], fp[f], cf, f < 3);
+          gas_finish(acc, R, parity, zk, xy, dnew, nv, out);
+        } else {
+          // momenta first (the thermal tensor needs them), then each stress /
+          // energy pair is finished and stored before the next is formed
+          T q[3];
+#pragma unroll
+          for (int d = 0; d < 3; d++) q[d] = field_update<T, NF>(s_f, d, lx, ly, fm[d], fp[d], cf, true);
+          bme_stream(acc, R, parity, zk, xy, dnew, q, out, [&](int m, T& P, T& W) {
+            P = field_update<T, NF>(s_f, 3 + m, lx, ly, fm[3 + m], fp[3 + m], cf, false);
+            W = field_update<T, NF>(s_f, 9 + m, lx, ly, fm[9 + m], fp[9 + m], cf, false);
+          });
+        }
+      }
+      __syncthreads();  // LDS tiles are rewritten for the next plane
+      dc = dp;
+#pragma unroll
+      for (int f = 0; f < NF; f++) fc[f] = fp[f];
     }
-    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + tile) * kNP + C * kNS);
+    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + item) * kNP + C * kNS);
   }
 }
 
 // Diagnostics terms of one cell of a state that has not been advanced.
 template <typename T>
-__device__ __forceinline__ void init_cell(Acc& ga, Acc& ba, const RunDev<T>& R, int parity, int i, int j, int k) {
-  const Stencil s = make_stencil(R.g, i, j, k, false);
-  const size_t z = s.z[1];
-  const uint32_t xy = s.xy[0];
+__device__ __forceinline__ void init_cell(Acc& ga, Acc& ba, const RunDev<T>& R, int parity, size_t z, uint32_t xy) {
   auto f = [&](int field) { return ld_at(as_global((const T*)R.cur[oidx(field)]), z, xy); };
   const double rho = ld_at(as_global((const double*)R.dens[parity][0]), z, xy);
   const double n = ld_at(as_global((const double*)R.dens[parity][1]), z, xy);
@@ -473,20 +605,28 @@ __device__ __forceinline__ void init_cell(Acc& ga, Acc& ba, const RunDev<T>& R, 
   bme_terms(ba, n, q, P, W);
 }
 
+// Partial rows of a state that has not been advanced, over the same column
+// items (and rows) as the Lagrangian kernels.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_init_partials(const RunDev<T>* __restrict__ runs,
                                                           const WorkItem* __restrict__ work, unsigned nwork,
                                                           int parity, double* __restrict__ partials) {
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const int run = uniform(work[w].run), item = uniform(work[w].tile);
     const RunDev<T>& R = runs[run];
-    const TileCell c = tile_cell(R, tile);
+    const Grid& g = R.g;
+    const int tx = item % R.ntx, ty = (item / R.ntx) % R.nty, kc = item / (R.ntx * R.nty);
+    const int i = tx * kTX + (int)threadIdx.x, j = ty * kTY + (int)threadIdx.y;
+    const int k0 = kc * R.cz, k1 = min(k0 + R.cz, g.nz);
     Acc ga, ba;
     acc_init(ga);
     acc_init(ba);
-    if (c.inside) init_cell<T>(ga, ba, R, parity, c.i, c.j, c.k);
-    const gptr<double> row = as_global(partials) + ((size_t)R.row0 + tile) * kNP;
+    if (i < g.nx && j < g.ny) {
+      const uint32_t xy = (uint32_t)i + (uint32_t)g.nx * (uint32_t)j;
+      for (int k = k0; k < k1; k++) init_cell<T>(ga, ba, R, parity, (size_t)g.nx * g.ny * k, xy);
+    }
+    const gptr<double> row = as_global(partials) + ((size_t)R.row0 + item) * kNP;
     block_reduce_store(ga, row + kGasSlots);
     block_reduce_store(ba, row + kBmeSlots);
   }
