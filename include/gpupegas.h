@@ -72,7 +72,7 @@ enum { GP_STAGE_EUL = 0, GP_STAGE_LAG = 1, GP_STAGE_POISSON = 2, GP_STAGE_FINALI
  * one kernel per component: the gas (rho, m, E, e) and the stars / dark
  * matter (n, q, Pi, W), which those stages never couple. */
 enum {
-  GP_K_EUL_GAS = 0, GP_K_EUL_BME, GP_K_VERTEX, GP_K_LAG_GAS, GP_K_LAG_BME, GP_K_REDUCE, GP_K_FFT_X_FWD,
+  GP_K_EUL_GAS = 0, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME, GP_K_REDUCE, GP_K_FFT_X_FWD,
   GP_K_FFT_Y_FWD, GP_K_FFT_Z, GP_K_FFT_Y_INV, GP_K_FFT_X_INV, GP_K_FINALIZE, GP_NKERNELS
 };
 
@@ -161,7 +161,7 @@ gp_status gp_time_kernels(gp_sim *sim, int32_t nsteps, double *ms, int32_t max);
 gp_status gp_use_graph(gp_sim *sim, int32_t enable);
 
 /* Persistent grid size (workgroups) of a per-cell kernel (GP_K_EUL_GAS,
- * GP_K_EUL_BME, GP_K_VERTEX, GP_K_LAG_GAS or GP_K_LAG_BME).  By default the first step times a few
+ * GP_K_EUL_BME, GP_K_LAG_GAS or GP_K_LAG_BME).  By default the first step times a few
  * candidates and keeps the fastest; gp_set_launch fixes the size instead
  * (0 = one workgroup per tile) and disables that tuning.  Results never
  * depend on the grid size. */

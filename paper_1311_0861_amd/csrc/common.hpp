@@ -97,8 +97,6 @@ struct RunDev {
   double* dens[2][2];  // [parity][rho, n]
   T* cur[kNO];
   T* tmp[kNO];
-  T* vtx;              // corner velocities, 6 components of vstride each
-  size_t vstride;
   T* phi;
   DevScalars* sc;
   unsigned row0;       // first row of this run in the partial-sum table

@@ -36,8 +36,8 @@ using namespace gp;
 
 namespace {
 
-constexpr int kTunedKernels = 5;  // the per-cell kernels
-const int kTunedIds[kTunedKernels] = {GP_K_EUL_GAS, GP_K_EUL_BME, GP_K_VERTEX, GP_K_LAG_GAS, GP_K_LAG_BME};
+constexpr int kTunedKernels = 4;  // the per-cell kernels
+const int kTunedIds[kTunedKernels] = {GP_K_EUL_GAS, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME};
 
 struct RunHost {
   gp_config cfg{};
@@ -46,12 +46,10 @@ struct RunHost {
   double* dens[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   void* cur[kNO] = {};
   void* tmp[kNO] = {};
-  void* vtx = nullptr;
-  size_t vstride = 0;
   void* phi = nullptr;
   DevScalars* sc = nullptr;
   gp_diag* ring = nullptr;
-  unsigned row0 = 0, ntiles = 0, nvtiles = 0, ncols = 0;
+  unsigned row0 = 0, ntiles = 0, ncols = 0;
   int ntx = 0, nty = 0, cz = 0, nkc = 0;
   int cls = 0, slot = 0;  // size class and position inside it
 };
@@ -94,8 +92,6 @@ struct gp_batch {
   unsigned ncell_work = 0;
   WorkItem* col_work = nullptr;   // tile columns by z chunk (Lagrangian, partial rows)
   unsigned ncol_work = 0;
-  WorkItem* vtx_work = nullptr;
-  unsigned nvtx_work = 0;
   double* partials = nullptr;
   RedItem* red_items = nullptr;
   int nred = 0;
@@ -255,7 +251,6 @@ void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
     case GP_K_EUL_BME:
       launch_eulerian<T>(runs, b->cell_work, b->ncell_work, b->parity, COMP_BME, nblocks, b->st);
       break;
-    case GP_K_VERTEX: launch_vertex<T>(runs, b->vtx_work, b->nvtx_work, nblocks, b->st); break;
     case GP_K_LAG_GAS:
       launch_lagrangian<T>(runs, b->col_work, b->ncol_work, b->parity, b->partials, COMP_GAS, nblocks, b->st);
       break;
@@ -266,7 +261,6 @@ void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
 }
 
 unsigned work_count(const gp_batch* b, int k) {
-  if (k == GP_K_VERTEX) return b->nvtx_work;
   if (k == GP_K_LAG_GAS || k == GP_K_LAG_BME) return b->ncol_work;
   return b->ncell_work;
 }
@@ -319,7 +313,6 @@ void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
       cell(GP_K_EUL_BME);
       break;
     case GP_STAGE_LAG:
-      cell(GP_K_VERTEX);
       cell(GP_K_LAG_GAS);
       cell(GP_K_LAG_BME);
       if (allow_tune && b->tune) b->tuned = true;
@@ -441,8 +434,6 @@ RunDev<T> make_rundev(const RunHost& r) {
     d.cur[o] = static_cast<T*>(r.cur[o]);
     d.tmp[o] = static_cast<T*>(r.tmp[o]);
   }
-  d.vtx = static_cast<T*>(r.vtx);
-  d.vstride = r.vstride;
   d.phi = static_cast<T*>(r.phi);
   d.sc = r.sc;
   d.row0 = r.row0;
@@ -497,7 +488,6 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     R.cz = (int)std::max<long>(4, std::min<long>(16, (long)R.ntx * R.nty * R.g.nz / 2048));
     R.nkc = (R.g.nz + R.cz - 1) / R.cz;
     R.ncols = (unsigned)(R.ntx * R.nty * R.nkc);
-    R.nvtiles = (unsigned)(((size_t)(R.g.nx + 1) * (R.g.ny + 1) * (R.g.nz + 1) + kBlock - 1) / kBlock);
     R.row0 = row;
     row += R.ncols;
     const auto key = std::make_tuple(R.g.nx, R.g.ny, R.g.nz, R.g.h, R.ph.G);
@@ -528,8 +518,6 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
       R.cur[o] = dalloc(b, nc * es, &st);
       R.tmp[o] = dalloc(b, nc * es, &st);
     }
-    R.vstride = (((size_t)(R.g.nx + 1) * (R.g.ny + 1) * (R.g.nz + 1)) + 63) / 64 * 64;
-    R.vtx = dalloc(b, 6 * R.vstride * es, &st);
     R.sc = static_cast<DevScalars*>(dalloc(b, sizeof(DevScalars), &st));
     R.ring = static_cast<gp_diag*>(dalloc(b, sizeof(gp_diag) * kDiagCap, &st));
   }
@@ -586,7 +574,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   b->epot = static_cast<double*>(dalloc(b, std::max(1u, eoff) * sizeof(double), &st));
 
   // work lists, partial rows, reduction items, finalize descriptors
-  std::vector<WorkItem> cw, vw, colw;
+  std::vector<WorkItem> cw, colw;
   std::vector<RedItem> items;
   std::vector<FinDesc> fins;
   unsigned soff = 0;
@@ -604,7 +592,6 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
       for (int ty = 0; ty < R.nty; ty++)
         for (int tx = 0; tx < R.ntx; tx++)
           for (int k = z0; k < std::min(z0 + cz, R.g.nz); k++) cw.push_back({r, tx + R.ntx * (ty + R.nty * k)});
-    for (unsigned t = 0; t < R.nvtiles; t++) vw.push_back({r, (int)t});
     // column items, x fastest, then y, then the z chunk: the columns whose
     // rings overlap run side by side
     for (unsigned c = 0; c < R.ncols; c++) colw.push_back({r, (int)c});
@@ -630,11 +617,9 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   }
   b->ncell_work = (unsigned)cw.size();
   b->ncol_work = (unsigned)colw.size();
-  b->nvtx_work = (unsigned)vw.size();
   b->nred = (int)items.size();
   b->cell_work = static_cast<WorkItem*>(dalloc(b, cw.size() * sizeof(WorkItem), &st));
   b->col_work = static_cast<WorkItem*>(dalloc(b, colw.size() * sizeof(WorkItem), &st));
-  b->vtx_work = static_cast<WorkItem*>(dalloc(b, vw.size() * sizeof(WorkItem), &st));
   b->partials = static_cast<double*>(dalloc(b, (size_t)row * kNP * sizeof(double), &st));
   b->red_items = static_cast<RedItem*>(dalloc(b, items.size() * sizeof(RedItem), &st));
   b->scratch = static_cast<double*>(dalloc(b, (size_t)soff * kNP * sizeof(double), &st));
@@ -651,7 +636,6 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   };
   put(b->cell_work, cw.data(), cw.size() * sizeof(WorkItem));
   put(b->col_work, colw.data(), colw.size() * sizeof(WorkItem));
-  put(b->vtx_work, vw.data(), vw.size() * sizeof(WorkItem));
   put(b->red_items, items.data(), items.size() * sizeof(RedItem));
   put(b->fin, fins.data(), fins.size() * sizeof(FinDesc));
   if (b->prec == GP_FP64) {
@@ -710,7 +694,6 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   b->blocks[GP_K_EUL_BME] = b->ncell_work;
   b->blocks[GP_K_LAG_GAS] = b->ncol_work;
   b->blocks[GP_K_LAG_BME] = b->ncol_work;
-  b->blocks[GP_K_VERTEX] = b->nvtx_work;
   return GP_OK;
 }
 
@@ -877,30 +860,22 @@ double fft_bytes_per_cell(const gp_batch* b, int k) {
 
 double engine_bytes_per_cell(const gp_batch* b, int32_t kernel) {
   const double es = (double)esize(b->prec);
-  double cells = 0.0, vr = 0.0;
-  for (const RunHost& R : b->runs) {
-    cells += (double)R.g.ncell;
-    vr += (double)(R.g.nx + 1) * (R.g.ny + 1) * (R.g.nz + 1);
-  }
-  vr /= cells;  // vertices per cell
   // Eulerian: read the density, the component's fields and Phi; write its fields
   const double eul_gas = 8.0 + 5 * es + es + 5 * es;
   const double eul_bme = 8.0 + 15 * es + es + 15 * es;
-  const double vtx = 6 * es + 6 * es * vr;  // read 6 velocities; write 6 per vertex
-  // Lagrangian: read the density, the post-Eulerian fields and 3 corner
-  // velocity components; write the density and the fields
-  const double lag_gas = 8.0 + 5 * es + 3 * es * vr + 8.0 + 5 * es;
-  const double lag_bme = 8.0 + 15 * es + 3 * es * vr + 8.0 + 15 * es;
+  // Lagrangian: read the density and the post-Eulerian fields (the corner
+  // velocities are formed on chip); write the density and the fields
+  const double lag_gas = 8.0 + 5 * es + 8.0 + 5 * es;
+  const double lag_bme = 8.0 + 15 * es + 8.0 + 15 * es;
   switch (kernel) {
     case GP_K_EUL_GAS: return eul_gas;
     case GP_K_EUL_BME: return eul_bme;
-    case GP_K_VERTEX: return vtx;
     case GP_K_LAG_GAS: return lag_gas;
     case GP_K_LAG_BME: return lag_bme;
     case GP_K_REDUCE:
     case GP_K_FINALIZE: return 0.0;
     case -1: {
-      double t = eul_gas + eul_bme + vtx + lag_gas + lag_bme;
+      double t = eul_gas + eul_bme + lag_gas + lag_bme;
       for (int k = GP_K_FFT_X_FWD; k <= GP_K_FFT_X_INV; k++) t += fft_bytes_per_cell(b, k);
       return t;
     }

@@ -14,9 +14,6 @@ void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork
                      unsigned nblocks, hipStream_t st);
 
 // ---- Lagrangian stage + energy balance + diagnostics partials -------------
-// Corner velocities from the post-Eulerian velocities (vertex work list).
-template <typename T>
-void launch_vertex(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, unsigned nblocks, hipStream_t st);
 // New state of component comp into cur / dens[parity ^ 1], and that
 // component's kNS slots of the partial row of each tile (row R.row0 + tile).
 template <typename T>

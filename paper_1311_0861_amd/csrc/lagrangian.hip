@@ -4,8 +4,9 @@
 //     F on a face = (1/4) sum over its 4 corners of v_d f^+, f^+ the upwind
 //     cell value for that corner's velocity; a corner velocity is the mean of
 //     the 8 cells sharing the vertex (post-Eulerian m/rho for the gas, q/n for
-//     the stars), computed once per vertex by k_vertex; the flux is written per
-//     cell as A+ f_c + A- f_{c+e_d};
+//     the stars), formed on chip from the velocity tiles by one fixed
+//     expression, so every cell sharing a vertex sees the same bits; the flux
+//     is written per cell as A+ f_c + A- f_{c+e_d};
 //   - correctness integrals kappa (Sec. 2.4) measured on the advected state;
 //   - energy balance: e := E - |m|^2/(2 rho) where that exceeds eta E, and
 //     each diagonal stress Pi_dd := W_dd - q_d^2/n where that exceeds eta W_dd;
@@ -143,57 +144,6 @@ __device__ __forceinline__ void bme_terms(Acc& a, double n, const T q[3], const 
   a.err |= err;
 }
 
-// Corner velocities: vertex (I, J, K), I in [0, nx], sits between cells I-1
-// and I on x (likewise y, z); its velocity is the mean of the 8 cells sharing
-// it, cells outside the grid taken by the hydrodynamic boundary rule.  The
-// post-Eulerian momentum slots hold velocities already.
-template <typename T>
-__device__ __forceinline__ void vertex_point(const Fields<T>& eul, gptr<T> vtx, const Grid& g,
-                                             size_t vstride, int I, int J, int K) {
-  const size_t nx = g.nx, nxy = (size_t)g.nx * g.ny;
-  const size_t xi[2] = {(size_t)bc_index(I - 1, g.nx, g.bc[0]), (size_t)bc_index(I, g.nx, g.bc[0])};
-  const size_t yj[2] = {nx * bc_index(J - 1, g.ny, g.bc[1]), nx * bc_index(J, g.ny, g.bc[1])};
-  const size_t zk[2] = {nxy * bc_index(K - 1, g.nz, g.bc[2]), nxy * bc_index(K, g.nz, g.bc[2])};
-  T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-  for (int c3 = 0; c3 < 2; c3++)
-#pragma unroll
-    for (int b3 = 0; b3 < 2; b3++)
-#pragma unroll
-      for (int a3 = 0; a3 < 2; a3++) {
-        const size_t cc = xi[a3] + yj[b3] + zk[c3];
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-          acc[d] += eul.o[oidx(GP_MX + d)][cc];
-          acc[3 + d] += eul.o[oidx(GP_QX + d)][cc];
-        }
-      }
-  const size_t w = I + (size_t)(g.nx + 1) * (J + (size_t)(g.ny + 1) * K);
-#pragma unroll
-  for (int v = 0; v < 6; v++) vtx[v * vstride + w] = acc[v] * T(0.125);
-}
-
-// Vertices are processed in flat index order, kBlock per work item, so every
-// wave writes 64 consecutive vertices whatever the (nx+1) row length.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_vertex(const RunDev<T>* __restrict__ runs,
-                                                   const WorkItem* __restrict__ work, unsigned nwork) {
-  const WorkRange wr = xcd_range(nwork);
-  const unsigned tid = threadIdx.x + kTX * threadIdx.y;
-  for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
-    const RunDev<T>& R = runs[run];
-    const unsigned vx = R.g.nx + 1, vy = R.g.ny + 1;
-    const size_t v = (size_t)tile * kBlock + tid;
-    if (v < (size_t)vx * vy * (R.g.nz + 1)) {
-      const unsigned I = (unsigned)(v % vx);
-      const size_t JK = v / vx;
-      const unsigned J = (unsigned)(JK % vy), K = (unsigned)(JK / vy);
-      vertex_point<T>(fields_eul(R), as_global(R.vtx), R.g, R.vstride, (int)I, (int)J, (int)K);
-    }
-  }
-}
-
 // ---- Lagrangian flux update -------------------------------------------------
 
 // Face flux of an FP64 density; both cells sharing the face evaluate exactly
@@ -259,11 +209,14 @@ __device__ __forceinline__ T advect7(const T x[7], const Weights<T>& w) {
 //
 // A workgroup owns a 64 x 4 tile of cells and walks a chunk of z planes.  For
 // plane k the tile of every advected field, with a one-cell ring of x / y
-// neighbours, sits in LDS; the z neighbours (planes k-1 and k+1) stay in
-// registers from one plane to the next, and the corner velocities of vertex
-// planes k and k+1 sit in a double-buffered LDS tile.  Each plane of a field
-// is thus read from memory once per tile plus its ring, in coalesced rows,
-// instead of 7 times through the cache hierarchy.
+// neighbours, sits in LDS; the z+ neighbours come into registers one plane
+// ahead and the z- ones are read back from the LDS centres of the previous
+// plane.  The velocity tiles of planes k and k+1 (with rings) are both held,
+// which is what the corner velocities of vertex plane k+1 need; the corners
+// of vertex planes k and k+1 sit in a double-buffered LDS tile.  Each plane
+// of a field is thus read from memory once per tile plus its ring, in
+// coalesced rows, instead of 7 times through the cache hierarchy, and the
+// corner velocities never go to memory.
 
 constexpr int kLX = kTX + 2, kLY = kTY + 2;  // plane tile with its neighbour ring
 constexpr int kVX = kTX + 1, kVY = kTY + 1;  // vertex tile of a cell tile
@@ -385,23 +338,19 @@ struct CellFlux {
   double dn[7];
 };
 
-// The 7 post-Eulerian values of field f at the centre cell (x / y ring and
-// centre from the LDS tile, z neighbours from registers).
-template <typename T, int NF>
-__device__ __forceinline__ T field_update(const T (&tile)[NF][kLY][kLX], int f, int lx, int ly, T zm, T zp,
-                                          const CellFlux<T>& cf, bool mom) {
+// Flux update of the field in tile slot t from its 7 post-Eulerian values
+// (x / y ring and centre from the LDS tile, z neighbours from registers).
+template <typename T, int NT>
+__device__ __forceinline__ T field_update(const T (&tile)[NT][kLY][kLX], int t, int lx, int ly, T zm, T zp,
+                                          const CellFlux<T>& cf) {
   T x[7];
-  x[0] = tile[f][ly + 1][lx + 1];
-  x[1] = tile[f][ly + 1][lx];
-  x[2] = tile[f][ly + 1][lx + 2];
-  x[3] = tile[f][ly][lx + 1];
-  x[4] = tile[f][ly + 2][lx + 1];
+  x[0] = tile[t][ly + 1][lx + 1];
+  x[1] = tile[t][ly + 1][lx];
+  x[2] = tile[t][ly + 1][lx + 2];
+  x[3] = tile[t][ly][lx + 1];
+  x[4] = tile[t][ly + 2][lx + 1];
   x[5] = zm;
   x[6] = zp;
-  if (mom) {  // momentum slots hold velocities
-#pragma unroll
-    for (int p = 0; p < 7; p++) x[p] *= (T)cf.dn[p];
-  }
   return advect7(x, cf.w);
 }
 
@@ -414,14 +363,16 @@ constexpr int lag_waves() {
 
 template <int C, typename T>
 __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const RunDev<T>* __restrict__ runs,
-                                                       const WorkItem* __restrict__ work, unsigned nwork,
-                                                       int parity, double* __restrict__ partials) {
+                                                                        const WorkItem* __restrict__ work,
+                                                                        unsigned nwork, int parity,
+                                                                        double* __restrict__ partials) {
   using K = Comp<C>;
   constexpr int NF = K::kNF;
   constexpr int O0 = K::kFirst < GP_N ? K::kFirst - 1 : K::kFirst - 2;  // first "other" slot
   __shared__ double s_dn[kLY][kLX];
-  __shared__ T s_f[NF][kLY][kLX];
-  __shared__ T s_v[2][kVTile];
+  __shared__ T s_f[NF - 3][kLY][kLX];  // plane k of the fields after the velocities
+  __shared__ T s_u[2][3][kLY][kLX];    // velocity tiles of planes k and k+1, alternating
+  __shared__ T s_v[2][kVTile];        // corner velocities of vertex planes k and k+1
   const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + kTX * ly;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
@@ -454,46 +405,72 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
     }
     const uint32_t xy_h =
         (uint32_t)ring_src(i0 + hc - 1, g.nx, g.bc[0]) + nx * (uint32_t)ring_src(j0 + hr - 1, g.ny, g.bc[1]);
-    // corner values this thread stages per vertex plane: element e of the
-    // vertex tile is component e / (kVX kVY), row and column within it
-    const uint32_t vx = nx + 1;
-    const size_t vxy = (size_t)vx * (size_t)(g.ny + 1);
-    size_t voff[kVPer];
+    const gptr<const double> din = as_global((const double*)R.dens[parity][K::kDens]);
+    auto fin = [&](int f) { return as_global((const T*)R.tmp[O0 + f]); };
+    auto plane = [&](int k) -> size_t { return nxy * (size_t)bc_index(k, g.nz, g.bc[2]); };
+
+    // Corner velocities.  Vertex (I, J, K) is the mean of the 8 cells I-1..I,
+    // J-1..J, K-1..K (boundary rule outside the grid), summed z-major, then y,
+    // then x; the cells come from the velocity tiles (with their rings) of
+    // planes K-1 and K.  Entry e of the vertex tile (component e / (kVX kVY),
+    // vertex row and column within it) is formed by thread e mod kBlock; vo[]
+    // is the tile offset of its lower-left cell.
+    int vo[kVPer];
 #pragma unroll
     for (int q = 0; q < kVPer; q++) {
       const int e = min(tid + q * kBlock, kVTile - 1);
       const int d = e / (kVX * kVY), rem = e % (kVX * kVY);
-      const int I = min(i0 + rem % kVX, g.nx), J = min(j0 + rem / kVX, g.ny);
-      voff[q] = (size_t)(K::kVel + d) * R.vstride + (size_t)I + (size_t)vx * (size_t)J;
+      vo[q] = (d * kLY + rem / kVX) * kLX + rem % kVX;
     }
-    const gptr<const T> vtx = as_global((const T*)R.vtx);
-    const gptr<const double> din = as_global((const double*)R.dens[parity][K::kDens]);
-    auto fin = [&](int f) { return as_global((const T*)R.tmp[O0 + f]); };
-    auto plane = [&](int k) -> size_t { return nxy * (size_t)bc_index(k, g.nz, g.bc[2]); };
-    auto stage_vertices = [&](int kv, T* dst) {
-      T v[kVPer];
+    auto corner_plane = [&](const T (&lo)[3][kLY][kLX], const T (&hi)[3][kLY][kLX], T* dst) {
+      const T* a = &lo[0][0][0];
+      const T* b = &hi[0][0][0];
 #pragma unroll
-      for (int q = 0; q < kVPer; q++)
-        if (tid + q * kBlock < kVTile) v[q] = vtx[vxy * (size_t)kv + voff[q]];
+      for (int q = 0; q < kVPer; q++) {
+        const int o = vo[q];
+        T v = a[o];
+        v += a[o + 1];
+        v += a[o + kLX];
+        v += a[o + kLX + 1];
+        v += b[o];
+        v += b[o + 1];
+        v += b[o + kLX];
+        v += b[o + kLX + 1];
+        if (tid + q * kBlock < kVTile) dst[tid + q * kBlock] = v * T(0.125);
+      }
+    };
+    // centre and ring of plane z of the three velocities into tile u
+    auto stage_velocity = [&](size_t z, T (&u)[3][kLY][kLX], const T ctr[3]) {
 #pragma unroll
-      for (int q = 0; q < kVPer; q++)
-        if (tid + q * kBlock < kVTile) dst[tid + q * kBlock] = v[q];
+      for (int d = 0; d < 3; d++) u[d][ly + 1][lx + 1] = ctr[d];
+      if (ring) {
+#pragma unroll
+        for (int d = 0; d < 3; d++) u[d][hr][hc] = ld_at(fin(d), z, xy_h);
+      }
     };
 
     // prologue: plane k0 - 1 goes to the LDS centre slots (each plane's z-
-    // neighbours are read back from there), plane k0 to registers
+    // neighbours are read back from there) and to the velocity tile
+    // s_u[(k0 + 1) & 1]; plane k0 goes to registers and to s_u[k0 & 1]; the
+    // two give the corner velocities of vertex plane k0
     double dc, dp;
     T fc[NF], fp[NF];
     {
       const size_t zm = plane(k0 - 1), z0 = nxy * (size_t)k0;
+      T um[3];
       s_dn[ly + 1][lx + 1] = ld_at(din, zm, xy_c);
 #pragma unroll
-      for (int f = 0; f < NF; f++) s_f[f][ly + 1][lx + 1] = ld_at(fin(f), zm, xy_c);
+      for (int f = 0; f < 3; f++) um[f] = ld_at(fin(f), zm, xy_c);
+#pragma unroll
+      for (int f = 3; f < NF; f++) s_f[f - 3][ly + 1][lx + 1] = ld_at(fin(f), zm, xy_c);
+      stage_velocity(zm, s_u[(k0 + 1) & 1], um);
       dc = ld_at(din, z0, xy_c);
 #pragma unroll
       for (int f = 0; f < NF; f++) fc[f] = ld_at(fin(f), z0, xy_c);
+      stage_velocity(z0, s_u[k0 & 1], fc);
+      __syncthreads();
+      corner_plane(s_u[(k0 + 1) & 1], s_u[k0 & 1], s_v[k0 & 1]);
     }
-    stage_vertices(k0, s_v[k0 & 1]);
 
     Acc acc;
     acc_init(acc);
@@ -501,26 +478,33 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
     const T r = (T)rd;
     for (int k = k0; k < k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane(k + 1);
+      const int cu = k & 1, nu = cu ^ 1;  // velocity tiles of planes k and k+1
       // the previous centres become the z- neighbours (each thread reads back
-      // its own slot); this plane's ring and centres go into LDS, the next
-      // vertex plane too, and the next plane of the column (z+ neighbours)
-      // into registers
+      // its own slot; the velocities from the tile of plane k-1); this
+      // plane's ring and centres go into LDS; the next plane of the column
+      // (z+ neighbours) goes into registers, and its velocities with their
+      // ring into the other velocity tile
       const double dm = s_dn[ly + 1][lx + 1];
       T fm[NF];
 #pragma unroll
-      for (int f = 0; f < NF; f++) fm[f] = s_f[f][ly + 1][lx + 1];
+      for (int f = 0; f < 3; f++) fm[f] = s_u[nu][f][ly + 1][lx + 1];
+#pragma unroll
+      for (int f = 3; f < NF; f++) fm[f] = s_f[f - 3][ly + 1][lx + 1];
+      __syncthreads();  // every thread is done with the previous plane's tiles
       if (ring) {
         s_dn[hr][hc] = ld_at(din, zk, xy_h);
 #pragma unroll
-        for (int f = 0; f < NF; f++) s_f[f][hr][hc] = ld_at(fin(f), zk, xy_h);
+        for (int f = 3; f < NF; f++) s_f[f - 3][hr][hc] = ld_at(fin(f), zk, xy_h);
       }
       s_dn[ly + 1][lx + 1] = dc;
 #pragma unroll
-      for (int f = 0; f < NF; f++) s_f[f][ly + 1][lx + 1] = fc[f];
-      stage_vertices(k + 1, s_v[(k + 1) & 1]);
+      for (int f = 3; f < NF; f++) s_f[f - 3][ly + 1][lx + 1] = fc[f];
       dp = ld_at(din, zp, xy_c);
 #pragma unroll
       for (int f = 0; f < NF; f++) fp[f] = ld_at(fin(f), zp, xy_c);
+      stage_velocity(zp, s_u[nu], fp);
+      __syncthreads();
+      corner_plane(s_u[cu], s_u[nu], s_v[(k + 1) & 1]);
       __syncthreads();
 
       if (active) {
@@ -554,24 +538,39 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
         const double dnew = advect_density(cf.dn, cf.ap, cf.am, rd, g, i, j, k, out);
         cf.w = flux_weights(cf.ap, cf.am, r);
         const uint32_t xy = (uint32_t)i + nx * (uint32_t)j;
+        // velocities: x / y neighbours from the velocity tile of plane k
+        auto vel_update = [&](int d) -> T {
+          T x[7];
+          x[0] = s_u[cu][d][ly + 1][lx + 1];
+          x[1] = s_u[cu][d][ly + 1][lx];
+          x[2] = s_u[cu][d][ly + 1][lx + 2];
+          x[3] = s_u[cu][d][ly][lx + 1];
+          x[4] = s_u[cu][d][ly + 2][lx + 1];
+          x[5] = fm[d];
+          x[6] = fp[d];
+#pragma unroll
+          for (int p = 0; p < 7; p++) x[p] *= (T)cf.dn[p];
+          return advect7(x, cf.w);
+        };
         if constexpr (C == COMP_GAS) {
           T nv[NF];
 #pragma unroll
-          for (int f = 0; f < NF; f++) nv[f] = field_update<T, NF>(s_f, f, lx, ly, fm[f], fp[f], cf, f < 3);
+          for (int d = 0; d < 3; d++) nv[d] = vel_update(d);
+#pragma unroll
+          for (int f = 3; f < NF; f++) nv[f] = field_update<T, NF - 3>(s_f, f - 3, lx, ly, fm[f], fp[f], cf);
           gas_finish(acc, R, parity, zk, xy, dnew, nv, out);
         } else {
           // momenta first (the thermal tensor needs them), then each stress /
           // energy pair is finished and stored before the next is formed
           T q[3];
 #pragma unroll
-          for (int d = 0; d < 3; d++) q[d] = field_update<T, NF>(s_f, d, lx, ly, fm[d], fp[d], cf, true);
+          for (int d = 0; d < 3; d++) q[d] = vel_update(d);
           bme_stream(acc, R, parity, zk, xy, dnew, q, out, [&](int m, T& P, T& W) {
-            P = field_update<T, NF>(s_f, 3 + m, lx, ly, fm[3 + m], fp[3 + m], cf, false);
-            W = field_update<T, NF>(s_f, 9 + m, lx, ly, fm[9 + m], fp[9 + m], cf, false);
+            P = field_update<T, NF - 3>(s_f, m, lx, ly, fm[3 + m], fp[3 + m], cf);
+            W = field_update<T, NF - 3>(s_f, 6 + m, lx, ly, fm[9 + m], fp[9 + m], cf);
           });
         }
       }
-      __syncthreads();  // LDS tiles are rewritten for the next plane
       dc = dp;
 #pragma unroll
       for (int f = 0; f < NF; f++) fc[f] = fp[f];
@@ -633,10 +632,6 @@ __global__ void __launch_bounds__(kBlock) k_init_partials(const RunDev<T>* __res
 }
 
 template <typename T>
-void launch_vertex(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, unsigned nblocks, hipStream_t st) {
-  k_vertex<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork);
-}
-template <typename T>
 void launch_lagrangian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, double* partials,
                        int comp, unsigned nblocks, hipStream_t st) {
   if (comp == COMP_GAS)
@@ -650,7 +645,6 @@ void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned 
   k_init_partials<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
 }
 #define GP_INSTANTIATE(T)                                                                                  \
-  template void launch_vertex<T>(const RunDev<T>*, const WorkItem*, unsigned, unsigned, hipStream_t);       \
   template void launch_lagrangian<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, int,        \
                                      unsigned, hipStream_t);                                                \
   template void launch_init_partials<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, unsigned, \

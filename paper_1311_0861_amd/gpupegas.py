@@ -25,9 +25,9 @@ FIELD_NAMES = [
     "Wxx", "Wxy", "Wxz", "Wyy", "Wyz", "Wzz",
 ]
 GP_PHI = 22
-KERNEL_NAMES = ["eul_gas", "eul_bme", "vertex", "lag_gas", "lag_bme", "reduce", "fft_x_fwd", "fft_y_fwd",
-                "fft_z_green", "fft_y_inv", "fft_x_inv", "finalize"]
-CELL_KERNELS = ["eul_gas", "eul_bme", "vertex", "lag_gas", "lag_bme"]  # persistent, launch size settable
+KERNEL_NAMES = ["eul_gas", "eul_bme", "lag_gas", "lag_bme", "reduce", "fft_x_fwd", "fft_y_fwd", "fft_z_green",
+                "fft_y_inv", "fft_x_inv", "finalize"]
+CELL_KERNELS = ["eul_gas", "eul_bme", "lag_gas", "lag_bme"]  # persistent, launch size settable
 
 
 class gp_config(ctypes.Structure):
