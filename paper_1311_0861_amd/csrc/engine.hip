@@ -36,6 +36,7 @@ using namespace gp;
 
 namespace {
 
+constexpr long kColItems = 512;   // target column items per run (Lagrangian)
 constexpr int kTunedKernels = 4;  // the per-cell kernels
 const int kTunedIds[kTunedKernels] = {GP_K_EUL_GAS, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME};
 
@@ -483,9 +484,10 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     R.nty = (R.g.ny + kTY - 1) / kTY;
     R.ntiles = (unsigned)(R.ntx * R.nty * R.g.nz);
     // Lagrangian column items: a tile column split into chunks of cz planes,
-    // as many as it takes to give the launch some 2048 items per run
-    // (chunks of 4 to 16 planes)
-    R.cz = (int)std::max<long>(4, std::min<long>(16, (long)R.ntx * R.nty * R.g.nz / 2048));
+    // about kColItems items per run (chunks of 4 to 32 planes).  Each chunk
+    // re-reads the planes just below and above it, so chunks are as long as
+    // the workgroups resident on the chip (2-3 per CU) allow.
+    R.cz = (int)std::max<long>(4, std::min<long>(32, (long)R.ntx * R.nty * R.g.nz / kColItems));
     R.nkc = (R.g.nz + R.cz - 1) / R.cz;
     R.ncols = (unsigned)(R.ntx * R.nty * R.nkc);
     R.row0 = row;
