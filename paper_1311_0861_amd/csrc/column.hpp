@@ -1,0 +1,77 @@
+// Tile-column geometry shared by the Eulerian and Lagrangian kernels.
+//
+// A column work item is a 64 x 4 tile of cells and a chunk of z planes; the
+// workgroup walks the planes in order.  For plane k it keeps the tile of each
+// field it needs, with a one-cell ring of x / y neighbours, in LDS (kLY x kLX
+// values, the tile at rows / columns 1..kTY / 1..kTX); z neighbours are held
+// in registers.  Each lane owns the cell of its (threadIdx.x, threadIdx.y);
+// the first kRing lanes of the workgroup also fetch one ring cell each.
+#pragma once
+
+#include "common.hpp"
+
+namespace gp {
+
+constexpr int kLX = kTX + 2, kLY = kTY + 2;  // plane tile with its neighbour ring
+constexpr int kRing = 2 * kLX + 2 * kTY;     // ring cells of a plane tile
+
+// Source cell of tile position x under a boundary rule: the rule itself on
+// the one-cell ring outside the grid (x = -1 or x = n); positions further out
+// (ragged edge tiles) are never read and take any valid cell.
+__device__ __forceinline__ int ring_src(int x, int n, int bc) {
+  if (x < 0 || x == n) return bc_index(x, n, bc);
+  return x < n ? x : n - 1;
+}
+
+struct Column {
+  int i0, j0, k0, k1;  // tile origin and plane range [k0, k1)
+  int i, j;            // this lane's cell
+  bool active;         // the cell is inside the grid
+  uint32_t xy_c;       // in-plane offset the lane stages for its own slot
+  bool ring;           // the lane also stages ring cell (hr, hc)
+  int hr, hc;          // LDS row / column of that ring cell
+  uint32_t xy_h;       // its in-plane offset
+};
+
+// Geometry of column item `item` of a run with ntx x nty tiles per plane and
+// chunks of cz planes.  periodic = true takes the periodic rule on x and y
+// (the potential) instead of the hydrodynamic one.
+__device__ __forceinline__ Column make_column(const Grid& g, int ntx, int nty, int cz, int item, bool periodic) {
+  Column c;
+  const int tx = item % ntx, ty = (item / ntx) % nty, kc = item / (ntx * nty);
+  c.i0 = tx * kTX;
+  c.j0 = ty * kTY;
+  c.k0 = kc * cz;
+  c.k1 = min(c.k0 + cz, g.nz);
+  c.i = c.i0 + (int)threadIdx.x;
+  c.j = c.j0 + (int)threadIdx.y;
+  c.active = c.i < g.nx && c.j < g.ny;
+  const int bx = periodic ? GP_BC_PERIODIC : g.bc[0], by = periodic ? GP_BC_PERIODIC : g.bc[1];
+  const uint32_t nx = (uint32_t)g.nx;
+  c.xy_c = (uint32_t)ring_src(c.i, g.nx, bx) + nx * (uint32_t)ring_src(c.j, g.ny, by);
+  // ring cells: rows -1 and kTY (kLX each), then columns -1 and kTX
+  const int tid = (int)threadIdx.x + kTX * (int)threadIdx.y;
+  c.ring = tid < kRing;
+  if (tid < kLX) {
+    c.hr = 0;
+    c.hc = tid;
+  } else if (tid < 2 * kLX) {
+    c.hr = kLY - 1;
+    c.hc = tid - kLX;
+  } else if (tid < 2 * kLX + kTY) {
+    c.hr = 1 + tid - 2 * kLX;
+    c.hc = 0;
+  } else {
+    c.hr = 1 + min(tid - 2 * kLX - kTY, kTY - 1);
+    c.hc = kLX - 1;
+  }
+  c.xy_h = (uint32_t)ring_src(c.i0 + c.hc - 1, g.nx, bx) + nx * (uint32_t)ring_src(c.j0 + c.hr - 1, g.ny, by);
+  return c;
+}
+
+// Element offset of plane k under the z boundary rule.
+__device__ __forceinline__ size_t plane_at(const Grid& g, int k, int bc) {
+  return (size_t)g.nx * (size_t)g.ny * (size_t)bc_index(k, g.nz, bc);
+}
+
+}  // namespace gp

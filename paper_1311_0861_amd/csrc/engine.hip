@@ -36,7 +36,7 @@ using namespace gp;
 
 namespace {
 
-constexpr long kColItems = 512;   // target column items per run (Lagrangian)
+constexpr long kColItems = 512;   // target column items per run
 constexpr int kTunedKernels = 4;  // the per-cell kernels
 const int kTunedIds[kTunedKernels] = {GP_K_EUL_GAS, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME};
 
@@ -50,7 +50,7 @@ struct RunHost {
   void* phi = nullptr;
   DevScalars* sc = nullptr;
   gp_diag* ring = nullptr;
-  unsigned row0 = 0, ntiles = 0, ncols = 0;
+  unsigned row0 = 0, ncols = 0;
   int ntx = 0, nty = 0, cz = 0, nkc = 0;
   int cls = 0, slot = 0;  // size class and position inside it
 };
@@ -89,9 +89,7 @@ struct gp_batch {
   std::vector<std::pair<void*, size_t>> allocs;
 
   void* runs_dev = nullptr;  // RunDev<T>[nruns]
-  WorkItem* cell_work = nullptr;  // plane tiles (Eulerian)
-  unsigned ncell_work = 0;
-  WorkItem* col_work = nullptr;   // tile columns by z chunk (Lagrangian, partial rows)
+  WorkItem* col_work = nullptr;   // tile columns by z chunk (every per-cell kernel, partial rows)
   unsigned ncol_work = 0;
   double* partials = nullptr;
   RedItem* red_items = nullptr;
@@ -247,10 +245,10 @@ void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
   switch (k) {
     case GP_K_EUL_GAS:
-      launch_eulerian<T>(runs, b->cell_work, b->ncell_work, b->parity, COMP_GAS, nblocks, b->st);
+      launch_eulerian<T>(runs, b->col_work, b->ncol_work, b->parity, COMP_GAS, nblocks, b->st);
       break;
     case GP_K_EUL_BME:
-      launch_eulerian<T>(runs, b->cell_work, b->ncell_work, b->parity, COMP_BME, nblocks, b->st);
+      launch_eulerian<T>(runs, b->col_work, b->ncol_work, b->parity, COMP_BME, nblocks, b->st);
       break;
     case GP_K_LAG_GAS:
       launch_lagrangian<T>(runs, b->col_work, b->ncol_work, b->parity, b->partials, COMP_GAS, nblocks, b->st);
@@ -262,8 +260,8 @@ void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
 }
 
 unsigned work_count(const gp_batch* b, int k) {
-  if (k == GP_K_LAG_GAS || k == GP_K_LAG_BME) return b->ncol_work;
-  return b->ncell_work;
+  (void)k;
+  return b->ncol_work;
 }
 
 // Time the persistent grid-size candidates of kernel k and keep the fastest.
@@ -482,8 +480,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     R.ph = Phys{cfgs[r].gamma, cfgs[r].G, cfgs[r].cfl, cfgs[r].eta, cfgs[r].fixed_dt, cfgs[r].t_end};
     R.ntx = (R.g.nx + kTX - 1) / kTX;
     R.nty = (R.g.ny + kTY - 1) / kTY;
-    R.ntiles = (unsigned)(R.ntx * R.nty * R.g.nz);
-    // Lagrangian column items: a tile column split into chunks of cz planes,
+    // Column items: a tile column split into chunks of cz planes,
     // about kColItems items per run (chunks of 4 to 32 planes).  Each chunk
     // re-reads the planes just below and above it, so chunks are as long as
     // the workgroups resident on the chip (2-3 per CU) allow.
@@ -576,26 +573,14 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   b->epot = static_cast<double*>(dalloc(b, std::max(1u, eoff) * sizeof(double), &st));
 
   // work lists, partial rows, reduction items, finalize descriptors
-  std::vector<WorkItem> cw, colw;
+  std::vector<WorkItem> colw;
   std::vector<RedItem> items;
   std::vector<FinDesc> fins;
   unsigned soff = 0;
   for (int r = 0; r < nruns; r++) {
     RunHost& R = b->runs[r];
-    // Cell tiles go in chunks of cz z planes; inside a chunk, tile columns in
-    // x-then-y order, each walked z fastest.  The workgroups of an XCD, which
-    // take consecutive items, then share one plane of a column while its z
-    // neighbours are read, and the x / y neighbour columns follow within a few
-    // dozen items, so the 7-point stencils re-read their halos from L2
-    // instead of HBM.  Partial rows stay indexed by tile, so the order changes
-    // no result.
-    const int cz = std::max(4, std::min(16, 64 / R.ntx));
-    for (int z0 = 0; z0 < R.g.nz; z0 += cz)
-      for (int ty = 0; ty < R.nty; ty++)
-        for (int tx = 0; tx < R.ntx; tx++)
-          for (int k = z0; k < std::min(z0 + cz, R.g.nz); k++) cw.push_back({r, tx + R.ntx * (ty + R.nty * k)});
     // column items, x fastest, then y, then the z chunk: the columns whose
-    // rings overlap run side by side
+    // rings overlap run side by side on one XCD
     for (unsigned c = 0; c < R.ncols; c++) colw.push_back({r, (int)c});
     const unsigned nscr = std::max(1u, std::min(256u, R.ncols / 16));
     const unsigned chunk = (R.ncols + nscr - 1) / nscr;
@@ -617,10 +602,8 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     fins.push_back(fd);
     soff += nscr;
   }
-  b->ncell_work = (unsigned)cw.size();
   b->ncol_work = (unsigned)colw.size();
   b->nred = (int)items.size();
-  b->cell_work = static_cast<WorkItem*>(dalloc(b, cw.size() * sizeof(WorkItem), &st));
   b->col_work = static_cast<WorkItem*>(dalloc(b, colw.size() * sizeof(WorkItem), &st));
   b->partials = static_cast<double*>(dalloc(b, (size_t)row * kNP * sizeof(double), &st));
   b->red_items = static_cast<RedItem*>(dalloc(b, items.size() * sizeof(RedItem), &st));
@@ -636,7 +619,6 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   auto put = [&](void* dst, const void* src, size_t bytes) {
     if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
   };
-  put(b->cell_work, cw.data(), cw.size() * sizeof(WorkItem));
   put(b->col_work, colw.data(), colw.size() * sizeof(WorkItem));
   put(b->red_items, items.data(), items.size() * sizeof(RedItem));
   put(b->fin, fins.data(), fins.size() * sizeof(FinDesc));
@@ -692,8 +674,8 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(b, e, "engine upload");
   for (int k = 0; k < GP_NKERNELS; k++) b->blocks[k] = 0;
-  b->blocks[GP_K_EUL_GAS] = b->ncell_work;
-  b->blocks[GP_K_EUL_BME] = b->ncell_work;
+  b->blocks[GP_K_EUL_GAS] = b->ncol_work;
+  b->blocks[GP_K_EUL_BME] = b->ncol_work;
   b->blocks[GP_K_LAG_GAS] = b->ncol_work;
   b->blocks[GP_K_LAG_BME] = b->ncol_work;
   return GP_OK;

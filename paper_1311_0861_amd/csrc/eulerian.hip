@@ -15,27 +15,14 @@
 // Lagrangian stage advects with (it rebuilds m' = rho v' where it needs it).
 //
 // The two components only share the potential, so each has its own kernel:
-// the gas kernel touches 5 + 1 arrays per stencil point, the stars / dark
-// matter kernel 10 + 1, and each holds half the live state of a joint one,
-// which buys occupancy for these latency-bound stencils.
+// the gas kernel needs 5 primitives + the potential per stencil point, the
+// stars / dark matter kernel 10 + 1, and each holds half the live state of a
+// joint one, which buys occupancy for these latency-bound stencils.
+#include "column.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace gp {
-
-// Gravity acceleration -grad Phi at a cell (zero when G = 0): central
-// differences of the periodic potential.
-template <typename T>
-__device__ __forceinline__ void gravity(gptr<const T> phi, const Grid& g, double G, int i, int j, int k,
-                                        T grad[3]) {
-  grad[0] = grad[1] = grad[2] = T(0);
-  if (G == 0.0) return;
-  const Stencil w = make_stencil(g, i, j, k, true);
-  const T r2h = (T)(0.5 / g.h);
-  grad[0] = (ld_pt<2>(phi, w) - ld_pt<1>(phi, w)) * r2h;
-  grad[1] = (ld_pt<4>(phi, w) - ld_pt<3>(phi, w)) * r2h;
-  grad[2] = (ld_pt<6>(phi, w) - ld_pt<5>(phi, w)) * r2h;
-}
 
 // ---------------------------------------------------------------- gas ----
 
@@ -43,37 +30,6 @@ template <typename T>
 struct GasPrim {
   T rho, vd, p;  // density, velocity normal to the face, pressure
 };
-
-template <typename T>
-struct GasIn {
-  gptr<const double> rho;
-  gptr<const T> m[3], E, e;
-};
-
-// Raw loads of one stencil point for faces normal to D: rho, m_D, e.
-template <typename T>
-struct GasRaw {
-  double rho;
-  T md, e;
-};
-
-template <int P, int D, typename T>
-__device__ __forceinline__ GasRaw<T> load_gas(const GasIn<T>& in, const Stencil& s) {
-  GasRaw<T> r;
-  r.rho = ld_pt<P>(in.rho, s);
-  r.md = ld_pt<P>(in.m[D], s);
-  r.e = ld_pt<P>(in.e, s);
-  return r;
-}
-
-template <typename T>
-__device__ __forceinline__ GasPrim<T> prim_of(const GasRaw<T>& r, T gm1) {
-  GasPrim<T> q;
-  q.rho = (T)r.rho;
-  q.vd = r.md * rcp(q.rho);
-  q.p = gm1 * r.e;
-  return q;
-}
 
 // Sec. 2.1: V and P at a face between left and right states; z is the
 // acoustic impedance sqrt(gamma (pL + pR) rhoL rhoR / (rhoL + rhoR)).
@@ -86,71 +42,7 @@ __device__ __forceinline__ void gas_face(const GasPrim<T>& L, const GasPrim<T>& 
   P = T(0.5) * (pl + pr) + T(0.5) * (L.vd - R.vd) * z;
 }
 
-template <typename T>
-__device__ __forceinline__ void gas_axis(const GasRaw<T>& lo, const GasRaw<T>& hi, const GasPrim<T>& C, T gamma,
-                                         T gm1, T& dP, T& dPV, T& dV) {
-  T Vm, Pm, Vp, Pp;
-  gas_face(prim_of(lo, gm1), C, gamma, Vm, Pm);
-  gas_face(C, prim_of(hi, gm1), gamma, Vp, Pp);
-  dP = Pp - Pm;
-  dPV += Pp * Vp - Pm * Vm;
-  dV += Vp - Vm;
-}
-
-template <typename T>
-__device__ __forceinline__ void eul_gas_cell(const RunDev<T>& R, int parity, double tau_d, int i, int j, int k) {
-  const Grid& g = R.g;
-  const T tau = (T)tau_d, r = (T)(tau_d / g.h);
-  const T gamma = (T)R.ph.gamma, gm1 = gamma - T(1);
-  const Stencil s = make_stencil(g, i, j, k, false);
-  GasIn<T> in;
-  in.rho = as_global((const double*)R.dens[parity][0]);
-#pragma unroll
-  for (int d = 0; d < 3; d++) in.m[d] = as_global((const T*)R.cur[oidx(GP_MX + d)]);
-  in.E = as_global((const T*)R.cur[oidx(GP_E)]);
-  in.e = as_global((const T*)R.cur[oidx(GP_EINT)]);
-
-  // every load of the cell first (3 per neighbour), then the faces
-  const double rho_c = ld_pt<0>(in.rho, s);
-  T m[3];
-#pragma unroll
-  for (int d = 0; d < 3; d++) m[d] = ld_pt<0>(in.m[d], s);
-  const T e = ld_pt<0>(in.e, s), E = ld_pt<0>(in.E, s);
-  const GasRaw<T> xl = load_gas<1, 0>(in, s), xh = load_gas<2, 0>(in, s);
-  const GasRaw<T> yl = load_gas<3, 1>(in, s), yh = load_gas<4, 1>(in, s);
-  const GasRaw<T> zl = load_gas<5, 2>(in, s), zh = load_gas<6, 2>(in, s);
-  T grad[3];
-  gravity<T>(as_global((const T*)R.phi), g, R.ph.G, i, j, k, grad);
-
-  GasPrim<T> C;
-  C.rho = (T)rho_c;
-  const T irho = rcp(C.rho);
-  C.p = gm1 * e;
-  T dP[3], dPV = T(0), dV = T(0);
-  C.vd = m[0] * irho;
-  gas_axis(xl, xh, C, gamma, gm1, dP[0], dPV, dV);
-  C.vd = m[1] * irho;
-  gas_axis(yl, yh, C, gamma, gm1, dP[1], dPV, dV);
-  C.vd = m[2] * irho;
-  gas_axis(zl, zh, C, gamma, gm1, dP[2], dPV, dV);
-
-  // momentum slots receive v' = m' / rho
-  const size_t z = s.z[1];
-  const uint32_t xy = s.xy[0];
-#pragma unroll
-  for (int d = 0; d < 3; d++)
-    st_at(as_global((T*)R.tmp[oidx(GP_MX + d)]), z, xy, (m[d] - r * dP[d] - tau * C.rho * grad[d]) * irho);
-  st_at(as_global((T*)R.tmp[oidx(GP_E)]), z, xy, E - r * dPV - tau * (m[0] * grad[0] + m[1] * grad[1] + m[2] * grad[2]));
-  st_at(as_global((T*)R.tmp[oidx(GP_EINT)]), z, xy, e - r * gm1 * e * dV);
-}
-
 // ------------------------------------------------- stars / dark matter ----
-
-template <typename T>
-struct BmeIn {
-  gptr<const double> n;
-  gptr<const T> q[3], P[6], W[6];
-};
 
 // One side of a face normal to axis D: density, velocity and row D of Pi
 // (components DD, DA, DB with A = D+1, B = D+2 mod 3).
@@ -158,40 +50,6 @@ template <typename T>
 struct BmeSide {
   T n, u[3], pdd, pda, pdb;
 };
-
-// Raw loads of a neighbour across a face normal to D (converted only when
-// the face is solved, so the loads stay in flight meanwhile).
-template <typename T>
-struct BmeRaw {
-  double n;
-  T q[3], p[3];
-};
-
-template <int Pt, int D, typename T>
-__device__ __forceinline__ BmeRaw<T> load_raw(const BmeIn<T>& in, const Stencil& s) {
-  constexpr int A_ = (D + 1) % 3, B_ = (D + 2) % 3;
-  BmeRaw<T> r;
-  r.n = ld_pt<Pt>(in.n, s);
-#pragma unroll
-  for (int d = 0; d < 3; d++) r.q[d] = ld_pt<Pt>(in.q[d], s);
-  r.p[0] = ld_pt<Pt>(in.P[sym(D, D)], s);
-  r.p[1] = ld_pt<Pt>(in.P[sym(D, A_)], s);
-  r.p[2] = ld_pt<Pt>(in.P[sym(D, B_)], s);
-  return r;
-}
-
-template <typename T>
-__device__ __forceinline__ BmeSide<T> side_of(const BmeRaw<T>& r) {
-  BmeSide<T> o;
-  o.n = (T)r.n;
-  const T in_ = rcp(o.n);
-#pragma unroll
-  for (int d = 0; d < 3; d++) o.u[d] = r.q[d] * in_;
-  o.pdd = r.p[0];
-  o.pda = r.p[1];
-  o.pdb = r.p[2];
-  return o;
-}
 
 // Centre cell: n, u and the full Pi.
 template <typename T>
@@ -264,127 +122,326 @@ __device__ __forceinline__ void bme_face_add(const T us[3], const T ps[3], T sg,
     }
 }
 
-// Solves the face on side `plus` of axis D against the neighbour's raw loads
-// and folds it in.
-template <int D, bool kPlus, typename T>
-__device__ __forceinline__ void bme_face_step(const BmeRaw<T>& nb, const BmeCentre<T>& C, T dq[3], T dW[6],
-                                              T dPi[6]) {
-  T us[3], ps[3];
-  if constexpr (kPlus)
-    bme_face<T, D>(centre_side<D>(C), side_of(nb), us, ps);
-  else
-    bme_face<T, D>(side_of(nb), centre_side<D>(C), us, ps);
-  bme_face_add<D>(us, ps, kPlus ? T(1) : T(-1), C, dq, dW, dPi);
+// ------------------------------------------------------------ columns ----
+//
+// Both kernels walk tile columns (see column.hpp).  For plane k the
+// primitives of every cell of the tile and its ring sit in LDS, formed once
+// per cell as they are staged (u = q / n, v = m / rho, p = (gamma - 1) e);
+// the next plane's primitives come into registers a plane ahead and the
+// previous plane's are read back from the LDS centres.  The potential has
+// its own tile with a periodic ring.
+
+// Gas tile slots: rho, v_x, v_y, v_z, p.  Stars / DM: n, u_x, u_y, u_z, Pi (6).
+constexpr int kGasPrims = 5;
+constexpr int kBmePrims = 10;
+
+template <int D, typename T>
+__device__ __forceinline__ GasPrim<T> gas_at(const T (&t)[kGasPrims][kLY][kLX], int r, int c) {
+  return GasPrim<T>{t[0][r][c], t[1 + D][r][c], t[4][r][c]};
+}
+template <int D, typename T>
+__device__ __forceinline__ GasPrim<T> gas_of(const T (&a)[kGasPrims]) {
+  return GasPrim<T>{a[0], a[1 + D], a[4]};
+}
+template <int D, typename T>
+__device__ __forceinline__ BmeSide<T> bme_at(const T (&t)[kBmePrims][kLY][kLX], int r, int c) {
+  BmeSide<T> o;
+  o.n = t[0][r][c];
+#pragma unroll
+  for (int d = 0; d < 3; d++) o.u[d] = t[1 + d][r][c];
+  o.pdd = t[4 + sym(D, D)][r][c];
+  o.pda = t[4 + sym(D, (D + 1) % 3)][r][c];
+  o.pdb = t[4 + sym(D, (D + 2) % 3)][r][c];
+  return o;
+}
+template <int D, typename T>
+__device__ __forceinline__ BmeSide<T> bme_of(const T (&a)[kBmePrims]) {
+  BmeSide<T> o;
+  o.n = a[0];
+#pragma unroll
+  for (int d = 0; d < 3; d++) o.u[d] = a[1 + d];
+  o.pdd = a[4 + sym(D, D)];
+  o.pda = a[4 + sym(D, (D + 1) % 3)];
+  o.pdb = a[4 + sym(D, (D + 2) % 3)];
+  return o;
 }
 
-// Ends a face phase: the accumulators must hold this face's contribution
-// here (an empty asm that reads and rewrites them), so the face is solved
-// while the loads issued for later faces are still in flight, instead of
-// being deferred until every load has returned.
+// Potential of the cell at (z, xy), zero without gravity.
 template <typename T>
-__device__ __forceinline__ void phase_fence(T dq[3], T dW[6], T dPi[6]) {
-#pragma unroll
-  for (int a = 0; a < 3; a++) asm volatile("" : "+v"(dq[a]));
-#pragma unroll
-  for (int a = 0; a < 6; a++) asm volatile("" : "+v"(dW[a]), "+v"(dPi[a]));
+__device__ __forceinline__ T phi_at(gptr<const T> phi, bool grav, size_t z, uint32_t xy) {
+  return grav ? ld_at(phi, z, xy) : T(0);
 }
 
-template <typename T>
-__device__ __forceinline__ void eul_bme_cell(const RunDev<T>& R, int parity, double tau_d, int i, int j, int k) {
-  const Grid& g = R.g;
-  const T tau = (T)tau_d, r = (T)(tau_d / g.h);
-  const Stencil s = make_stencil(g, i, j, k, false);
-  BmeIn<T> in;
-  in.n = as_global((const double*)R.dens[parity][1]);
-#pragma unroll
-  for (int d = 0; d < 3; d++) in.q[d] = as_global((const T*)R.cur[oidx(GP_QX + d)]);
-#pragma unroll
-  for (int m = 0; m < 6; m++) {
-    in.P[m] = as_global((const T*)R.cur[oidx(GP_PXX + m)]);
-    in.W[m] = as_global((const T*)R.cur[oidx(GP_WXX + m)]);
-  }
-
-  // centre, then the six neighbours two faces ahead of the face being solved
-  T qc[3];
-  BmeCentre<T> C;
-  C.n = (T)ld_pt<0>(in.n, s);
-#pragma unroll
-  for (int d = 0; d < 3; d++) qc[d] = ld_pt<0>(in.q[d], s);
-#pragma unroll
-  for (int m = 0; m < 6; m++) C.P[m] = ld_pt<0>(in.P[m], s);
-  BmeRaw<T> a = load_raw<1, 0>(in, s);
-  BmeRaw<T> b = load_raw<2, 0>(in, s);
-  {
-    const T inb = rcp(C.n);
-#pragma unroll
-    for (int d = 0; d < 3; d++) C.u[d] = qc[d] * inb;
-  }
-  T dq[3] = {T(0), T(0), T(0)};
-  T dW[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  T dPi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  bme_face_step<0, false>(a, C, dq, dW, dPi);
-  BmeRaw<T> c = load_raw<3, 1>(in, s);
-  phase_fence(dq, dW, dPi);
-  bme_face_step<0, true>(b, C, dq, dW, dPi);
-  BmeRaw<T> d = load_raw<4, 1>(in, s);
-  phase_fence(dq, dW, dPi);
-  bme_face_step<1, false>(c, C, dq, dW, dPi);
-  BmeRaw<T> e = load_raw<5, 2>(in, s);
-  phase_fence(dq, dW, dPi);
-  bme_face_step<1, true>(d, C, dq, dW, dPi);
-  BmeRaw<T> f = load_raw<6, 2>(in, s);
-  T W[6];
-#pragma unroll
-  for (int m = 0; m < 6; m++) W[m] = ld_pt<0>(in.W[m], s);
-  T grad[3];
-  gravity<T>(as_global((const T*)R.phi), g, R.ph.G, i, j, k, grad);
-  phase_fence(dq, dW, dPi);
-  bme_face_step<2, false>(e, C, dq, dW, dPi);
-  phase_fence(dq, dW, dPi);
-  bme_face_step<2, true>(f, C, dq, dW, dPi);
-
-  // momentum slots receive u' = q' / n
-  const T inb = rcp(C.n);
-  const size_t z = s.z[1];
-  const uint32_t xy = s.xy[0];
-#pragma unroll
-  for (int dd = 0; dd < 3; dd++)
-    st_at(as_global((T*)R.tmp[oidx(GP_QX + dd)]), z, xy, (qc[dd] - r * dq[dd] - tau * C.n * grad[dd]) * inb);
-#pragma unroll
-  for (int aa = 0; aa < 3; aa++)
-#pragma unroll
-    for (int bb = aa; bb < 3; bb++) {
-      const int m = sym(aa, bb);
-      st_at(as_global((T*)R.tmp[oidx(GP_WXX + m)]), z, xy,
-            W[m] - r * dW[m] - tau * (qc[aa] * grad[bb] + qc[bb] * grad[aa]));
-      st_at(as_global((T*)R.tmp[oidx(GP_PXX + m)]), z, xy, C.P[m] - r * dPi[m]);
-    }
-}
-
-// ------------------------------------------------------------ launches ----
-
-// Persistent launches over the (run, tile) work list of a batch.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict__ runs,
                                                     const WorkItem* __restrict__ work, unsigned nwork, int parity) {
+  __shared__ T s_g[kGasPrims][kLY][kLX];
+  __shared__ T s_phi[kLY][kLX];
+  const int lx = threadIdx.x, ly = threadIdx.y;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const int run = uniform(work[w].run), item = uniform(work[w].tile);
     const RunDev<T>& R = runs[run];
-    const TileCell c = tile_cell(R, tile);
-    if (c.inside) eul_gas_cell<T>(R, parity, R.sc->dt, c.i, c.j, c.k);
+    const Grid& g = R.g;
+    const Column col = make_column(g, R.ntx, R.nty, R.cz, item, false);
+    const Column pc = make_column(g, R.ntx, R.nty, R.cz, item, true);
+    const bool grav = R.ph.G != 0.0;
+    const size_t nxy = (size_t)g.nx * g.ny;
+    const double tau_d = R.sc->dt;
+    const T tau = (T)tau_d, r = (T)(tau_d / g.h), r2h = (T)(0.5 / g.h);
+    const T gamma = (T)R.ph.gamma, gm1 = gamma - T(1);
+    const gptr<const double> rho_in = as_global((const double*)R.dens[parity][0]);
+    gptr<const T> m_in[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) m_in[d] = as_global((const T*)R.cur[oidx(GP_MX + d)]);
+    const gptr<const T> E_in = as_global((const T*)R.cur[oidx(GP_E)]);
+    const gptr<const T> e_in = as_global((const T*)R.cur[oidx(GP_EINT)]);
+    const gptr<const T> phi = as_global((const T*)R.phi);
+    // raw loads of a cell, then its primitives
+    auto load = [&](size_t z, uint32_t xy, double& rho, T m[3], T& e) {
+      rho = ld_at(rho_in, z, xy);
+#pragma unroll
+      for (int d = 0; d < 3; d++) m[d] = ld_at(m_in[d], z, xy);
+      e = ld_at(e_in, z, xy);
+    };
+    auto prims = [&](double rho, const T m[3], T e, T (&a)[kGasPrims]) {
+      a[0] = (T)rho;
+      const T ir = rcp(a[0]);
+#pragma unroll
+      for (int d = 0; d < 3; d++) a[1 + d] = m[d] * ir;
+      a[4] = gm1 * e;
+    };
+
+    // prologue: plane k0 - 1 into the LDS centres, plane k0 into registers
+    T pc_[kGasPrims], mc[3], ec, phc;
+    {
+      const size_t zm = plane_at(g, col.k0 - 1, g.bc[2]), z0 = nxy * (size_t)col.k0;
+      double rho, rho0;
+      T m[3], e, pm[kGasPrims];
+      load(zm, col.xy_c, rho, m, e);
+      load(z0, col.xy_c, rho0, mc, ec);
+      const T phm = phi_at(phi, grav, plane_at(g, col.k0 - 1, GP_BC_PERIODIC), pc.xy_c);
+      phc = phi_at(phi, grav, z0, pc.xy_c);
+      prims(rho, m, e, pm);
+      prims(rho0, mc, ec, pc_);
+#pragma unroll
+      for (int f = 0; f < kGasPrims; f++) s_g[f][ly + 1][lx + 1] = pm[f];
+      s_phi[ly + 1][lx + 1] = phm;
+    }
+    for (int k = col.k0; k < col.k1; k++) {
+      const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
+      T pm[kGasPrims];
+#pragma unroll
+      for (int f = 0; f < kGasPrims; f++) pm[f] = s_g[f][ly + 1][lx + 1];
+      const T phm = s_phi[ly + 1][lx + 1];
+      __syncthreads();  // every thread is done with the previous plane's tiles
+      double rho_h, rho_n;
+      T m_h[3], e_h, m_n[3], e_n;
+      if (col.ring) load(zk, col.xy_h, rho_h, m_h, e_h);
+      load(zp, col.xy_c, rho_n, m_n, e_n);
+      const T E = ld_at(E_in, zk, col.xy_c);
+      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pc.xy_c);
+      const T phh = (col.ring && grav) ? ld_at(phi, zk, pc.xy_h) : T(0);
+      if (col.ring) {
+        T a[kGasPrims];
+        prims(rho_h, m_h, e_h, a);
+#pragma unroll
+        for (int f = 0; f < kGasPrims; f++) s_g[f][col.hr][col.hc] = a[f];
+        s_phi[col.hr][col.hc] = phh;
+      }
+#pragma unroll
+      for (int f = 0; f < kGasPrims; f++) s_g[f][ly + 1][lx + 1] = pc_[f];
+      s_phi[ly + 1][lx + 1] = phc;
+      T pn[kGasPrims];
+      prims(rho_n, m_n, e_n, pn);
+      __syncthreads();
+
+      if (col.active) {
+        // faces: x / y neighbours from the tile, z from registers
+        T Vm, Pm, Vp, Pp, dP[3], dPV = T(0), dV = T(0);
+        gas_face(gas_at<0>(s_g, ly + 1, lx), gas_of<0>(pc_), gamma, Vm, Pm);
+        gas_face(gas_of<0>(pc_), gas_at<0>(s_g, ly + 1, lx + 2), gamma, Vp, Pp);
+        dP[0] = Pp - Pm;
+        dPV += Pp * Vp - Pm * Vm;
+        dV += Vp - Vm;
+        gas_face(gas_at<1>(s_g, ly, lx + 1), gas_of<1>(pc_), gamma, Vm, Pm);
+        gas_face(gas_of<1>(pc_), gas_at<1>(s_g, ly + 2, lx + 1), gamma, Vp, Pp);
+        dP[1] = Pp - Pm;
+        dPV += Pp * Vp - Pm * Vm;
+        dV += Vp - Vm;
+        gas_face(gas_of<2>(pm), gas_of<2>(pc_), gamma, Vm, Pm);
+        gas_face(gas_of<2>(pc_), gas_of<2>(pn), gamma, Vp, Pp);
+        dP[2] = Pp - Pm;
+        dPV += Pp * Vp - Pm * Vm;
+        dV += Vp - Vm;
+        T grad[3] = {T(0), T(0), T(0)};
+        if (grav) {
+          grad[0] = (s_phi[ly + 1][lx + 2] - s_phi[ly + 1][lx]) * r2h;
+          grad[1] = (s_phi[ly + 2][lx + 1] - s_phi[ly][lx + 1]) * r2h;
+          grad[2] = (php - phm) * r2h;
+        }
+        // momentum slots receive v' = m' / rho
+        const T irho = rcp(pc_[0]);
+        const uint32_t xy = col.xy_c;
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+          st_at(as_global((T*)R.tmp[oidx(GP_MX + d)]), zk, xy, (mc[d] - r * dP[d] - tau * pc_[0] * grad[d]) * irho);
+        st_at(as_global((T*)R.tmp[oidx(GP_E)]), zk, xy,
+              E - r * dPV - tau * (mc[0] * grad[0] + mc[1] * grad[1] + mc[2] * grad[2]));
+        st_at(as_global((T*)R.tmp[oidx(GP_EINT)]), zk, xy, ec - r * gm1 * ec * dV);
+      }
+#pragma unroll
+      for (int f = 0; f < kGasPrims; f++) pc_[f] = pn[f];
+#pragma unroll
+      for (int d = 0; d < 3; d++) mc[d] = m_n[d];
+      ec = e_n;
+      phc = php;
+    }
+    __syncthreads();  // the next item restages the tiles
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_eul_bme(const RunDev<T>* __restrict__ runs,
+__global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restrict__ runs,
                                                     const WorkItem* __restrict__ work, unsigned nwork, int parity) {
+  __shared__ T s_p[kBmePrims][kLY][kLX];
+  __shared__ T s_phi[kLY][kLX];
+  const int lx = threadIdx.x, ly = threadIdx.y;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), tile = uniform(work[w].tile);
+    const int run = uniform(work[w].run), item = uniform(work[w].tile);
     const RunDev<T>& R = runs[run];
-    const TileCell c = tile_cell(R, tile);
-    if (c.inside) eul_bme_cell<T>(R, parity, R.sc->dt, c.i, c.j, c.k);
+    const Grid& g = R.g;
+    const Column col = make_column(g, R.ntx, R.nty, R.cz, item, false);
+    const Column pc = make_column(g, R.ntx, R.nty, R.cz, item, true);
+    const bool grav = R.ph.G != 0.0;
+    const size_t nxy = (size_t)g.nx * g.ny;
+    const double tau_d = R.sc->dt;
+    const T tau = (T)tau_d, r = (T)(tau_d / g.h), r2h = (T)(0.5 / g.h);
+    const gptr<const double> n_in = as_global((const double*)R.dens[parity][1]);
+    gptr<const T> q_in[3], P_in[6];
+#pragma unroll
+    for (int d = 0; d < 3; d++) q_in[d] = as_global((const T*)R.cur[oidx(GP_QX + d)]);
+#pragma unroll
+    for (int m = 0; m < 6; m++) P_in[m] = as_global((const T*)R.cur[oidx(GP_PXX + m)]);
+    const gptr<const T> phi = as_global((const T*)R.phi);
+    auto load = [&](size_t z, uint32_t xy, double& n, T q[3], T P[6]) {
+      n = ld_at(n_in, z, xy);
+#pragma unroll
+      for (int d = 0; d < 3; d++) q[d] = ld_at(q_in[d], z, xy);
+#pragma unroll
+      for (int m = 0; m < 6; m++) P[m] = ld_at(P_in[m], z, xy);
+    };
+    auto prims = [&](double n, const T q[3], const T P[6], T (&a)[kBmePrims]) {
+      a[0] = (T)n;
+      const T in_ = rcp(a[0]);
+#pragma unroll
+      for (int d = 0; d < 3; d++) a[1 + d] = q[d] * in_;
+#pragma unroll
+      for (int m = 0; m < 6; m++) a[4 + m] = P[m];
+    };
+
+    // prologue: plane k0 - 1 into the LDS centres, plane k0 into registers
+    T pc_[kBmePrims], qc[3], phc;
+    {
+      const size_t zm = plane_at(g, col.k0 - 1, g.bc[2]), z0 = nxy * (size_t)col.k0;
+      double n, n0;
+      T q[3], P[6], P0[6], pm[kBmePrims];
+      load(zm, col.xy_c, n, q, P);
+      load(z0, col.xy_c, n0, qc, P0);
+      const T phm = phi_at(phi, grav, plane_at(g, col.k0 - 1, GP_BC_PERIODIC), pc.xy_c);
+      phc = phi_at(phi, grav, z0, pc.xy_c);
+      prims(n, q, P, pm);
+      prims(n0, qc, P0, pc_);
+#pragma unroll
+      for (int f = 0; f < kBmePrims; f++) s_p[f][ly + 1][lx + 1] = pm[f];
+      s_phi[ly + 1][lx + 1] = phm;
+    }
+    for (int k = col.k0; k < col.k1; k++) {
+      const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
+      T pm[kBmePrims];
+#pragma unroll
+      for (int f = 0; f < kBmePrims; f++) pm[f] = s_p[f][ly + 1][lx + 1];
+      const T phm = s_phi[ly + 1][lx + 1];
+      __syncthreads();  // every thread is done with the previous plane's tiles
+      {
+        double n_h;
+        T q_h[3], P_h[6];
+        if (col.ring) load(zk, col.xy_h, n_h, q_h, P_h);
+        const T phh = (col.ring && grav) ? ld_at(phi, zk, pc.xy_h) : T(0);
+        if (col.ring) {
+          T a[kBmePrims];
+          prims(n_h, q_h, P_h, a);
+#pragma unroll
+          for (int f = 0; f < kBmePrims; f++) s_p[f][col.hr][col.hc] = a[f];
+          s_phi[col.hr][col.hc] = phh;
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < kBmePrims; f++) s_p[f][ly + 1][lx + 1] = pc_[f];
+      s_phi[ly + 1][lx + 1] = phc;
+      double n_n;
+      T q_n[3], P_n[6], W[6];
+      load(zp, col.xy_c, n_n, q_n, P_n);
+#pragma unroll
+      for (int m = 0; m < 6; m++) W[m] = ld_at(as_global((const T*)R.cur[oidx(GP_WXX + m)]), zk, col.xy_c);
+      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pc.xy_c);
+      T pn[kBmePrims];
+      prims(n_n, q_n, P_n, pn);
+      __syncthreads();
+
+      if (col.active) {
+        BmeCentre<T> C;
+        C.n = pc_[0];
+#pragma unroll
+        for (int d = 0; d < 3; d++) C.u[d] = pc_[1 + d];
+#pragma unroll
+        for (int m = 0; m < 6; m++) C.P[m] = pc_[4 + m];
+        T dq[3] = {T(0), T(0), T(0)};
+        T dW[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        T dPi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        T us[3], ps[3];
+        bme_face<T, 0>(bme_at<0>(s_p, ly + 1, lx), centre_side<0>(C), us, ps);
+        bme_face_add<0>(us, ps, T(-1), C, dq, dW, dPi);
+        bme_face<T, 0>(centre_side<0>(C), bme_at<0>(s_p, ly + 1, lx + 2), us, ps);
+        bme_face_add<0>(us, ps, T(1), C, dq, dW, dPi);
+        bme_face<T, 1>(bme_at<1>(s_p, ly, lx + 1), centre_side<1>(C), us, ps);
+        bme_face_add<1>(us, ps, T(-1), C, dq, dW, dPi);
+        bme_face<T, 1>(centre_side<1>(C), bme_at<1>(s_p, ly + 2, lx + 1), us, ps);
+        bme_face_add<1>(us, ps, T(1), C, dq, dW, dPi);
+        bme_face<T, 2>(bme_of<2>(pm), centre_side<2>(C), us, ps);
+        bme_face_add<2>(us, ps, T(-1), C, dq, dW, dPi);
+        bme_face<T, 2>(centre_side<2>(C), bme_of<2>(pn), us, ps);
+        bme_face_add<2>(us, ps, T(1), C, dq, dW, dPi);
+        T grad[3] = {T(0), T(0), T(0)};
+        if (grav) {
+          grad[0] = (s_phi[ly + 1][lx + 2] - s_phi[ly + 1][lx]) * r2h;
+          grad[1] = (s_phi[ly + 2][lx + 1] - s_phi[ly][lx + 1]) * r2h;
+          grad[2] = (php - phm) * r2h;
+        }
+        // momentum slots receive u' = q' / n
+        const T inb = rcp(C.n);
+        const uint32_t xy = col.xy_c;
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+          st_at(as_global((T*)R.tmp[oidx(GP_QX + d)]), zk, xy, (qc[d] - r * dq[d] - tau * C.n * grad[d]) * inb);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+          for (int b = a; b < 3; b++) {
+            const int m = sym(a, b);
+            st_at(as_global((T*)R.tmp[oidx(GP_WXX + m)]), zk, xy,
+                  W[m] - r * dW[m] - tau * (qc[a] * grad[b] + qc[b] * grad[a]));
+            st_at(as_global((T*)R.tmp[oidx(GP_PXX + m)]), zk, xy, C.P[m] - r * dPi[m]);
+          }
+      }
+#pragma unroll
+      for (int f = 0; f < kBmePrims; f++) pc_[f] = pn[f];
+#pragma unroll
+      for (int d = 0; d < 3; d++) qc[d] = q_n[d];
+      phc = php;
+    }
+    __syncthreads();  // the next item restages the tiles
   }
 }
 

@@ -17,6 +17,7 @@
 // precisions.  The gas and the stars / dark matter advect with their own
 // corner velocities and share nothing else in this stage, so each has its own
 // kernel (6 and 16 fields), which halves the live state of a joint one.
+#include "column.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -218,9 +219,7 @@ __device__ __forceinline__ T advect7(const T x[7], const Weights<T>& w) {
 // coalesced rows, instead of 7 times through the cache hierarchy, and the
 // corner velocities never go to memory.
 
-constexpr int kLX = kTX + 2, kLY = kTY + 2;  // plane tile with its neighbour ring
 constexpr int kVX = kTX + 1, kVY = kTY + 1;  // vertex tile of a cell tile
-constexpr int kRing = 2 * kLX + 2 * kTY;     // ring cells of a plane tile
 constexpr int kVTile = 3 * kVX * kVY;        // corner values staged per vertex plane
 constexpr int kVPer = (kVTile + kBlock - 1) / kBlock;
 
@@ -242,14 +241,6 @@ struct Comp<COMP_BME> {
   static constexpr int kVel = 3;
   static constexpr int kDens = 1;
 };
-
-// Source cell of tile position x for the LDS tile: the boundary rule on the
-// one-cell ring outside the grid (x = -1 or x = n); positions further out are
-// never read and take any valid cell.
-__device__ __forceinline__ int ring_src(int x, int n, int bc) {
-  if (x < 0 || x == n) return bc_index(x, n, bc);
-  return x < n ? x : n - 1;
-}
 
 // Gas epilogue: kappa, energy balance, stores and diagnostics of a cell.
 template <typename T>
@@ -379,35 +370,15 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
     const int run = uniform(work[w].run), item = uniform(work[w].tile);
     const RunDev<T>& R = runs[run];
     const Grid& g = R.g;
-    const int tx = item % R.ntx, ty = (item / R.ntx) % R.nty, kc = item / (R.ntx * R.nty);
-    const int i0 = tx * kTX, j0 = ty * kTY, k0 = kc * R.cz, k1 = min(k0 + R.cz, g.nz);
-    const int i = i0 + lx, j = j0 + ly;
-    const bool active = i < g.nx && j < g.ny;
-    const uint32_t nx = (uint32_t)g.nx;
+    const Column col = make_column(g, R.ntx, R.nty, R.cz, item, false);
+    const int k0 = col.k0, k1 = col.k1, i = col.i, j = col.j;
+    const bool active = col.active, ring = col.ring;
+    const int hr = col.hr, hc = col.hc;
+    const uint32_t nx = (uint32_t)g.nx, xy_c = col.xy_c, xy_h = col.xy_h;
     const size_t nxy = (size_t)g.nx * g.ny;
-    const uint32_t xy_c = (uint32_t)ring_src(i, g.nx, g.bc[0]) + nx * (uint32_t)ring_src(j, g.ny, g.bc[1]);
-    // ring cell of this thread (threads tid < kRing): rows -1 and kTY, then
-    // columns -1 and kTX; (hr, hc) is its LDS position
-    const bool ring = tid < kRing;
-    int hr, hc;
-    if (tid < kLX) {
-      hr = 0;
-      hc = tid;
-    } else if (tid < 2 * kLX) {
-      hr = kLY - 1;
-      hc = tid - kLX;
-    } else if (tid < 2 * kLX + kTY) {
-      hr = 1 + tid - 2 * kLX;
-      hc = 0;
-    } else {
-      hr = 1 + min(tid - 2 * kLX - kTY, kTY - 1);
-      hc = kLX - 1;
-    }
-    const uint32_t xy_h =
-        (uint32_t)ring_src(i0 + hc - 1, g.nx, g.bc[0]) + nx * (uint32_t)ring_src(j0 + hr - 1, g.ny, g.bc[1]);
     const gptr<const double> din = as_global((const double*)R.dens[parity][K::kDens]);
     auto fin = [&](int f) { return as_global((const T*)R.tmp[O0 + f]); };
-    auto plane = [&](int k) -> size_t { return nxy * (size_t)bc_index(k, g.nz, g.bc[2]); };
+    auto plane = [&](int k) -> size_t { return plane_at(g, k, g.bc[2]); };
 
     // Corner velocities.  Vertex (I, J, K) is the mean of the 8 cells I-1..I,
     // J-1..J, K-1..K (boundary rule outside the grid), summed z-major, then y,
