@@ -69,6 +69,16 @@ __device__ __forceinline__ Column make_column(const Grid& g, int ntx, int nty, i
   return c;
 }
 
+// Re-issues a lane offset inside a plane loop.  Without it the compiler
+// hoists "array base + lane offset" out of the loop as one 64-bit vector
+// pointer per array and adds the plane offset to each of them every
+// iteration; with the offset opaque, each access is a scalar plane base plus
+// a 32-bit lane offset (one global load with a scalar base).
+__device__ __forceinline__ uint32_t fresh(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 // Element offset of plane k under the z boundary rule.
 __device__ __forceinline__ size_t plane_at(const Grid& g, int k, int bc) {
   return (size_t)g.nx * (size_t)g.ny * (size_t)bc_index(k, g.nz, bc);

@@ -230,6 +230,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
     }
     for (int k = col.k0; k < col.k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
+      const uint32_t xy_c = col.xy_c, xy_h = col.xy_h, pxy_c = pc.xy_c, pxy_h = pc.xy_h;
       T pm[kGasPrims];
 #pragma unroll
       for (int f = 0; f < kGasPrims; f++) pm[f] = s_g[f][ly + 1][lx + 1];
@@ -237,11 +238,11 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       __syncthreads();  // every thread is done with the previous plane's tiles
       double rho_h, rho_n;
       T m_h[3], e_h, m_n[3], e_n;
-      if (col.ring) load(zk, col.xy_h, rho_h, m_h, e_h);
-      load(zp, col.xy_c, rho_n, m_n, e_n);
-      const T E = ld_at(E_in, zk, col.xy_c);
-      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pc.xy_c);
-      const T phh = (col.ring && grav) ? ld_at(phi, zk, pc.xy_h) : T(0);
+      if (col.ring) load(zk, xy_h, rho_h, m_h, e_h);
+      load(zp, xy_c, rho_n, m_n, e_n);
+      const T E = ld_at(E_in, zk, xy_c);
+      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
+      const T phh = (col.ring && grav) ? ld_at(phi, zk, pxy_h) : T(0);
       if (col.ring) {
         T a[kGasPrims];
         prims(rho_h, m_h, e_h, a);
@@ -282,7 +283,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
         }
         // momentum slots receive v' = m' / rho
         const T irho = rcp(pc_[0]);
-        const uint32_t xy = col.xy_c;
+        const uint32_t xy = xy_c;
 #pragma unroll
         for (int d = 0; d < 3; d++)
           st_at(as_global((T*)R.tmp[oidx(GP_MX + d)]), zk, xy, (mc[d] - r * dP[d] - tau * pc_[0] * grad[d]) * irho);
@@ -359,6 +360,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
     }
     for (int k = col.k0; k < col.k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
+      const uint32_t xy_c = fresh(col.xy_c), xy_h = fresh(col.xy_h);
+      const uint32_t pxy_c = fresh(pc.xy_c), pxy_h = fresh(pc.xy_h);
       T pm[kBmePrims];
 #pragma unroll
       for (int f = 0; f < kBmePrims; f++) pm[f] = s_p[f][ly + 1][lx + 1];
@@ -367,8 +370,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       {
         double n_h;
         T q_h[3], P_h[6];
-        if (col.ring) load(zk, col.xy_h, n_h, q_h, P_h);
-        const T phh = (col.ring && grav) ? ld_at(phi, zk, pc.xy_h) : T(0);
+        if (col.ring) load(zk, xy_h, n_h, q_h, P_h);
+        const T phh = (col.ring && grav) ? ld_at(phi, zk, pxy_h) : T(0);
         if (col.ring) {
           T a[kBmePrims];
           prims(n_h, q_h, P_h, a);
@@ -382,10 +385,10 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       s_phi[ly + 1][lx + 1] = phc;
       double n_n;
       T q_n[3], P_n[6], W[6];
-      load(zp, col.xy_c, n_n, q_n, P_n);
+      load(zp, xy_c, n_n, q_n, P_n);
 #pragma unroll
-      for (int m = 0; m < 6; m++) W[m] = ld_at(as_global((const T*)R.cur[oidx(GP_WXX + m)]), zk, col.xy_c);
-      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pc.xy_c);
+      for (int m = 0; m < 6; m++) W[m] = ld_at(as_global((const T*)R.cur[oidx(GP_WXX + m)]), zk, xy_c);
+      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
       T pn[kBmePrims];
       prims(n_n, q_n, P_n, pn);
       __syncthreads();
@@ -421,7 +424,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
         }
         // momentum slots receive u' = q' / n
         const T inb = rcp(C.n);
-        const uint32_t xy = col.xy_c;
+        const uint32_t xy = xy_c;
 #pragma unroll
         for (int d = 0; d < 3; d++)
           st_at(as_global((T*)R.tmp[oidx(GP_QX + d)]), zk, xy, (qc[d] - r * dq[d] - tau * C.n * grad[d]) * inb);

@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
     const int k0 = col.k0, k1 = col.k1, i = col.i, j = col.j;
     const bool active = col.active, ring = col.ring;
     const int hr = col.hr, hc = col.hc;
-    const uint32_t nx = (uint32_t)g.nx, xy_c = col.xy_c, xy_h = col.xy_h;
+    const uint32_t nx = (uint32_t)g.nx;
     const size_t nxy = (size_t)g.nx * g.ny;
     const gptr<const double> din = as_global((const double*)R.dens[parity][K::kDens]);
     auto fin = [&](int f) { return as_global((const T*)R.tmp[O0 + f]); };
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
       }
     };
     // centre and ring of plane z of the three velocities into tile u
-    auto stage_velocity = [&](size_t z, T (&u)[3][kLY][kLX], const T ctr[3]) {
+    auto stage_velocity = [&](size_t z, uint32_t xy_h, T (&u)[3][kLY][kLX], const T ctr[3]) {
 #pragma unroll
       for (int d = 0; d < 3; d++) u[d][ly + 1][lx + 1] = ctr[d];
       if (ring) {
@@ -420,6 +420,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
       }
     };
 
+    const uint32_t xy_c = col.xy_c, xy_h = col.xy_h;
     // prologue: plane k0 - 1 goes to the LDS centre slots (each plane's z-
     // neighbours are read back from there) and to the velocity tile
     // s_u[(k0 + 1) & 1]; plane k0 goes to registers and to s_u[k0 & 1]; the
@@ -434,11 +435,11 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
       for (int f = 0; f < 3; f++) um[f] = ld_at(fin(f), zm, xy_c);
 #pragma unroll
       for (int f = 3; f < NF; f++) s_f[f - 3][ly + 1][lx + 1] = ld_at(fin(f), zm, xy_c);
-      stage_velocity(zm, s_u[(k0 + 1) & 1], um);
+      stage_velocity(zm, xy_h, s_u[(k0 + 1) & 1], um);
       dc = ld_at(din, z0, xy_c);
 #pragma unroll
       for (int f = 0; f < NF; f++) fc[f] = ld_at(fin(f), z0, xy_c);
-      stage_velocity(z0, s_u[k0 & 1], fc);
+      stage_velocity(z0, xy_h, s_u[k0 & 1], fc);
       __syncthreads();
       corner_plane(s_u[(k0 + 1) & 1], s_u[k0 & 1], s_v[k0 & 1]);
     }
@@ -450,6 +451,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
     for (int k = k0; k < k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane(k + 1);
       const int cu = k & 1, nu = cu ^ 1;  // velocity tiles of planes k and k+1
+      const uint32_t xy_c = fresh(col.xy_c), xy_h = fresh(col.xy_h);
       // the previous centres become the z- neighbours (each thread reads back
       // its own slot; the velocities from the tile of plane k-1); this
       // plane's ring and centres go into LDS; the next plane of the column
@@ -473,7 +475,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
       dp = ld_at(din, zp, xy_c);
 #pragma unroll
       for (int f = 0; f < NF; f++) fp[f] = ld_at(fin(f), zp, xy_c);
-      stage_velocity(zp, s_u[nu], fp);
+      stage_velocity(zp, xy_h, s_u[nu], fp);
       __syncthreads();
       corner_plane(s_u[cu], s_u[nu], s_v[(k + 1) & 1]);
       __syncthreads();
@@ -508,7 +510,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
         double out;
         const double dnew = advect_density(cf.dn, cf.ap, cf.am, rd, g, i, j, k, out);
         cf.w = flux_weights(cf.ap, cf.am, r);
-        const uint32_t xy = (uint32_t)i + nx * (uint32_t)j;
+        const uint32_t xy = xy_c;  // i + nx j for a cell inside the grid
         // velocities: x / y neighbours from the velocity tile of plane k
         auto vel_update = [&](int d) -> T {
           T x[7];
