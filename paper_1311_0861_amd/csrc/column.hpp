@@ -79,6 +79,24 @@ __device__ __forceinline__ uint32_t fresh(uint32_t x) {
   return x;
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// fences global memory, which makes every wave wait for all its outstanding
+// global loads first, including loads fetched ahead for later planes.  In
+// the column kernels threads share data through LDS alone (the global arrays
+// a kernel writes are not read by it), so an LDS fence is enough.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Compiler-only ordering point for memory accesses (no instruction, no
+// wait): loads written before it are issued before loads written after it.
+// The column kernels issue a plane's ring loads first and the loads fetched
+// ahead for later planes after them, so waiting for the ring does not wait
+// for the fetch-ahead.
+__device__ __forceinline__ void issue_order() { asm volatile("" ::: "memory"); }
+
 // Element offset of plane k under the z boundary rule.
 __device__ __forceinline__ size_t plane_at(const Grid& g, int k, int bc) {
   return (size_t)g.nx * (size_t)g.ny * (size_t)bc_index(k, g.nz, bc);

@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
 #pragma unroll
       for (int f = 0; f < kGasPrims; f++) pm[f] = s_g[f][ly + 1][lx + 1];
       const T phm = s_phi[ly + 1][lx + 1];
-      __syncthreads();  // every thread is done with the previous plane's tiles
+      lds_barrier();  // every thread is done with the previous plane's tiles
       double rho_h, rho_n;
       T m_h[3], e_h, m_n[3], e_n;
       if (col.ring) load(zk, xy_h, rho_h, m_h, e_h);
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       s_phi[ly + 1][lx + 1] = phc;
       T pn[kGasPrims];
       prims(rho_n, m_n, e_n, pn);
-      __syncthreads();
+      lds_barrier();
 
       if (col.active) {
         // faces: x / y neighbours from the tile, z from registers
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       ec = e_n;
       phc = php;
     }
-    __syncthreads();  // the next item restages the tiles
+    lds_barrier();  // the next item restages the tiles
   }
 }
 
@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
 #pragma unroll
       for (int f = 0; f < kBmePrims; f++) pm[f] = s_p[f][ly + 1][lx + 1];
       const T phm = s_phi[ly + 1][lx + 1];
-      __syncthreads();  // every thread is done with the previous plane's tiles
+      lds_barrier();  // every thread is done with the previous plane's tiles
       {
         double n_h;
         T q_h[3], P_h[6];
@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
       T pn[kBmePrims];
       prims(n_n, q_n, P_n, pn);
-      __syncthreads();
+      lds_barrier();
 
       if (col.active) {
         BmeCentre<T> C;
@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       for (int d = 0; d < 3; d++) qc[d] = q_n[d];
       phc = php;
     }
-    __syncthreads();  // the next item restages the tiles
+    lds_barrier();  // the next item restages the tiles
   }
 }
 

@@ -424,9 +424,17 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
     // prologue: plane k0 - 1 goes to the LDS centre slots (each plane's z-
     // neighbours are read back from there) and to the velocity tile
     // s_u[(k0 + 1) & 1]; plane k0 goes to registers and to s_u[k0 & 1]; the
-    // two give the corner velocities of vertex plane k0
+    // two give the corner velocities of vertex plane k0.  Plane k0 + 1 comes
+    // into registers too: the loop fetches each plane's centres two planes
+    // ahead, so they arrive while earlier planes are computed.
     double dc, dp;
     T fc[NF], fp[NF];
+    {
+      const size_t z1 = plane(k0 + 1);
+      dp = ld_at(din, z1, xy_c);
+#pragma unroll
+      for (int f = 0; f < NF; f++) fp[f] = ld_at(fin(f), z1, xy_c);
+    }
     {
       const size_t zm = plane(k0 - 1), z0 = nxy * (size_t)k0;
       T um[3];
@@ -440,7 +448,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
 #pragma unroll
       for (int f = 0; f < NF; f++) fc[f] = ld_at(fin(f), z0, xy_c);
       stage_velocity(z0, xy_h, s_u[k0 & 1], fc);
-      __syncthreads();
+      lds_barrier();
       corner_plane(s_u[(k0 + 1) & 1], s_u[k0 & 1], s_v[k0 & 1]);
     }
 
@@ -449,36 +457,49 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
     const double rd = R.sc->dt / g.h;
     const T r = (T)rd;
     for (int k = k0; k < k1; k++) {
-      const size_t zk = nxy * (size_t)k, zp = plane(k + 1);
+      const size_t zk = nxy * (size_t)k, zp = plane(k + 1), zpp = plane(k + 2);
       const int cu = k & 1, nu = cu ^ 1;  // velocity tiles of planes k and k+1
       const uint32_t xy_c = fresh(col.xy_c), xy_h = fresh(col.xy_h);
       // the previous centres become the z- neighbours (each thread reads back
       // its own slot; the velocities from the tile of plane k-1); this
-      // plane's ring and centres go into LDS; the next plane of the column
-      // (z+ neighbours) goes into registers, and its velocities with their
-      // ring into the other velocity tile
+      // plane's ring and centres go into LDS; the next plane's centres (z+
+      // neighbours, already in registers) and velocity ring go into the other
+      // velocity tile; plane k+2's centres are fetched for later
       const double dm = s_dn[ly + 1][lx + 1];
       T fm[NF];
 #pragma unroll
       for (int f = 0; f < 3; f++) fm[f] = s_u[nu][f][ly + 1][lx + 1];
 #pragma unroll
       for (int f = 3; f < NF; f++) fm[f] = s_f[f - 3][ly + 1][lx + 1];
-      __syncthreads();  // every thread is done with the previous plane's tiles
-      if (ring) {
-        s_dn[hr][hc] = ld_at(din, zk, xy_h);
+      lds_barrier();  // every thread is done with the previous plane's tiles
+      // ring loads (every lane has a valid ring address; only ring lanes
+      // store), then the plane k+2 prefetch, then the LDS writes
+      const double rd_h = ld_at(din, zk, xy_h);
+      T rf_h[NF], ru_h[3];
 #pragma unroll
-        for (int f = 3; f < NF; f++) s_f[f - 3][hr][hc] = ld_at(fin(f), zk, xy_h);
+      for (int f = 3; f < NF; f++) rf_h[f] = ld_at(fin(f), zk, xy_h);
+#pragma unroll
+      for (int f = 0; f < 3; f++) ru_h[f] = ld_at(fin(f), zp, xy_h);
+      issue_order();
+      const double dpp = ld_at(din, zpp, xy_c);
+      T fpp[NF];
+#pragma unroll
+      for (int f = 0; f < NF; f++) fpp[f] = ld_at(fin(f), zpp, xy_c);
+      if (ring) {
+        s_dn[hr][hc] = rd_h;
+#pragma unroll
+        for (int f = 3; f < NF; f++) s_f[f - 3][hr][hc] = rf_h[f];
+#pragma unroll
+        for (int f = 0; f < 3; f++) s_u[nu][f][hr][hc] = ru_h[f];
       }
       s_dn[ly + 1][lx + 1] = dc;
 #pragma unroll
       for (int f = 3; f < NF; f++) s_f[f - 3][ly + 1][lx + 1] = fc[f];
-      dp = ld_at(din, zp, xy_c);
 #pragma unroll
-      for (int f = 0; f < NF; f++) fp[f] = ld_at(fin(f), zp, xy_c);
-      stage_velocity(zp, xy_h, s_u[nu], fp);
-      __syncthreads();
+      for (int f = 0; f < 3; f++) s_u[nu][f][ly + 1][lx + 1] = fp[f];
+      lds_barrier();
       corner_plane(s_u[cu], s_u[nu], s_v[(k + 1) & 1]);
-      __syncthreads();
+      lds_barrier();
 
       if (active) {
         CellFlux<T> cf;
@@ -545,8 +566,12 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
         }
       }
       dc = dp;
+      dp = dpp;
 #pragma unroll
-      for (int f = 0; f < NF; f++) fc[f] = fp[f];
+      for (int f = 0; f < NF; f++) {
+        fc[f] = fp[f];
+        fp[f] = fpp[f];
+      }
     }
     block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + item) * kNP + C * kNS);
   }
