@@ -33,16 +33,15 @@ struct Column {
   uint32_t xy_h;       // its in-plane offset
 };
 
-// Geometry of column item `item` of a run with ntx x nty tiles per plane and
-// chunks of cz planes.  periodic = true takes the periodic rule on x and y
-// (the potential) instead of the hydrodynamic one.
-__device__ __forceinline__ Column make_column(const Grid& g, int ntx, int nty, int cz, int item, bool periodic) {
+// Geometry of a work item of a run with ntx tiles along x.  periodic = true
+// takes the periodic rule on x and y (the potential) instead of the
+// hydrodynamic one.
+__device__ __forceinline__ Column make_column(const Grid& g, int ntx, const WorkItem& it, bool periodic) {
   Column c;
-  const int tx = item % ntx, ty = (item / ntx) % nty, kc = item / (ntx * nty);
-  c.i0 = tx * kTX;
-  c.j0 = ty * kTY;
-  c.k0 = kc * cz;
-  c.k1 = min(c.k0 + cz, g.nz);
+  c.i0 = (it.col % ntx) * kTX;
+  c.j0 = (it.col / ntx) * kTY;
+  c.k0 = it.k0;
+  c.k1 = it.k1;
   c.i = c.i0 + (int)threadIdx.x;
   c.j = c.j0 + (int)threadIdx.y;
   c.active = c.i < g.nx && c.j < g.ny;

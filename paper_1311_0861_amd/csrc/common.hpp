@@ -100,14 +100,27 @@ struct RunDev {
   T* phi;
   DevScalars* sc;
   unsigned row0;       // first row of this run in the partial-sum table
-  int ntx, nty;        // cell tiles per plane and per column
-  int cz, nkc;         // z planes per column chunk, chunks per column
+  int ntx, nty;        // cell tiles along x and y
 };
 
+// One work item of a per-cell kernel: a 64 x 4 tile column (col = tx + ntx
+// ty) of one run over planes [k0, k1), whose partial sums go to partial row
+// row0 + row of that run.
 struct WorkItem {
-  int run;
-  int tile;
+  int run, col, k0, k1, row;
+  int pad[3];
 };
+
+// The item of list slot w, with every field in scalar registers.
+__device__ __forceinline__ WorkItem load_item(const WorkItem* work, unsigned w) {
+  WorkItem it;
+  it.run = __builtin_amdgcn_readfirstlane(work[w].run);
+  it.col = __builtin_amdgcn_readfirstlane(work[w].col);
+  it.k0 = __builtin_amdgcn_readfirstlane(work[w].k0);
+  it.k1 = __builtin_amdgcn_readfirstlane(work[w].k1);
+  it.row = __builtin_amdgcn_readfirstlane(work[w].row);
+  return it;
+}
 
 // The hardware hands consecutive workgroups to the 8 XCDs in turn, and each
 // XCD has its own L2.  A persistent launch gives XCD x one contiguous range of

@@ -36,7 +36,15 @@ using namespace gp;
 
 namespace {
 
-constexpr long kColItems = 512;   // target column items per run
+// Target work items per run of the two work lists (see make_items), by
+// working precision: {stars / DM kernels, gas kernels}.  About as many items
+// as the chip keeps stars / DM workgroups resident (2 per CU in FP64).
+// Finer lists for the gas kernels, which fit 3-4 workgroups per CU, measured
+// slower at 128^3 FP64 (832 items: 0.065 -> 0.073 ms Eulerian, 0.087 -> 0.101
+// ms Lagrangian): the per-item prologue and reduction outweigh the extra
+// resident workgroups.
+constexpr long kItemsFp64[2] = {512, 512};
+constexpr long kItemsFp32[2] = {512, 512};
 constexpr int kTunedKernels = 4;  // the per-cell kernels
 const int kTunedIds[kTunedKernels] = {GP_K_EUL_GAS, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME};
 
@@ -50,8 +58,8 @@ struct RunHost {
   void* phi = nullptr;
   DevScalars* sc = nullptr;
   gp_diag* ring = nullptr;
-  unsigned row0 = 0, ncols = 0;
-  int ntx = 0, nty = 0, cz = 0, nkc = 0;
+  unsigned row0 = 0, nrows = 0;
+  int ntx = 0, nty = 0;
   int cls = 0, slot = 0;  // size class and position inside it
 };
 
@@ -89,8 +97,9 @@ struct gp_batch {
   std::vector<std::pair<void*, size_t>> allocs;
 
   void* runs_dev = nullptr;  // RunDev<T>[nruns]
-  WorkItem* col_work = nullptr;   // tile columns by z chunk (every per-cell kernel, partial rows)
-  unsigned ncol_work = 0;
+  // work lists: [0] stars / DM kernels, [1] gas kernels
+  WorkItem* work[2] = {nullptr, nullptr};
+  unsigned nwork[2] = {0, 0};
   double* partials = nullptr;
   RedItem* red_items = nullptr;
   int nred = 0;
@@ -240,28 +249,58 @@ void enqueue_finalize(gp_batch* b, int advanced, Timer* tm) {
   tdone(tm, GP_K_FINALIZE);
 }
 
+// Work lists.  A run's tile columns (64 x 4 tiles along z) are cut into
+// chunks of cz planes, cz = ncolumns nz / target clamped to 4..32, so the
+// list has about `target` items; list 0 (stars / DM kernels) and list 1 (gas
+// kernels) have their own target.  A workgroup walks its chunk plane by
+// plane, so short chunks re-read more planes at their ends, long ones leave
+// resident workgroup slots idle.  Items go x fastest, then y, then chunk: the
+// columns whose rings overlap run side by side on one XCD.  Item i of a run
+// writes partial row i.
+int chunk_planes(const RunHost& R, int prec, int list) {
+  const long target = (prec == GP_FP64 ? kItemsFp64 : kItemsFp32)[list];
+  return (int)std::max<long>(4, std::min<long>(32, (long)R.ntx * R.nty * R.g.nz / target));
+}
+unsigned items_per_run(const RunHost& R, int prec, int list) {
+  const int cz = chunk_planes(R, prec, list);
+  return (unsigned)(R.ntx * R.nty * ((R.g.nz + cz - 1) / cz));
+}
+void make_items(const RunHost& R, int run, int prec, int list, std::vector<WorkItem>& out) {
+  const int cz = chunk_planes(R, prec, list);
+  int row = 0;
+  for (int k0 = 0; k0 < R.g.nz; k0 += cz)
+    for (int col = 0; col < R.ntx * R.nty; col++) {
+      WorkItem it{};
+      it.run = run;
+      it.col = col;
+      it.k0 = k0;
+      it.k1 = std::min(k0 + cz, R.g.nz);
+      it.row = row++;
+      out.push_back(it);
+    }
+}
+
 template <typename T>
 void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
   switch (k) {
     case GP_K_EUL_GAS:
-      launch_eulerian<T>(runs, b->col_work, b->ncol_work, b->parity, COMP_GAS, nblocks, b->st);
+      launch_eulerian<T>(runs, b->work[1], b->nwork[1], b->parity, COMP_GAS, nblocks, b->st);
       break;
     case GP_K_EUL_BME:
-      launch_eulerian<T>(runs, b->col_work, b->ncol_work, b->parity, COMP_BME, nblocks, b->st);
+      launch_eulerian<T>(runs, b->work[0], b->nwork[0], b->parity, COMP_BME, nblocks, b->st);
       break;
     case GP_K_LAG_GAS:
-      launch_lagrangian<T>(runs, b->col_work, b->ncol_work, b->parity, b->partials, COMP_GAS, nblocks, b->st);
+      launch_lagrangian<T>(runs, b->work[1], b->nwork[1], b->parity, b->partials, COMP_GAS, nblocks, b->st);
       break;
     case GP_K_LAG_BME:
-      launch_lagrangian<T>(runs, b->col_work, b->ncol_work, b->parity, b->partials, COMP_BME, nblocks, b->st);
+      launch_lagrangian<T>(runs, b->work[0], b->nwork[0], b->parity, b->partials, COMP_BME, nblocks, b->st);
       break;
   }
 }
 
 unsigned work_count(const gp_batch* b, int k) {
-  (void)k;
-  return b->ncol_work;
+  return (k == GP_K_EUL_GAS || k == GP_K_LAG_GAS) ? b->nwork[1] : b->nwork[0];
 }
 
 // Time the persistent grid-size candidates of kernel k and keep the fastest.
@@ -330,7 +369,10 @@ void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
 template <typename T>
 void enqueue_prologue(gp_batch* b) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
-  launch_init_partials<T>(runs, b->col_work, b->ncol_work, b->parity, b->partials, b->blocks[GP_K_LAG_BME], b->st);
+  launch_init_partials<T>(runs, b->work[1], b->nwork[1], b->parity, b->partials, COMP_GAS, b->blocks[GP_K_LAG_GAS],
+                          b->st);
+  launch_init_partials<T>(runs, b->work[0], b->nwork[0], b->parity, b->partials, COMP_BME, b->blocks[GP_K_LAG_BME],
+                          b->st);
   enqueue_reduce(b, nullptr);
   enqueue_poisson<T>(b, nullptr);
   enqueue_finalize(b, 0, nullptr);
@@ -438,8 +480,6 @@ RunDev<T> make_rundev(const RunHost& r) {
   d.row0 = r.row0;
   d.ntx = r.ntx;
   d.nty = r.nty;
-  d.cz = r.cz;
-  d.nkc = r.nkc;
   return d;
 }
 
@@ -480,15 +520,12 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     R.ph = Phys{cfgs[r].gamma, cfgs[r].G, cfgs[r].cfl, cfgs[r].eta, cfgs[r].fixed_dt, cfgs[r].t_end};
     R.ntx = (R.g.nx + kTX - 1) / kTX;
     R.nty = (R.g.ny + kTY - 1) / kTY;
-    // Column items: a tile column split into chunks of cz planes,
-    // about kColItems items per run (chunks of 4 to 32 planes).  Each chunk
-    // re-reads the planes just below and above it, so chunks are as long as
-    // the workgroups resident on the chip (2-3 per CU) allow.
-    R.cz = (int)std::max<long>(4, std::min<long>(32, (long)R.ntx * R.nty * R.g.nz / kColItems));
-    R.nkc = (R.g.nz + R.cz - 1) / R.cz;
-    R.ncols = (unsigned)(R.ntx * R.nty * R.nkc);
+    // partial rows: one per item of the longer of the run's two lists (each
+    // component writes its own slots of rows 0.. of its list; the slots of
+    // rows beyond a list stay zero, which the reductions ignore)
+    R.nrows = std::max(items_per_run(R, b->prec, 0), items_per_run(R, b->prec, 1));
     R.row0 = row;
-    row += R.ncols;
+    row += R.nrows;
     const auto key = std::make_tuple(R.g.nx, R.g.ny, R.g.nz, R.g.h, R.ph.G);
     auto it = cls_of.find(key);
     if (it == cls_of.end()) {
@@ -573,19 +610,17 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   b->epot = static_cast<double*>(dalloc(b, std::max(1u, eoff) * sizeof(double), &st));
 
   // work lists, partial rows, reduction items, finalize descriptors
-  std::vector<WorkItem> colw;
+  std::vector<WorkItem> lists[2];
   std::vector<RedItem> items;
   std::vector<FinDesc> fins;
   unsigned soff = 0;
   for (int r = 0; r < nruns; r++) {
     RunHost& R = b->runs[r];
-    // column items, x fastest, then y, then the z chunk: the columns whose
-    // rings overlap run side by side on one XCD
-    for (unsigned c = 0; c < R.ncols; c++) colw.push_back({r, (int)c});
-    const unsigned nscr = std::max(1u, std::min(256u, R.ncols / 16));
-    const unsigned chunk = (R.ncols + nscr - 1) / nscr;
+    for (int l = 0; l < 2; l++) make_items(R, r, b->prec, l, lists[l]);
+    const unsigned nscr = std::max(1u, std::min(256u, R.nrows / 16));
+    const unsigned chunk = (R.nrows + nscr - 1) / nscr;
     for (unsigned c = 0; c < nscr; c++) {
-      const unsigned a = std::min(R.ncols, c * chunk), e = std::min(R.ncols, a + chunk);
+      const unsigned a = std::min(R.nrows, c * chunk), e = std::min(R.nrows, a + chunk);
       items.push_back({R.row0 + a, R.row0 + e});
     }
     FinDesc fd{};
@@ -602,9 +637,9 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     fins.push_back(fd);
     soff += nscr;
   }
-  b->ncol_work = (unsigned)colw.size();
+  for (int l = 0; l < 2; l++) b->nwork[l] = (unsigned)lists[l].size();
   b->nred = (int)items.size();
-  b->col_work = static_cast<WorkItem*>(dalloc(b, colw.size() * sizeof(WorkItem), &st));
+  for (int l = 0; l < 2; l++) b->work[l] = static_cast<WorkItem*>(dalloc(b, lists[l].size() * sizeof(WorkItem), &st));
   b->partials = static_cast<double*>(dalloc(b, (size_t)row * kNP * sizeof(double), &st));
   b->red_items = static_cast<RedItem*>(dalloc(b, items.size() * sizeof(RedItem), &st));
   b->scratch = static_cast<double*>(dalloc(b, (size_t)soff * kNP * sizeof(double), &st));
@@ -619,7 +654,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   auto put = [&](void* dst, const void* src, size_t bytes) {
     if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
   };
-  put(b->col_work, colw.data(), colw.size() * sizeof(WorkItem));
+  for (int l = 0; l < 2; l++) put(b->work[l], lists[l].data(), lists[l].size() * sizeof(WorkItem));
   put(b->red_items, items.data(), items.size() * sizeof(RedItem));
   put(b->fin, fins.data(), fins.size() * sizeof(FinDesc));
   if (b->prec == GP_FP64) {
@@ -674,10 +709,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(b, e, "engine upload");
   for (int k = 0; k < GP_NKERNELS; k++) b->blocks[k] = 0;
-  b->blocks[GP_K_EUL_GAS] = b->ncol_work;
-  b->blocks[GP_K_EUL_BME] = b->ncol_work;
-  b->blocks[GP_K_LAG_GAS] = b->ncol_work;
-  b->blocks[GP_K_LAG_BME] = b->ncol_work;
+  for (int k : kTunedIds) b->blocks[k] = work_count(b, k);
   return GP_OK;
 }
 

@@ -180,11 +180,12 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
   const int lx = threadIdx.x, ly = threadIdx.y;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), item = uniform(work[w].tile);
+    const WorkItem it = load_item(work, w);
+    const int run = it.run;
     const RunDev<T>& R = runs[run];
     const Grid& g = R.g;
-    const Column col = make_column(g, R.ntx, R.nty, R.cz, item, false);
-    const Column pc = make_column(g, R.ntx, R.nty, R.cz, item, true);
+    const Column col = make_column(g, R.ntx, it, false);
+    const Column pc = make_column(g, R.ntx, it, true);
     const bool grav = R.ph.G != 0.0;
     const size_t nxy = (size_t)g.nx * g.ny;
     const double tau_d = R.sc->dt;
@@ -310,11 +311,12 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
   const int lx = threadIdx.x, ly = threadIdx.y;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), item = uniform(work[w].tile);
+    const WorkItem it = load_item(work, w);
+    const int run = it.run;
     const RunDev<T>& R = runs[run];
     const Grid& g = R.g;
-    const Column col = make_column(g, R.ntx, R.nty, R.cz, item, false);
-    const Column pc = make_column(g, R.ntx, R.nty, R.cz, item, true);
+    const Column col = make_column(g, R.ntx, it, false);
+    const Column pc = make_column(g, R.ntx, it, true);
     const bool grav = R.ph.G != 0.0;
     const size_t nxy = (size_t)g.nx * g.ny;
     const double tau_d = R.sc->dt;

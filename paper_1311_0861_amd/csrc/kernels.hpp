@@ -19,10 +19,11 @@ void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork
 template <typename T>
 void launch_lagrangian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, double* partials,
                        int comp, unsigned nblocks, hipStream_t st);
-// Partial rows of a state that has not been advanced (prologue).
+// One component's partial rows of a state that has not been advanced
+// (prologue), over that component's Lagrangian work list.
 template <typename T>
 void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity,
-                          double* partials, unsigned nblocks, hipStream_t st);
+                          double* partials, int comp, unsigned nblocks, hipStream_t st);
 
 // ---- FFT Poisson ---------------------------------------------------------
 template <typename T>

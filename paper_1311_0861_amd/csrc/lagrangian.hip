@@ -367,14 +367,13 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
   const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + kTX * ly;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), item = uniform(work[w].tile);
-    const RunDev<T>& R = runs[run];
+    const WorkItem it = load_item(work, w);
+    const RunDev<T>& R = runs[it.run];
     const Grid& g = R.g;
-    const Column col = make_column(g, R.ntx, R.nty, R.cz, item, false);
+    const Column col = make_column(g, R.ntx, it, false);
     const int k0 = col.k0, k1 = col.k1, i = col.i, j = col.j;
     const bool active = col.active, ring = col.ring;
     const int hr = col.hr, hc = col.hc;
-    const uint32_t nx = (uint32_t)g.nx;
     const size_t nxy = (size_t)g.nx * g.ny;
     const gptr<const double> din = as_global((const double*)R.dens[parity][K::kDens]);
     auto fin = [&](int f) { return as_global((const T*)R.tmp[O0 + f]); };
@@ -573,59 +572,56 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
         fp[f] = fpp[f];
       }
     }
-    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + item) * kNP + C * kNS);
+    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + it.row) * kNP + C * kNS);
   }
 }
 
-// Diagnostics terms of one cell of a state that has not been advanced.
-template <typename T>
-__device__ __forceinline__ void init_cell(Acc& ga, Acc& ba, const RunDev<T>& R, int parity, size_t z, uint32_t xy) {
+// Diagnostics terms of one component of a cell of a state that has not been
+// advanced.
+template <int C, typename T>
+__device__ __forceinline__ void init_cell(Acc& acc, const RunDev<T>& R, int parity, size_t z, uint32_t xy) {
   auto f = [&](int field) { return ld_at(as_global((const T*)R.cur[oidx(field)]), z, xy); };
-  const double rho = ld_at(as_global((const double*)R.dens[parity][0]), z, xy);
-  const double n = ld_at(as_global((const double*)R.dens[parity][1]), z, xy);
-  T m[3], q[3], P[6], W[6];
+  if constexpr (C == COMP_GAS) {
+    const double rho = ld_at(as_global((const double*)R.dens[parity][0]), z, xy);
+    T m[3];
 #pragma unroll
-  for (int d = 0; d < 3; d++) {
-    m[d] = f(GP_MX + d);
-    q[d] = f(GP_QX + d);
-  }
+    for (int d = 0; d < 3; d++) m[d] = f(GP_MX + d);
+    const T E = f(GP_E), e = f(GP_EINT);
+    T ekin;
+    acc.v[S_KAPPA] += (double)gas_kappa(rho, m, E, e, ekin);
+    gas_terms(acc, rho, m, E, e, (T)R.ph.gamma);
+  } else {
+    const double n = ld_at(as_global((const double*)R.dens[parity][1]), z, xy);
+    T q[3], P[6], W[6], Tt[6];
 #pragma unroll
-  for (int a = 0; a < 6; a++) {
-    P[a] = f(GP_PXX + a);
-    W[a] = f(GP_WXX + a);
+    for (int d = 0; d < 3; d++) q[d] = f(GP_QX + d);
+#pragma unroll
+    for (int a = 0; a < 6; a++) {
+      P[a] = f(GP_PXX + a);
+      W[a] = f(GP_WXX + a);
+    }
+    acc.v[S_KAPPA] += (double)bme_kappa(n, q, P, W, Tt);
+    bme_terms(acc, n, q, P, W);
   }
-  const T E = f(GP_E), e = f(GP_EINT);
-  T ekin, Tt[6];
-  ga.v[S_KAPPA] += (double)gas_kappa(rho, m, E, e, ekin);
-  ba.v[S_KAPPA] += (double)bme_kappa(n, q, P, W, Tt);
-  gas_terms(ga, rho, m, E, e, (T)R.ph.gamma);
-  bme_terms(ba, n, q, P, W);
 }
 
-// Partial rows of a state that has not been advanced, over the same column
-// items (and rows) as the Lagrangian kernels.
-template <typename T>
+// Partial rows of one component of a state that has not been advanced, over
+// the same items (and rows) as that component's Lagrangian kernel.
+template <int C, typename T>
 __global__ void __launch_bounds__(kBlock) k_init_partials(const RunDev<T>* __restrict__ runs,
                                                           const WorkItem* __restrict__ work, unsigned nwork,
                                                           int parity, double* __restrict__ partials) {
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
-    const int run = uniform(work[w].run), item = uniform(work[w].tile);
-    const RunDev<T>& R = runs[run];
+    const WorkItem it = load_item(work, w);
+    const RunDev<T>& R = runs[it.run];
     const Grid& g = R.g;
-    const int tx = item % R.ntx, ty = (item / R.ntx) % R.nty, kc = item / (R.ntx * R.nty);
-    const int i = tx * kTX + (int)threadIdx.x, j = ty * kTY + (int)threadIdx.y;
-    const int k0 = kc * R.cz, k1 = min(k0 + R.cz, g.nz);
-    Acc ga, ba;
-    acc_init(ga);
-    acc_init(ba);
-    if (i < g.nx && j < g.ny) {
-      const uint32_t xy = (uint32_t)i + (uint32_t)g.nx * (uint32_t)j;
-      for (int k = k0; k < k1; k++) init_cell<T>(ga, ba, R, parity, (size_t)g.nx * g.ny * k, xy);
-    }
-    const gptr<double> row = as_global(partials) + ((size_t)R.row0 + item) * kNP;
-    block_reduce_store(ga, row + kGasSlots);
-    block_reduce_store(ba, row + kBmeSlots);
+    const Column col = make_column(g, R.ntx, it, false);
+    Acc acc;
+    acc_init(acc);
+    if (col.active)
+      for (int k = col.k0; k < col.k1; k++) init_cell<C, T>(acc, R, parity, (size_t)g.nx * g.ny * k, col.xy_c);
+    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + it.row) * kNP + C * kNS);
   }
 }
 
@@ -639,14 +635,17 @@ void launch_lagrangian(const RunDev<T>* runs, const WorkItem* work, unsigned nwo
 }
 template <typename T>
 void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity,
-                          double* partials, unsigned nblocks, hipStream_t st) {
-  k_init_partials<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
+                          double* partials, int comp, unsigned nblocks, hipStream_t st) {
+  if (comp == COMP_GAS)
+    k_init_partials<COMP_GAS, T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
+  else
+    k_init_partials<COMP_BME, T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
 }
 #define GP_INSTANTIATE(T)                                                                                  \
   template void launch_lagrangian<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, int,        \
                                      unsigned, hipStream_t);                                                \
-  template void launch_init_partials<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, unsigned, \
-                                        hipStream_t);
+  template void launch_init_partials<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, int,      \
+                                        unsigned, hipStream_t);
 GP_INSTANTIATE(double)
 GP_INSTANTIATE(float)
 #undef GP_INSTANTIATE
