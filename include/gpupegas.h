@@ -70,10 +70,13 @@ enum { GP_STAGE_EUL = 0, GP_STAGE_LAG = 1, GP_STAGE_POISSON = 2, GP_STAGE_FINALI
 
 /* Kernels timed by gp_time_kernels.  The Eulerian and Lagrangian stages run
  * one kernel per component: the gas (rho, m, E, e) and the stars / dark
- * matter (n, q, Pi, W), which those stages never couple. */
+ * matter (n, q, Pi, W), which those stages never couple.  The Poisson solve
+ * is three passes over the half spectrum: the x and y transforms (one kernel
+ * per z plane where a plane fits in LDS, else an x and a y kernel, timed
+ * together), the z transforms with the symbol, and the inverse x and y. */
 enum {
-  GP_K_EUL_GAS = 0, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME, GP_K_REDUCE, GP_K_FFT_X_FWD,
-  GP_K_FFT_Y_FWD, GP_K_FFT_Z, GP_K_FFT_Y_INV, GP_K_FFT_X_INV, GP_K_FINALIZE, GP_NKERNELS
+  GP_K_EUL_GAS = 0, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME, GP_K_REDUCE, GP_K_FFT_XY_FWD,
+  GP_K_FFT_Z, GP_K_FFT_XY_INV, GP_K_FINALIZE, GP_NKERNELS
 };
 
 typedef struct {
@@ -168,6 +171,13 @@ gp_status gp_use_graph(gp_sim *sim, int32_t enable);
 gp_status gp_set_launch(gp_sim *sim, int32_t kernel, int32_t blocks);
 gp_status gp_get_launch(gp_sim *sim, int32_t kernel, int32_t *blocks);
 
+/* Form of the x and y transforms of the Poisson solve: GP_FFT_AUTO (one
+ * workgroup per z plane wherever a plane of the half spectrum fits in a
+ * workgroup's LDS, else separate x and y passes) or GP_FFT_LINES (always the
+ * separate passes).  Both compute the same transform, equal to rounding. */
+enum { GP_FFT_AUTO = 0, GP_FFT_LINES = 1 };
+gp_status gp_set_fft_form(gp_sim *sim, int32_t form);
+
 const char *gp_status_str(gp_status s);
 const char *gp_last_error(const gp_sim *sim);
 
@@ -193,6 +203,7 @@ gp_status gp_batch_get_diag(gp_batch *b, int32_t run, gp_diag *out, int32_t max,
 gp_status gp_batch_time_kernels(gp_batch *b, int32_t nsteps, double *ms, int32_t max);
 gp_status gp_batch_set_launch(gp_batch *b, int32_t kernel, int32_t blocks);
 gp_status gp_batch_get_launch(gp_batch *b, int32_t kernel, int32_t *blocks);
+gp_status gp_batch_set_fft_form(gp_batch *b, int32_t form);
 double gp_batch_algorithmic_bytes_per_cell(const gp_batch *b, int32_t kernel);
 int64_t gp_batch_cells(const gp_batch *b);  /* total cells over all runs */
 const char *gp_batch_last_error(const gp_batch *b);

@@ -118,6 +118,7 @@ struct gp_batch {
   unsigned blocks[GP_NKERNELS] = {};
   bool tuned = false;
   bool tune = true;
+  int fft_form = GP_FFT_AUTO;
   std::string last_error;
 };
 
@@ -214,19 +215,33 @@ void tdone(Timer* tm, int k) {
 template <typename T>
 void enqueue_poisson(gp_batch* b, Timer* tm) {
   // each pass runs over every size class before the next pass starts
-  const int passes[5] = {GP_K_FFT_X_FWD, GP_K_FFT_Y_FWD, GP_K_FFT_Z, GP_K_FFT_Y_INV, GP_K_FFT_X_INV};
+  const int passes[3] = {GP_K_FFT_XY_FWD, GP_K_FFT_Z, GP_K_FFT_XY_INV};
   for (int k : passes) {
     tmark(b, tm, k, 0);
     for (SizeClass& c : b->classes) {
       if (c.G == 0.0) continue;
       const FftTables<T> t = tables<T>(c);
       auto* spec = static_cast<cplx<T>*>(c.spec);
+      T* phi = static_cast<T*>(c.phi);
+      const bool plane = c.fg.plane && b->fft_form == GP_FFT_AUTO;
       switch (k) {
-        case GP_K_FFT_X_FWD: launch_fft_x_fwd<T>(c.src, b->parity, spec, c.fg, t, b->st); break;
-        case GP_K_FFT_Y_FWD: launch_fft_y<T>(spec, c.fg, t, false, b->st); break;
-        case GP_K_FFT_Z: launch_fft_z_green<T>(spec, c.fg, t, b->epot + c.eoff, b->st); break;
-        case GP_K_FFT_Y_INV: launch_fft_y<T>(spec, c.fg, t, true, b->st); break;
-        case GP_K_FFT_X_INV: launch_fft_x_inv<T>(spec, static_cast<T*>(c.phi), c.fg, t, b->st); break;
+        case GP_K_FFT_XY_FWD:
+          if (plane) {
+            launch_fft_xy_fwd<T>(c.src, b->parity, spec, c.fg, t, b->st);
+          } else {
+            launch_fft_x_fwd<T>(c.src, b->parity, spec, c.fg, t, b->st);
+            launch_fft_y<T>(spec, c.fg, t, false, b->st);
+          }
+          break;
+        case GP_K_FFT_Z: launch_fft_z_green<T>(spec, c.fg, t, b->epot + c.eoff, plane, b->st); break;
+        case GP_K_FFT_XY_INV:
+          if (plane) {
+            launch_fft_xy_inv<T>(spec, phi, c.fg, t, b->st);
+          } else {
+            launch_fft_y<T>(spec, c.fg, t, true, b->st);
+            launch_fft_x_inv<T>(spec, phi, c.fg, t, b->st);
+          }
+          break;
       }
     }
     tmark(b, tm, k, 1);
@@ -561,6 +576,12 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
 
   // size classes: contiguous source / potential / spectrum, FFT tables
   const int maxpts = 32768 / (int)(2 * es);
+  int dev = 0, lds_dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    lds_dev = 0;
+  const int lds_max = std::min(kPlaneLdsMax, lds_dev);
+  bool planes_ready = false;
   unsigned eoff = 0;
   for (SizeClass& c : b->classes) {
     FftGeom& f = c.fg;
@@ -582,6 +603,17 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     };
     f.cols_y = even_cols(f.ay.L);
     f.cols_z = even_cols(f.az.L);
+    // x and y transforms of a whole z plane per workgroup where it fits
+    f.pp = f.ax.L | 1;  // odd row pitch: lanes on neighbouring rows hit other banks
+    f.plane = c.G != 0.0 && plane_lds_bytes(f, 2 * es) <= (size_t)lds_max;
+    if (f.plane && !planes_ready) {
+      // one limit for every size class: the kernels are shared
+      const hipError_t e =
+          b->prec == GP_FP64 ? fft_plane_prepare<double>(lds_max) : fft_plane_prepare<float>(lds_max);
+      planes_ready = e == hipSuccess;
+      if (!planes_ready) (void)hipGetLastError();
+    }
+    if (!planes_ready) f.plane = 0;
     f.green_scale = -4.0 * M_PI * c.G * c.h * c.h / 6.0;
     f.norm = 2.0 / ((double)f.nx * f.ny * f.nz);
     const size_t nc = (size_t)c.nx * c.ny * c.nz, R = c.runs.size();
@@ -841,6 +873,15 @@ gp_status engine_time_kernels(gp_batch* b, int32_t nsteps, double* ms, int32_t m
   return GP_OK;
 }
 
+gp_status engine_set_fft_form(gp_batch* b, int32_t form) {
+  if (form != GP_FFT_AUTO && form != GP_FFT_LINES) return GP_E_INVALID;
+  if (form != b->fft_form) {
+    b->fft_form = form;
+    drop_graphs(b);
+  }
+  return GP_OK;
+}
+
 gp_status engine_set_launch(gp_batch* b, int32_t kernel, int32_t blocks) {
   int which = -1;
   for (int q = 0; q < kTunedKernels; q++)
@@ -863,11 +904,9 @@ double fft_bytes_per_cell(const gp_batch* b, int k) {
     const double spec = 2.0 * es * (R.g.nx / 2 + 1) / R.g.nx;
     double v = 0.0;
     switch (k) {
-      case GP_K_FFT_X_FWD: v = 16.0 + spec; break;  // reads rho and n (FP64)
-      case GP_K_FFT_X_INV: v = spec + es; break;
-      case GP_K_FFT_Y_FWD:
-      case GP_K_FFT_Z:
-      case GP_K_FFT_Y_INV: v = 2.0 * spec; break;
+      case GP_K_FFT_XY_FWD: v = 16.0 + spec; break;  // reads rho and n (FP64)
+      case GP_K_FFT_XY_INV: v = spec + es; break;
+      case GP_K_FFT_Z: v = 2.0 * spec; break;
     }
     bytes += v * (double)R.g.ncell;
   }
@@ -892,7 +931,7 @@ double engine_bytes_per_cell(const gp_batch* b, int32_t kernel) {
     case GP_K_FINALIZE: return 0.0;
     case -1: {
       double t = eul_gas + eul_bme + lag_gas + lag_bme;
-      for (int k = GP_K_FFT_X_FWD; k <= GP_K_FFT_X_INV; k++) t += fft_bytes_per_cell(b, k);
+      for (int k = GP_K_FFT_XY_FWD; k <= GP_K_FFT_XY_INV; k++) t += fft_bytes_per_cell(b, k);
       return t;
     }
     default: return fft_bytes_per_cell(b, kernel);
@@ -1019,6 +1058,11 @@ gp_status gp_set_launch(gp_sim* s, int32_t kernel, int32_t blocks) {
   return engine_set_launch(s, kernel, blocks);
 }
 
+gp_status gp_set_fft_form(gp_sim* s, int32_t form) {
+  if (!s) return GP_E_INVALID;
+  return engine_set_fft_form(s, form);
+}
+
 gp_status gp_get_launch(gp_sim* s, int32_t kernel, int32_t* blocks) {
   if (!s || !blocks || kernel < 0 || kernel >= GP_NKERNELS) return GP_E_INVALID;
   *blocks = (int32_t)s->blocks[kernel];
@@ -1088,6 +1132,11 @@ gp_status gp_batch_time_kernels(gp_batch* b, int32_t nsteps, double* ms, int32_t
 gp_status gp_batch_set_launch(gp_batch* b, int32_t kernel, int32_t blocks) {
   if (!b) return GP_E_INVALID;
   return engine_set_launch(b, kernel, blocks);
+}
+
+gp_status gp_batch_set_fft_form(gp_batch* b, int32_t form) {
+  if (!b) return GP_E_INVALID;
+  return engine_set_fft_form(b, form);
 }
 
 gp_status gp_batch_get_launch(gp_batch* b, int32_t kernel, int32_t* blocks) {

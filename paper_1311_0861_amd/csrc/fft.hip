@@ -3,28 +3,33 @@
 //   Phi^(0) = 0  (periodic, zero-mean potential; the printed symbol lacks the
 //   minus sign that Laplace(Phi) = 4 pi G s requires).
 //
-// Five passes over a half spectrum C[z][y][kx], kx in [0, nx/2] (row pitch px):
-//   x forward  : the source s = rho + n - <rho + n> is formed in FP64 from the
+// Passes over a half spectrum of rows of px = nx/2 + 1 values, kx in [0, nx/2],
+// stored C[z][ky][kx] by the line passes and C[ky][z][kx] by the plane passes:
+//   xy forward : the source s = rho + n - <rho + n> is formed in FP64 from the
 //                densities (the constant leaves Phi unchanged, as its zero mode
 //                is dropped, and keeping it out of an FP32 transform keeps the
 //                other modes accurate); real rows of length nx -> complex FFT
-//                of length nx/2 on packed (even, odd) pairs, then the even/odd
-//                split to nx/2+1 bins;
-//   y forward  : columns of C along y;
+//                of length nx/2 on packed (even, odd) pairs, the even/odd
+//                split to nx/2+1 bins, then the columns along y;
 //   z fused    : forward along z, multiply by the symbol (and the inverse
 //                normalisation), accumulate sum |s^|^2 G for the potential
 //                energy, inverse along z -- one read and one write of C;
-//   y inverse, x inverse (complex-to-real).
+//   xy inverse : columns along y, then the complex-to-real rows.
+// Where a whole z plane of the spectrum fits in LDS, one workgroup per plane
+// does both of its transforms (three passes over C in all); otherwise the x
+// and y transforms are separate passes (five in all).
 // Each workgroup stages whole lines in LDS and runs a Stockham autosort FFT
 // (radices 8, 4, 3, 2; output in natural order) with all butterflies of a stage
 // held in registers between two barriers, so the stages work in place.
 // Twiddles come from tables computed on the host in FP64.
+#include "column.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace gp {
 
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 256;     // x passes and column passes
+constexpr int kPlaneThreads = 1024;  // xy plane passes
 
 template <typename T>
 __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
@@ -84,31 +89,61 @@ __device__ __forceinline__ void dft_small(cplx<T> v[R], bool inv) {
   }
 }
 
-// Largest number of complex points one workgroup stages (32 KiB of LDS).
+// Largest number of complex points one workgroup of the line passes stages
+// (32 KiB of LDS), and of the plane passes (the whole LDS of a workgroup).
 template <typename T>
 constexpr int max_points() {
   return 32768 / (int)sizeof(cplx<T>);
 }
+template <typename T>
+constexpr int plane_points() {
+  return kPlaneLdsMax / (int)sizeof(cplx<T>);
+}
 
-// One Stockham stage of radix R on `lines` lines of length L (line pitch lp),
-// in place: reads to registers, barrier, writes, barrier.
-template <typename T, int R>
-__device__ void fft_stage(cplx<T>* buf, int lines, int L, int lp, int Ns, const cplx<T>* tw, bool inv) {
-  constexpr int MAXB = (max_points<T>() / R + kFftThreads - 1) / kFftThreads;
+// Division by a workgroup-uniform d through a multiply-high, exact while
+// q * d < 2^32 (the LDS indexes it divides stay below 2^15 and the divisors
+// below 2^14): one instruction where the compiler's division by a run-time
+// value takes about twenty.
+struct FastDiv {
+  uint32_t d, m;
+  __device__ explicit FastDiv(uint32_t dv) : d(dv), m(dv == 1 ? 0u : 0xffffffffu / dv + 1u) {}
+  __device__ __forceinline__ uint32_t div(uint32_t q) const { return d == 1 ? q : __umulhi(q, m); }
+};
+
+// One Stockham stage of radix R on `lines` lines of length L, in place: reads
+// to registers, barrier, writes, barrier.  Element j of line l sits at
+// buf[l * ls + j * es]; at most PMAX points (lines * L) per call.  LF puts the
+// line index fastest across the threads (for lines that are LDS columns, so
+// that neighbouring lanes touch neighbouring words).
+template <typename T, int R, int NT, int PMAX, bool LF>
+__device__ void fft_stage(cplx<T>* buf, int lines, int L, int ls, int es, int Ns, const cplx<T>* tw, bool inv) {
+  constexpr int MAXB = (PMAX / R + NT - 1) / NT;
   const int nb = L / R;
   const int total = lines * nb;
   const int tstep = L / (Ns * R);
+  const FastDiv dmaj(LF ? lines : nb), dns(Ns);
   cplx<T> v[MAXB][R];
+  // the thread's indexes are the same in every stage of a radix; computed
+  // here rather than hoisted out of the stage loop, where they would all stay
+  // live for the whole transform
+  const int tid = (int)fresh(threadIdx.x);
 #pragma unroll
   for (int b = 0; b < MAXB; b++) {
-    const int q = threadIdx.x + b * kFftThreads;
+    const int q = tid + b * NT;
     if (q < total) {
-      const int line = q / nb, jj = q - line * nb;
-      const int kk = jj % Ns;
-      const cplx<T>* base = buf + line * lp;
+      int line, jj;
+      if constexpr (LF) {
+        jj = (int)dmaj.div(q);
+        line = q - jj * lines;
+      } else {
+        line = (int)dmaj.div(q);
+        jj = q - line * nb;
+      }
+      const int kk = jj - (int)dns.div(jj) * Ns;
+      const cplx<T>* base = buf + line * ls;
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        cplx<T> x = base[jj + r * nb];
+        cplx<T> x = base[(jj + r * nb) * es];
         if (r > 0) {
           cplx<T> w = tw[kk * r * tstep];
           if (inv) w.y = -w.y;
@@ -119,82 +154,159 @@ __device__ void fft_stage(cplx<T>* buf, int lines, int L, int lp, int Ns, const 
       dft_small<T, R>(v[b], inv);
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int b = 0; b < MAXB; b++) {
-    const int q = threadIdx.x + b * kFftThreads;
+    // recomputed rather than held over the barrier beside the butterflies
+    const int q = (int)fresh(threadIdx.x) + b * NT;
     if (q < total) {
-      const int line = q / nb, jj = q - line * nb;
-      const int kk = jj % Ns;
-      cplx<T>* base = buf + line * lp;
-      const int d0 = (jj / Ns) * Ns * R + kk;
+      int line, jj;
+      if constexpr (LF) {
+        jj = (int)dmaj.div(q);
+        line = q - jj * lines;
+      } else {
+        line = (int)dmaj.div(q);
+        jj = q - line * nb;
+      }
+      const int jn = (int)dns.div(jj);
+      const int kk = jj - jn * Ns;
+      cplx<T>* base = buf + line * ls;
+      const int d0 = jn * Ns * R + kk;
 #pragma unroll
-      for (int r = 0; r < R; r++) base[d0 + r * Ns] = v[b][r];
+      for (int r = 0; r < R; r++) base[(d0 + r * Ns) * es] = v[b][r];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
-template <typename T>
-__device__ void lds_fft(cplx<T>* buf, int lines, int lp, const FftAxis& ax, const cplx<T>* tw, bool inv) {
+template <typename T, int NT, int PMAX, bool LF>
+__device__ void lds_fft(cplx<T>* buf, int lines, int ls, int es, const FftAxis& ax, const cplx<T>* tw, bool inv) {
   int Ns = 1;
   for (int s = 0; s < ax.nst; s++) {
     const int R = ax.rad[s];
     if (R == 8)
-      fft_stage<T, 8>(buf, lines, ax.L, lp, Ns, tw, inv);
+      fft_stage<T, 8, NT, PMAX, LF>(buf, lines, ax.L, ls, es, Ns, tw, inv);
     else if (R == 4)
-      fft_stage<T, 4>(buf, lines, ax.L, lp, Ns, tw, inv);
+      fft_stage<T, 4, NT, PMAX, LF>(buf, lines, ax.L, ls, es, Ns, tw, inv);
     else if (R == 3)
-      fft_stage<T, 3>(buf, lines, ax.L, lp, Ns, tw, inv);
+      fft_stage<T, 3, NT, PMAX, LF>(buf, lines, ax.L, ls, es, Ns, tw, inv);
     else
-      fft_stage<T, 2>(buf, lines, ax.L, lp, Ns, tw, inv);
+      fft_stage<T, 2, NT, PMAX, LF>(buf, lines, ax.L, ls, es, Ns, tw, inv);
     Ns *= R;
   }
 }
 
+// contiguous lines of the line passes (pitch lp odd: neighbouring lanes take
+// neighbouring lines, whose words fall in different banks)
 template <typename T>
+__device__ __forceinline__ void line_fft(cplx<T>* buf, int lines, int lp, const FftAxis& ax, const cplx<T>* tw,
+                                         bool inv) {
+  lds_fft<T, kFftThreads, max_points<T>(), true>(buf, lines, lp, 1, ax, tw, inv);
+}
+
+template <int NT, typename T>
 __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* src, int n) {
-  for (int t = threadIdx.x; t < n; t += kFftThreads) dst[t] = src[t];
+  for (int t = threadIdx.x; t < n; t += NT) dst[t] = src[t];
+}
+
+// Load through a global-address-space pointer (plain loads of pointers that
+// were read from memory compile to flat loads, which also count against the
+// LDS wait counter).
+template <typename V>
+__device__ __forceinline__ V gload(const V* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(1))) V*)p;
+#else
+  return *p;  // host pass: parsed, never run
+#endif
+}
+
+// (even, odd) pair of FP64 values, 16-byte aligned (a clang vector type: the
+// HIP double2 class copies through a generic-address-space reference)
+typedef double dpair __attribute__((ext_vector_type(2)));
+
+// Copies n values from global memory into LDS with up to KB loads in flight
+// per thread: get(q) loads (and converts) value q, put(q, v) stores it.  get
+// is called for every slot of a batch with q clamped to n - 1, so that the
+// loads issue back to back without branches; only the stores are guarded.
+template <int NT, int KB, typename V, typename Get, typename Put>
+__device__ __forceinline__ void staged_copy(int n, Get get, Put put) {
+  for (int q0 = threadIdx.x; q0 < n; q0 += KB * NT) {
+    V v[KB];
+#pragma unroll
+    for (int u = 0; u < KB; u++) v[u] = get(min(q0 + u * NT, n - 1));
+#pragma unroll
+    for (int u = 0; u < KB; u++) {
+      const int q = q0 + u * NT;
+      if (q < n) put(q, v[u]);
+    }
+  }
+}
+
+// Real-to-complex split of a packed transform Z (pairs (even, odd) of a real
+// row of length 2M): bin k from Z[k] and Z[M - k], with w = exp(-2 pi i k / 2M).
+//   X[k] = E + w O,  E = (Z[k] + conj Z[M-k]) / 2,  O = -i (Z[k] - conj Z[M-k]) / 2
+template <typename T>
+__device__ __forceinline__ cplx<T> split_fwd(cplx<T> zk, cplx<T> zc, cplx<T> w) {
+  zc.y = -zc.y;
+  const cplx<T> E = {T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
+  const cplx<T> O = {T(0.5) * (zk.y - zc.y), T(-0.5) * (zk.x - zc.x)};
+  return cadd(E, cmul(w, O));
+}
+// Its inverse: Z[k] = E + i O,  E = (X[k] + conj X[M-k]) / 2,
+// O = (X[k] - conj X[M-k]) / 2 * conj(w).
+template <typename T>
+__device__ __forceinline__ cplx<T> split_inv(cplx<T> xk, cplx<T> xc, cplx<T> w) {
+  xc.y = -xc.y;
+  const cplx<T> E = {T(0.5) * (xk.x + xc.x), T(0.5) * (xk.y + xc.y)};
+  w.y = -w.y;
+  const cplx<T> O = cmul({T(0.5) * (xk.x - xc.x), T(0.5) * (xk.y - xc.y)}, w);
+  return {E.x - O.y, E.y + O.x};
 }
 
 // ---- x forward: rows of s (length nx) -> C rows (nx/2 + 1 bins) -------------
 template <typename T>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __restrict__ src, int parity,
                                                            cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int M = f.ax.L;
+  const int M = f.ax.L, xp = M | 1;  // odd row pitch
   const int RB = f.rows_per_block;
-  cplx<T>* tw = lds + RB * M;
+  cplx<T>* tw = lds + RB * xp;
   cplx<T>* wn = tw + M;
   const int rows_run = f.ny * f.nz;
   const int nrows = rows_run * f.nruns;
   const int row0 = blockIdx.x * RB;
   const int rows = min(RB, nrows - row0);
-  load_twiddles(tw, t.tw_x, M);
-  load_twiddles(wn, t.wn_x, M + 1);
+  load_twiddles<kFftThreads>(tw, t.tw_x, M);
+  load_twiddles<kFftThreads>(wn, t.wn_x, M + 1);
+  const FastDiv dm(M), dm1(M + 1);
   // packed (even, odd) pairs of each row of s
-  for (int q = threadIdx.x; q < rows * M; q += kFftThreads) {
-    const int row = row0 + q / M, m = q % M;
-    const int slot = row / rows_run;
-    const size_t c = (size_t)(row - slot * rows_run) * f.nx + 2 * m;
-    const SrcSlot& S = src[slot];
-    const double shift = S.sc->shift;
-    const double* rho = S.rho[parity];
-    const double* nb = S.nb[parity];
-    lds[q] = {(T)(rho[c] + nb[c] - shift), (T)(rho[c + 1] + nb[c + 1] - shift)};
-  }
+  staged_copy<kFftThreads, 4, cplx<T>>(
+      rows * M,
+      [&](int q) {
+        const int rq = (int)dm.div(q);
+        const int row = row0 + rq, m = q - rq * M;
+        const int slot = row / rows_run;  // may exceed the range of FastDiv
+        const size_t c = (size_t)(row - slot * rows_run) * f.nx + 2 * m;
+        const SrcSlot& S = src[slot];
+        const double shift = gload(&S.sc->shift);
+        const dpair a = gload(reinterpret_cast<const dpair*>(S.rho[parity] + c));
+        const dpair b = gload(reinterpret_cast<const dpair*>(S.nb[parity] + c));
+        return cplx<T>{(T)(a.x + b.x - shift), (T)(a.y + b.y - shift)};
+      },
+      [&](int q, cplx<T> v) {
+        const int rq = (int)dm.div(q);
+        lds[rq * xp + q - rq * M] = v;
+      });
   __syncthreads();
-  lds_fft(lds, rows, M, f.ax, tw, false);
+  line_fft(lds, rows, xp, f.ax, tw, false);
   // even/odd split: X[k] = E[k] + W_N^k O[k]
   for (int q = threadIdx.x; q < rows * (M + 1); q += kFftThreads) {
-    const int rr = q / (M + 1), k = q - rr * (M + 1);
-    const cplx<T> zk = lds[rr * M + (k == M ? 0 : k)];
-    cplx<T> zc = lds[rr * M + (k == 0 ? 0 : M - k)];
-    zc.y = -zc.y;
-    const cplx<T> E = {T(0.5) * (zk.x + zc.x), T(0.5) * (zk.y + zc.y)};
-    const cplx<T> O = {T(0.5) * (zk.y - zc.y), T(-0.5) * (zk.x - zc.x)};  // -i (zk - zc) / 2
-    spec[(size_t)(row0 + rr) * f.px + k] = cadd(E, cmul(wn[k], O));
+    const int rr = (int)dm1.div(q), k = q - rr * (M + 1);
+    const cplx<T> zk = lds[rr * xp + (k == M ? 0 : k)];
+    const cplx<T> zc = lds[rr * xp + (k == 0 ? 0 : M - k)];
+    spec[(size_t)(row0 + rr) * f.px + k] = split_fwd(zk, zc, wn[k]);
   }
 }
 
@@ -202,79 +314,110 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __rest
 template <typename T>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __restrict__ spec, T* __restrict__ phi,
                                                            FftGeom f, FftTables<T> t) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int M = f.ax.L;
+  const int M = f.ax.L, xp = M | 1;  // odd row pitch
   const int RB = f.rows_per_block;
-  cplx<T>* xin = lds + RB * M;          // RB rows of M + 1 bins
+  cplx<T>* xin = lds + RB * xp;         // RB rows of M + 1 bins
   cplx<T>* tw = xin + RB * (M + 1);
   cplx<T>* wn = tw + M;
   const int nrows = f.ny * f.nz * f.nruns;
   const int row0 = blockIdx.x * RB;
   const int rows = min(RB, nrows - row0);
-  load_twiddles(tw, t.tw_x, M);
-  load_twiddles(wn, t.wn_x, M + 1);
-  for (int q = threadIdx.x; q < rows * (M + 1); q += kFftThreads) xin[q] = spec[(size_t)row0 * f.px + q];
+  load_twiddles<kFftThreads>(tw, t.tw_x, M);
+  load_twiddles<kFftThreads>(wn, t.wn_x, M + 1);
+  const FastDiv dm(M);
+  staged_copy<kFftThreads, 4, cplx<T>>(
+      rows * (M + 1), [&](int q) { return gload(spec + (size_t)row0 * f.px + q); },
+      [&](int q, cplx<T> v) { xin[q] = v; });
   __syncthreads();
-  // Z[k] = E[k] + i O[k],  E = (X_k + conj X_{M-k}) / 2,  O = (X_k - conj X_{M-k}) / 2 * W_N^{-k}
   for (int q = threadIdx.x; q < rows * M; q += kFftThreads) {
-    const int rr = q / M, k = q - rr * M;
-    const cplx<T> xk = xin[rr * (M + 1) + k];
-    cplx<T> xc = xin[rr * (M + 1) + M - k];
-    xc.y = -xc.y;
-    const cplx<T> E = {T(0.5) * (xk.x + xc.x), T(0.5) * (xk.y + xc.y)};
-    cplx<T> w = wn[k];
-    w.y = -w.y;
-    const cplx<T> O = cmul({T(0.5) * (xk.x - xc.x), T(0.5) * (xk.y - xc.y)}, w);
-    lds[rr * M + k] = {E.x - O.y, E.y + O.x};
+    const int rr = (int)dm.div(q), k = q - rr * M;
+    lds[rr * xp + k] = split_inv(xin[rr * (M + 1) + k], xin[rr * (M + 1) + M - k], wn[k]);
   }
   __syncthreads();
-  lds_fft(lds, rows, M, f.ax, tw, true);
+  line_fft(lds, rows, xp, f.ax, tw, true);
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(phi) + (size_t)row0 * M;
-  for (int q = threadIdx.x; q < rows * M; q += kFftThreads) dst[q] = lds[q];
+  for (int q = threadIdx.x; q < rows * M; q += kFftThreads) {
+    const int rq = (int)dm.div(q);
+    dst[q] = lds[rq * xp + q - rq * M];
+  }
 }
 
 // ---- column passes (y, and the fused z pass) -------------------------------
 // A workgroup takes `cb` consecutive kx columns and one index of the other
 // transverse axis of one run; line j of column c lives at base + j * stride + c
 // with base = run * run_stride + o * outer_stride + kx0 for outer index
-// run * outer_div + o.
+// run * outer_div + o.  The chunks of one outer line read neighbouring words
+// (rows of the spectrum are not cache-line aligned), so the block index puts
+// all chunks of a line on one XCD: blocks go round-robin over the 8 XCDs, and
+// in each group of 8 lines the chunk varies slowest.
+struct ColBlock {
+  int chunk, oline;
+};
+__device__ __forceinline__ ColBlock col_block(int b, int nchunks, int nolines) {
+  const int gsz = 8 * nchunks;
+  const int g = b / gsz, rem = b - g * gsz;
+  const int r = min(8, nolines - g * 8);  // lines in this group
+  const int chunk = rem / r;
+  return {chunk, g * 8 + (rem - chunk * r)};
+}
+
 template <typename T, int MODE>  // MODE 0: forward, 1: inverse, 2: forward * symbol * inverse
 __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t,
                                                          FftAxis ax, const cplx<T>* __restrict__ twg, int cb,
                                                          size_t stride, size_t outer_stride, int outer_div,
                                                          size_t run_stride, double* __restrict__ epot_partials) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int L = ax.L;
-  const int lp = L + 1;  // padded line pitch
+  const int lp = L | 1;  // odd line pitch
   cplx<T>* tw = lds + cb * lp;
   const int nchunks = (f.px + cb - 1) / cb;
-  const int chunk = blockIdx.x % nchunks;
-  const int oline = blockIdx.x / nchunks;
+  const ColBlock cbk = col_block(blockIdx.x, nchunks, (int)(gridDim.x / nchunks));
+  const int chunk = cbk.chunk, oline = cbk.oline;
   const int outer = oline % outer_div;
   const int kx0 = chunk * cb;
   const int ncols = min(cb, f.px - kx0);
-  load_twiddles(tw, twg, L);
-  cplx<T>* base = spec + (size_t)(oline / outer_div) * run_stride + (size_t)outer * outer_stride + kx0;
-  for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
-    const int c = q % cb, j = q / cb;
-    lds[c * lp + j] = (c < ncols) ? base[(size_t)j * stride + c] : cplx<T>{T(0), T(0)};
+  load_twiddles<kFftThreads>(tw, twg, L);
+  const FastDiv dcb(cb), dl(L);
+  // z pass: the symbol's factors D(kz) and D(kx) D(ky) of this block
+  double* gz = reinterpret_cast<double*>(tw + L);
+  double* gxy = gz + L;
+  if constexpr (MODE == 2) {
+    const double dy = gload(t.dy + outer);
+    for (int q = threadIdx.x; q < L + ncols; q += kFftThreads) {
+      if (q < L)
+        gz[q] = gload(t.dz + q);
+      else
+        gxy[q - L] = gload(t.dx + kx0 + q - L) * dy;
+    }
   }
+  cplx<T>* base = spec + (size_t)(oline / outer_div) * run_stride + (size_t)outer * outer_stride + kx0;
+  staged_copy<kFftThreads, 4, cplx<T>>(
+      cb * L,
+      [&](int q) {
+        const int j = (int)dcb.div(q), c = q - j * cb;
+        const cplx<T> v = gload(base + (size_t)j * stride + min(c, ncols - 1));
+        return (c < ncols) ? v : cplx<T>{T(0), T(0)};
+      },
+      [&](int q, cplx<T> v) {
+        const int j = (int)dcb.div(q), c = q - j * cb;
+        lds[c * lp + j] = v;
+      });
   __syncthreads();
-  lds_fft(lds, cb, lp, ax, tw, MODE == 1);
+  line_fft(lds, cb, lp, ax, tw, MODE == 1);
   if constexpr (MODE == 2) {
     // z pass: outer = ky, line position = kz, column = kx
     __shared__ double red[kFftThreads / 64];
     double ep = 0.0;
-    const double dy = t.dy[outer];
     for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
-      const int c = q / L, kz = q - c * L;
+      const int c = (int)dl.div(q), kz = q - c * L;
       if (c >= ncols) continue;
       const int kx = kx0 + c;
       cplx<T>& v = lds[c * lp + kz];
       double gk = 0.0;
-      if (kx != 0 || outer != 0 || kz != 0) gk = f.green_scale / (1.0 - t.dx[kx] * dy * t.dz[kz]);
+      if (kx != 0 || outer != 0 || kz != 0) gk = f.green_scale / (1.0 - gxy[c] * gz[kz]);
       const double w = (kx == 0 || 2 * kx == f.nx) ? 1.0 : 2.0;  // Hermitian half spectrum
       ep += w * gk * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
       const T gs = (T)(gk * f.norm);
@@ -290,17 +433,185 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
       for (int w = 0; w < kFftThreads / 64; w++) s += red[w];
       epot_partials[blockIdx.x] = s;
     }
-    lds_fft(lds, cb, lp, ax, tw, true);
+    line_fft(lds, cb, lp, ax, tw, true);
   }
   for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
-    const int c = q % cb, j = q / cb;
+    const int j = (int)dcb.div(q), c = q - j * cb;
     if (c < ncols) base[(size_t)j * stride + c] = lds[c * lp + j];
   }
 }
 
+// ---- xy plane passes: both transverse transforms of one z plane in LDS -----
+// A workgroup holds the plane as ny rows of pitch pp >= M + 1 complex values
+// (M = nx / 2).  The split leaves X[0] and X[M] of every row real, so they
+// share column 0 as X[0] + i X[M]: the y transforms then run on M columns, and
+// the spectra of the two real columns are separated afterwards from
+// W = FFT_y(X[0] + i X[M]):
+//   Y0[ky] = (W[ky] + conj W[-ky]) / 2,  YM[ky] = -i (W[ky] - conj W[-ky]) / 2.
+// The inverse packs C[ky][0] + i C[ky][M] into column 0 the same way (both are
+// spectra of real columns, so their inverse transforms come out real).
+template <typename T>
+struct PlaneLds {
+  cplx<T>* pl;   // ny x pp plane
+  cplx<T>* twx;  // M
+  cplx<T>* wn;   // M + 1
+  cplx<T>* twy;  // ny
+};
+
+template <typename T>
+__device__ __forceinline__ PlaneLds<T> plane_lds(const FftGeom& f, const FftTables<T>& t) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  PlaneLds<T> s;
+  const int M = f.ax.L;
+  s.pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  s.twx = s.pl + f.ny * f.pp;
+  s.wn = s.twx + M;
+  s.twy = s.wn + M + 1;
+  load_twiddles<kPlaneThreads>(s.twx, t.tw_x, M);
+  load_twiddles<kPlaneThreads>(s.wn, t.wn_x, M + 1);
+  load_twiddles<kPlaneThreads>(s.twy, t.tw_y, f.ny);
+  return s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __restrict__ src, int parity,
+                                                             cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t) {
+  constexpr int NT = kPlaneThreads, PM = plane_points<T>();
+  const PlaneLds<T> s = plane_lds(f, t);
+  const int M = f.ax.L, ny = f.ny, pp = f.pp;
+  const FastDiv dm(M), dm1(M + 1), dh(M / 2 + 1);
+  const int plane = blockIdx.x;  // run * nz + z
+  const int slot = plane / f.nz, z = plane - slot * f.nz;
+  const SrcSlot& S = src[slot];
+  const double shift = gload(&S.sc->shift);
+  const size_t off = (size_t)z * ny * f.nx;
+  const dpair* rho = reinterpret_cast<const dpair*>(S.rho[parity] + off);
+  const dpair* nb = reinterpret_cast<const dpair*>(S.nb[parity] + off);
+  // packed (even, odd) pairs of each row of s
+  staged_copy<NT, 8, cplx<T>>(
+      ny * M,
+      [&](int q) {
+        const dpair a = gload(rho + q), c = gload(nb + q);
+        return cplx<T>{(T)(a.x + c.x - shift), (T)(a.y + c.y - shift)};
+      },
+      [&](int q, cplx<T> v) {
+        const int y = (int)dm.div(q), m = q - y * M;
+        s.pl[y * pp + m] = v;
+      });
+  lds_barrier();
+  lds_fft<T, NT, PM, true>(s.pl, ny, pp, 1, f.ax, s.twx, false);
+  // split of each row, pairs (k, M - k) by one thread; X[0] + i X[M] in column 0
+  const int H = M / 2 + 1;
+  for (int q = threadIdx.x; q < ny * H; q += NT) {
+    const int y = (int)dh.div(q), k = q - y * H;
+    cplx<T>* row = s.pl + y * pp;
+    if (k == 0) {
+      const cplx<T> z0 = row[0];
+      row[0] = {z0.x + z0.y, z0.x - z0.y};
+    } else {
+      const cplx<T> a = row[k], b = row[M - k];
+      row[k] = split_fwd(a, b, s.wn[k]);
+      if (2 * k != M) row[M - k] = split_fwd(b, a, s.wn[M - k]);
+    }
+  }
+  lds_barrier();
+  lds_fft<T, NT, PM, true>(s.pl, M, 1, pp, f.ay, s.twy, false);
+  // spectrum rows ky-major: C[run][ky][z][kx], so that the z pass reads
+  // contiguous blocks
+  cplx<T>* out = spec + ((size_t)slot * ny * f.nz + z) * f.px;
+  const size_t kys = (size_t)f.nz * f.px;
+  for (int q = threadIdx.x; q < ny * (M + 1); q += NT) {
+    const int ky = (int)dm1.div(q), kx = q - ky * (M + 1);
+    cplx<T> v;
+    if (kx > 0 && kx < M) {
+      v = s.pl[ky * pp + kx];
+    } else {
+      const cplx<T> w = s.pl[ky * pp], wc = s.pl[(ky == 0 ? 0 : ny - ky) * pp];
+      v = kx == 0 ? cplx<T>{T(0.5) * (w.x + wc.x), T(0.5) * (w.y - wc.y)}
+                  : cplx<T>{T(0.5) * (w.y + wc.y), T(-0.5) * (w.x - wc.x)};
+    }
+    out[ky * kys + kx] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_inv(const cplx<T>* __restrict__ spec, T* __restrict__ phi,
+                                                             FftGeom f, FftTables<T> t) {
+  constexpr int NT = kPlaneThreads, PM = plane_points<T>();
+  const PlaneLds<T> s = plane_lds(f, t);
+  const int M = f.ax.L, ny = f.ny, pp = f.pp;
+  const FastDiv dm(M), dh(M / 2 + 1);
+  const int plane = blockIdx.x;
+  const int slot = plane / f.nz, z = plane - slot * f.nz;
+  const cplx<T>* in = spec + ((size_t)slot * ny * f.nz + z) * f.px;
+  const size_t kys = (size_t)f.nz * f.px;
+  staged_copy<NT, 8, cplx<T>>(
+      ny * M,
+      [&](int q) {
+        const int ky = (int)dm.div(q), kx = q - ky * M;
+        // column 0 takes C[ky][0] + i C[ky][M]
+        const cplx<T>* r = in + ky * kys;
+        const cplx<T> a = gload(r + kx), c = gload(r + (kx == 0 ? M : kx));
+        return kx == 0 ? cplx<T>{a.x - c.y, a.y + c.x} : a;
+      },
+      [&](int q, cplx<T> v) {
+        const int ky = (int)dm.div(q), kx = q - ky * M;
+        s.pl[ky * pp + kx] = v;
+      });
+  lds_barrier();
+  lds_fft<T, NT, PM, true>(s.pl, M, 1, pp, f.ay, s.twy, true);
+  const int H = M / 2 + 1;
+  for (int q = threadIdx.x; q < ny * H; q += NT) {
+    const int y = (int)dh.div(q), k = q - y * H;
+    cplx<T>* row = s.pl + y * pp;
+    if (k == 0) {
+      const cplx<T> w = row[0];  // X[0] + i X[M], both real
+      row[0] = {T(0.5) * (w.x + w.y), T(0.5) * (w.x - w.y)};
+    } else {
+      const cplx<T> a = row[k], b = row[M - k];
+      row[k] = split_inv(a, b, s.wn[k]);
+      if (2 * k != M) row[M - k] = split_inv(b, a, s.wn[M - k]);
+    }
+  }
+  lds_barrier();
+  lds_fft<T, NT, PM, true>(s.pl, ny, pp, 1, f.ax, s.twx, true);
+  cplx<T>* dst = reinterpret_cast<cplx<T>*>(phi) + (size_t)plane * ny * M;
+  for (int q = threadIdx.x; q < ny * M; q += NT) {
+    const int y = (int)dm.div(q), m = q - y * M;
+    dst[q] = s.pl[y * pp + m];
+  }
+}
+
+size_t plane_lds_bytes(const FftGeom& f, size_t csz) {
+  const size_t M = f.ax.L;
+  return csz * ((size_t)f.ny * f.pp + M + M + 1 + f.ny);
+}
+
+template <typename T>
+hipError_t fft_plane_prepare(int bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy_fwd<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy_inv<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
+}
+
+template <typename T>
+void launch_fft_xy_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
+                       hipStream_t st) {
+  k_fft_xy_fwd<T><<<f.nz * f.nruns, kPlaneThreads, plane_lds_bytes(f, sizeof(cplx<T>)), st>>>(src, parity, spec,
+                                                                                              f, t);
+}
+
+template <typename T>
+void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st) {
+  k_fft_xy_inv<T><<<f.nz * f.nruns, kPlaneThreads, plane_lds_bytes(f, sizeof(cplx<T>)), st>>>(spec, phi, f, t);
+}
+
 static size_t x_lds_bytes(const FftGeom& f, size_t csz, bool inv) {
   const size_t M = f.ax.L, RB = f.rows_per_block;
-  return csz * (RB * M + (inv ? RB * (M + 1) : 0) + M + M + 1);
+  return csz * (RB * (M | 1) + (inv ? RB * (M + 1) : 0) + M + M + 1);
 }
 
 int fft_blocks_z(const FftGeom& f) { return ((f.px + f.cols_z - 1) / f.cols_z) * f.ny * f.nruns; }
@@ -324,7 +635,7 @@ template <typename T>
 void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool inverse, hipStream_t st) {
   const int cb = f.cols_y;
   const int nblk = ((f.px + cb - 1) / cb) * f.nz * f.nruns;
-  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * (f.ay.L + 1) + f.ay.L);
+  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * (f.ay.L | 1) + f.ay.L);
   const size_t stride = f.px, outer = (size_t)f.px * f.ny, run = outer * f.nz;
   if (inverse)
     k_fft_col<T, 1><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr);
@@ -334,11 +645,14 @@ void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool i
 
 template <typename T>
 void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, double* epot_partials,
-                        hipStream_t st) {
+                        bool ky_major, hipStream_t st) {
   const int cb = f.cols_z;
   const int nblk = fft_blocks_z(f);
-  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * (f.az.L + 1) + f.az.L);
-  const size_t stride = (size_t)f.px * f.ny, outer = f.px, run = stride * f.nz;
+  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * (f.az.L | 1) + f.az.L) + sizeof(double) * (f.az.L + cb);
+  const size_t run = (size_t)f.px * f.ny * f.nz;
+  // C[run][z][ky][kx] (line passes) or C[run][ky][z][kx] (plane passes)
+  const size_t stride = ky_major ? (size_t)f.px : (size_t)f.px * f.ny;
+  const size_t outer = ky_major ? (size_t)f.px * f.nz : (size_t)f.px;
   k_fft_col<T, 2><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, cb, stride, outer, f.ny, run,
                                                   epot_partials);
 }
@@ -353,9 +667,20 @@ template void launch_fft_x_inv<float>(const cplx<float>*, float*, const FftGeom&
                                       hipStream_t);
 template void launch_fft_y<double>(cplx<double>*, const FftGeom&, const FftTables<double>&, bool, hipStream_t);
 template void launch_fft_y<float>(cplx<float>*, const FftGeom&, const FftTables<float>&, bool, hipStream_t);
-template void launch_fft_z_green<double>(cplx<double>*, const FftGeom&, const FftTables<double>&, double*,
+template void launch_fft_z_green<double>(cplx<double>*, const FftGeom&, const FftTables<double>&, double*, bool,
                                          hipStream_t);
-template void launch_fft_z_green<float>(cplx<float>*, const FftGeom&, const FftTables<float>&, double*,
+template void launch_fft_z_green<float>(cplx<float>*, const FftGeom&, const FftTables<float>&, double*, bool,
                                         hipStream_t);
+
+template void launch_fft_xy_fwd<double>(const SrcSlot*, int, cplx<double>*, const FftGeom&,
+                                        const FftTables<double>&, hipStream_t);
+template void launch_fft_xy_fwd<float>(const SrcSlot*, int, cplx<float>*, const FftGeom&, const FftTables<float>&,
+                                       hipStream_t);
+template void launch_fft_xy_inv<double>(const cplx<double>*, double*, const FftGeom&, const FftTables<double>&,
+                                        hipStream_t);
+template void launch_fft_xy_inv<float>(const cplx<float>*, float*, const FftGeom&, const FftTables<float>&,
+                                       hipStream_t);
+template hipError_t fft_plane_prepare<double>(int);
+template hipError_t fft_plane_prepare<float>(int);
 
 }  // namespace gp

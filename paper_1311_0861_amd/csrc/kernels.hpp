@@ -26,8 +26,11 @@ void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned 
                           double* partials, int comp, unsigned nblocks, hipStream_t st);
 
 // ---- FFT Poisson ---------------------------------------------------------
+// Aligned to its size, so that a value moves in one 16-byte (FP64) or 8-byte
+// (FP32) access: with lanes on neighbouring LDS lines of odd pitch that keeps
+// every access free of bank conflicts, where two 8-byte halves would not be.
 template <typename T>
-struct cplx {
+struct alignas(2 * sizeof(T)) cplx {
   T x, y;
 };
 
@@ -52,6 +55,8 @@ struct FftGeom {
   int nx, ny, nz, px;     // px = nx / 2 + 1 (half-spectrum row length)
   int nruns;              // runs of this size stored back to back
   FftAxis ax, ay, az;     // ax.L = nx / 2
+  int plane;              // 1: x and y transforms per z plane in LDS
+  int pp;                 // row pitch of a plane in LDS (complex values)
   int rows_per_block;     // x passes
   int cols_y, cols_z;     // columns per block in the y / z passes
   double green_scale;     // -4 pi G h^2 / 6
@@ -59,6 +64,13 @@ struct FftGeom {
 };
 
 int fft_blocks_z(const FftGeom& f);
+
+// LDS a workgroup of the plane passes may take (gfx950).
+constexpr int kPlaneLdsMax = 160 * 1024;
+size_t plane_lds_bytes(const FftGeom& f, size_t csz);
+// Raises the dynamic-LDS limit of the plane kernels to `bytes`.
+template <typename T>
+hipError_t fft_plane_prepare(int bytes);
 
 // Poisson source of each run of a size class: s = rho + n - <rho + n>, formed
 // in FP64 from the current densities (slot = run position in the class).
@@ -72,9 +84,16 @@ void launch_fft_x_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGe
                       hipStream_t st);
 template <typename T>
 void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool inverse, hipStream_t st);
+// ky_major: the spectrum is stored C[run][ky][z][kx] (as the plane passes
+// write it) rather than C[run][z][ky][kx].
 template <typename T>
 void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, double* epot_partials,
-                        hipStream_t st);
+                        bool ky_major, hipStream_t st);
+template <typename T>
+void launch_fft_xy_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
+                       hipStream_t st);
+template <typename T>
+void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st);
 template <typename T>
 void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st);
 

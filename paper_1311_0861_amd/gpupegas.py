@@ -25,8 +25,9 @@ FIELD_NAMES = [
     "Wxx", "Wxy", "Wxz", "Wyy", "Wyz", "Wzz",
 ]
 GP_PHI = 22
-KERNEL_NAMES = ["eul_gas", "eul_bme", "lag_gas", "lag_bme", "reduce", "fft_x_fwd", "fft_y_fwd", "fft_z_green",
-                "fft_y_inv", "fft_x_inv", "finalize"]
+KERNEL_NAMES = ["eul_gas", "eul_bme", "lag_gas", "lag_bme", "reduce", "fft_xy_fwd", "fft_z_green", "fft_xy_inv",
+                "finalize"]
+GP_FFT_AUTO, GP_FFT_LINES = 0, 1  # x and y transforms: per z plane where it fits, or separate passes
 CELL_KERNELS = ["eul_gas", "eul_bme", "lag_gas", "lag_bme"]  # persistent, launch size settable
 
 
@@ -98,6 +99,7 @@ def _load():
         "gp_algorithmic_bytes_per_cell": ([vp, i32], dbl),
         "gp_set_launch": ([vp, i32, i32], i32),
         "gp_get_launch": ([vp, i32, ctypes.POINTER(i32)], i32),
+        "gp_set_fft_form": ([vp, i32], i32),
         "gp_batch_create": ([ctypes.POINTER(gp_config), i32, vp, ctypes.POINTER(vp)], i32),
         "gp_batch_destroy": ([vp], i32),
         "gp_batch_set_field": ([vp, i32, i32, vp, i32, i32], i32),
@@ -108,6 +110,7 @@ def _load():
         "gp_batch_time_kernels": ([vp, i32, ctypes.POINTER(dbl), i32], i32),
         "gp_batch_set_launch": ([vp, i32, i32], i32),
         "gp_batch_get_launch": ([vp, i32, ctypes.POINTER(i32)], i32),
+        "gp_batch_set_fft_form": ([vp, i32], i32),
         "gp_batch_algorithmic_bytes_per_cell": ([vp, i32], dbl),
         "gp_batch_cells": ([vp], i64),
         "gp_batch_last_error": ([vp], ctypes.c_char_p),
@@ -237,6 +240,10 @@ def gp_set_launch(sim, kernel, blocks):
     _check(sim, lib.gp_set_launch(sim, int(kernel), int(blocks)))
 
 
+def gp_set_fft_form(sim, form):
+    _check(sim, lib.gp_set_fft_form(sim, int(form)))
+
+
 def gp_get_launch(sim, kernel):
     v = ctypes.c_int32()
     _check(sim, lib.gp_get_launch(sim, int(kernel), ctypes.byref(v)))
@@ -297,6 +304,10 @@ def gp_batch_time_kernels(b, nsteps):
 
 def gp_batch_set_launch(b, kernel, blocks):
     _check(b, lib.gp_batch_set_launch(b, int(kernel), int(blocks)), True)
+
+
+def gp_batch_set_fft_form(b, form):
+    _check(b, lib.gp_batch_set_fft_form(b, int(form)), True)
 
 
 def gp_batch_get_launch(b, kernel):
@@ -385,6 +396,9 @@ class Sim:
     def set_launch(self, kernel, blocks):
         gp_set_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel, blocks)
 
+    def set_fft_form(self, form):
+        gp_set_fft_form(self._h, form)
+
     def get_launch(self, kernel):
         return gp_get_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel)
 
@@ -448,6 +462,9 @@ class Batch:
 
     def set_launch(self, kernel, blocks):
         gp_batch_set_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel, blocks)
+
+    def set_fft_form(self, form):
+        gp_batch_set_fft_form(self._h, form)
 
     def get_launch(self, kernel):
         return gp_batch_get_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel)
