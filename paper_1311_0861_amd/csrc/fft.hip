@@ -204,6 +204,12 @@ __device__ __forceinline__ void line_fft(cplx<T>* buf, int lines, int lp, const 
   lds_fft<T, kFftThreads, max_points<T>(), true>(buf, lines, lp, 1, ax, tw, inv);
 }
 
+// columns of an LDS block of `cols` columns (row pitch cols)
+template <typename T>
+__device__ __forceinline__ void col_fft(cplx<T>* buf, int cols, const FftAxis& ax, const cplx<T>* tw, bool inv) {
+  lds_fft<T, kFftThreads, max_points<T>(), true>(buf, cols, 1, cols, ax, tw, inv);
+}
+
 template <int NT, typename T>
 __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* src, int n) {
   for (int t = threadIdx.x; t < n; t += NT) dst[t] = src[t];
@@ -371,8 +377,9 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int L = ax.L;
-  const int lp = L | 1;  // odd line pitch
-  cplx<T>* tw = lds + cb * lp;
+  // LDS holds the block as L rows of cb columns: element j of column c at
+  // j * cb + c, so that lanes on neighbouring columns touch neighbouring words
+  cplx<T>* tw = lds + cb * L;
   const int nchunks = (f.px + cb - 1) / cb;
   const ColBlock cbk = col_block(blockIdx.x, nchunks, (int)(gridDim.x / nchunks));
   const int chunk = cbk.chunk, oline = cbk.oline;
@@ -380,7 +387,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
   const int kx0 = chunk * cb;
   const int ncols = min(cb, f.px - kx0);
   load_twiddles<kFftThreads>(tw, twg, L);
-  const FastDiv dcb(cb), dl(L);
+  const FastDiv dcb(cb);
   // z pass: the symbol's factors D(kz) and D(kx) D(ky) of this block
   double* gz = reinterpret_cast<double*>(tw + L);
   double* gxy = gz + L;
@@ -401,21 +408,18 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
         const cplx<T> v = gload(base + (size_t)j * stride + min(c, ncols - 1));
         return (c < ncols) ? v : cplx<T>{T(0), T(0)};
       },
-      [&](int q, cplx<T> v) {
-        const int j = (int)dcb.div(q), c = q - j * cb;
-        lds[c * lp + j] = v;
-      });
+      [&](int q, cplx<T> v) { lds[q] = v; });
   __syncthreads();
-  line_fft(lds, cb, lp, ax, tw, MODE == 1);
+  col_fft(lds, cb, ax, tw, MODE == 1);
   if constexpr (MODE == 2) {
     // z pass: outer = ky, line position = kz, column = kx
     __shared__ double red[kFftThreads / 64];
     double ep = 0.0;
     for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
-      const int c = (int)dl.div(q), kz = q - c * L;
+      const int kz = (int)dcb.div(q), c = q - kz * cb;
       if (c >= ncols) continue;
       const int kx = kx0 + c;
-      cplx<T>& v = lds[c * lp + kz];
+      cplx<T>& v = lds[q];
       double gk = 0.0;
       if (kx != 0 || outer != 0 || kz != 0) gk = f.green_scale / (1.0 - gxy[c] * gz[kz]);
       const double w = (kx == 0 || 2 * kx == f.nx) ? 1.0 : 2.0;  // Hermitian half spectrum
@@ -433,11 +437,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
       for (int w = 0; w < kFftThreads / 64; w++) s += red[w];
       epot_partials[blockIdx.x] = s;
     }
-    line_fft(lds, cb, lp, ax, tw, true);
+    col_fft(lds, cb, ax, tw, true);
   }
   for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
     const int j = (int)dcb.div(q), c = q - j * cb;
-    if (c < ncols) base[(size_t)j * stride + c] = lds[c * lp + j];
+    if (c < ncols) base[(size_t)j * stride + c] = lds[q];
   }
 }
 
@@ -635,7 +639,7 @@ template <typename T>
 void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool inverse, hipStream_t st) {
   const int cb = f.cols_y;
   const int nblk = ((f.px + cb - 1) / cb) * f.nz * f.nruns;
-  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * (f.ay.L | 1) + f.ay.L);
+  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * f.ay.L + f.ay.L);
   const size_t stride = f.px, outer = (size_t)f.px * f.ny, run = outer * f.nz;
   if (inverse)
     k_fft_col<T, 1><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr);
@@ -648,7 +652,7 @@ void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, 
                         bool ky_major, hipStream_t st) {
   const int cb = f.cols_z;
   const int nblk = fft_blocks_z(f);
-  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * (f.az.L | 1) + f.az.L) + sizeof(double) * (f.az.L + cb);
+  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * f.az.L + f.az.L) + sizeof(double) * (f.az.L + cb);
   const size_t run = (size_t)f.px * f.ny * f.nz;
   // C[run][z][ky][kx] (line passes) or C[run][ky][z][kx] (plane passes)
   const size_t stride = ky_major ? (size_t)f.px : (size_t)f.px * f.ny;
