@@ -216,10 +216,13 @@ __device__ __forceinline__ E ld_at(gptr<const E> base, size_t z, uint32_t xy) {
   const gptr<const char> plane = (gptr<const char>)(base + z);
   return *(gptr<const E>)(plane + xy * (uint32_t)sizeof(E));
 }
+// Streaming store: the stage's outputs are read again only by the next stage,
+// so they should not displace the halo lines that neighbouring tiles still
+// read from L2.
 template <typename E>
 __device__ __forceinline__ void st_at(gptr<E> base, size_t z, uint32_t xy, E v) {
   const gptr<char> plane = (gptr<char>)(base + z);
-  *(gptr<E>)(plane + xy * (uint32_t)sizeof(E)) = v;
+  __builtin_nontemporal_store(v, (gptr<E>)(plane + xy * (uint32_t)sizeof(E)));
 }
 // Stencil point P (compile-time) of an array.
 template <int P, typename E>
