@@ -106,6 +106,18 @@ def recorded_traffic(kernel, n, precision, path=None):
     return None
 
 
+def cpu_model():
+    """Host CPU model name (for the stated CPU baseline)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def timed_steps(obj, steps, warmup):
     """Warm up, then time exactly `steps` graph-replayed steps of a Sim/Batch."""
     import torch
@@ -289,7 +301,7 @@ def main():
                 break
         csec = time.perf_counter() - c0
         cpu = {"value": round(ncell * steps / csec / 1e6, 4), "unit": "Mcell-updates/s",
-               "cores": oracle.get_threads(), "kind": "oracle",
+               "cores": oracle.get_threads(), "kind": "oracle", "cpu_model": cpu_model(),
                "sample": "%d steps of the same %d^3 two-disk workload from its initial state, FP64, "
                          "plain C + OpenMP" % (steps, n)}
         # the same steps on the GPU from the same inputs give the stated error
