@@ -229,6 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       for (int f = 0; f < kGasPrims; f++) s_g[f][ly + 1][lx + 1] = pm[f];
       s_phi[ly + 1][lx + 1] = phm;
     }
+    T Vz = T(0), Pz = T(0);  // z+ face of the previous plane
     for (int k = col.k0; k < col.k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
       const uint32_t xy_c = col.xy_c, xy_h = col.xy_h, pxy_c = pc.xy_c, pxy_h = pc.xy_h;
@@ -271,8 +272,13 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
         dP[1] = Pp - Pm;
         dPV += Pp * Vp - Pm * Vm;
         dV += Vp - Vm;
-        gas_face(gas_of<2>(pm), gas_of<2>(pc_), gamma, Vm, Pm);
+        // the z- face is the previous plane's z+ face (same inputs, same bits)
+        if (k == col.k0) gas_face(gas_of<2>(pm), gas_of<2>(pc_), gamma, Vz, Pz);
+        Vm = Vz;
+        Pm = Pz;
         gas_face(gas_of<2>(pc_), gas_of<2>(pn), gamma, Vp, Pp);
+        Vz = Vp;
+        Pz = Pp;
         dP[2] = Pp - Pm;
         dPV += Pp * Vp - Pm * Vm;
         dV += Vp - Vm;
@@ -360,6 +366,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       for (int f = 0; f < kBmePrims; f++) s_p[f][ly + 1][lx + 1] = pm[f];
       s_phi[ly + 1][lx + 1] = phm;
     }
+    T usz[3], psz[3];  // z+ face of the previous plane
     for (int k = col.k0; k < col.k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
       const uint32_t xy_c = fresh(col.xy_c), xy_h = fresh(col.xy_h);
@@ -414,10 +421,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
         bme_face_add<1>(us, ps, T(-1), C, dq, dW, dPi);
         bme_face<T, 1>(centre_side<1>(C), bme_at<1>(s_p, ly + 2, lx + 1), us, ps);
         bme_face_add<1>(us, ps, T(1), C, dq, dW, dPi);
-        bme_face<T, 2>(bme_of<2>(pm), centre_side<2>(C), us, ps);
-        bme_face_add<2>(us, ps, T(-1), C, dq, dW, dPi);
-        bme_face<T, 2>(centre_side<2>(C), bme_of<2>(pn), us, ps);
-        bme_face_add<2>(us, ps, T(1), C, dq, dW, dPi);
+        // the z- face is the previous plane's z+ face (same inputs, same bits)
+        if (k == col.k0) bme_face<T, 2>(bme_of<2>(pm), centre_side<2>(C), usz, psz);
+        bme_face_add<2>(usz, psz, T(-1), C, dq, dW, dPi);
+        bme_face<T, 2>(centre_side<2>(C), bme_of<2>(pn), usz, psz);
+        bme_face_add<2>(usz, psz, T(1), C, dq, dW, dPi);
         T grad[3] = {T(0), T(0), T(0)};
         if (grav) {
           grad[0] = (s_phi[ly + 1][lx + 2] - s_phi[ly + 1][lx]) * r2h;

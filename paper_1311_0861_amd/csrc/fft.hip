@@ -112,16 +112,18 @@ struct FastDiv {
 
 // One Stockham stage of radix R on `lines` lines of length L, in place: reads
 // to registers, barrier, writes, barrier.  Element j of line l sits at
-// buf[l * ls + j * es]; at most PMAX points (lines * L) per call.  LF puts the
-// line index fastest across the threads (for lines that are LDS columns, so
-// that neighbouring lanes touch neighbouring words).
-template <typename T, int R, int NT, int PMAX, bool LF>
+// buf[l * ls + j * es]; at most PMAX points (lines * L) per call.  The line
+// index runs fastest across the threads, so neighbouring lanes work on
+// neighbouring lines at the same element: one word apart when the lines are
+// LDS columns (ls = 1), an odd pitch apart when they are rows (es = 1); either
+// way they fall in different banks, and they share their twiddle factor.
+template <typename T, int R, int NT, int PMAX>
 __device__ void fft_stage(cplx<T>* buf, int lines, int L, int ls, int es, int Ns, const cplx<T>* tw, bool inv) {
   constexpr int MAXB = (PMAX / R + NT - 1) / NT;
   const int nb = L / R;
   const int total = lines * nb;
   const int tstep = L / (Ns * R);
-  const FastDiv dmaj(LF ? lines : nb), dns(Ns);
+  const FastDiv dline(lines), dns(Ns);
   cplx<T> v[MAXB][R];
   // the thread's indexes are the same in every stage of a radix; computed
   // here rather than hoisted out of the stage loop, where they would all stay
@@ -131,14 +133,8 @@ __device__ void fft_stage(cplx<T>* buf, int lines, int L, int ls, int es, int Ns
   for (int b = 0; b < MAXB; b++) {
     const int q = tid + b * NT;
     if (q < total) {
-      int line, jj;
-      if constexpr (LF) {
-        jj = (int)dmaj.div(q);
-        line = q - jj * lines;
-      } else {
-        line = (int)dmaj.div(q);
-        jj = q - line * nb;
-      }
+      const int jj = (int)dline.div(q);
+      const int line = q - jj * lines;
       const int kk = jj - (int)dns.div(jj) * Ns;
       const cplx<T>* base = buf + line * ls;
 #pragma unroll
@@ -160,14 +156,8 @@ __device__ void fft_stage(cplx<T>* buf, int lines, int L, int ls, int es, int Ns
     // recomputed rather than held over the barrier beside the butterflies
     const int q = (int)fresh(threadIdx.x) + b * NT;
     if (q < total) {
-      int line, jj;
-      if constexpr (LF) {
-        jj = (int)dmaj.div(q);
-        line = q - jj * lines;
-      } else {
-        line = (int)dmaj.div(q);
-        jj = q - line * nb;
-      }
+      const int jj = (int)dline.div(q);
+      const int line = q - jj * lines;
       const int jn = (int)dns.div(jj);
       const int kk = jj - jn * Ns;
       cplx<T>* base = buf + line * ls;
@@ -179,35 +169,34 @@ __device__ void fft_stage(cplx<T>* buf, int lines, int L, int ls, int es, int Ns
   lds_barrier();
 }
 
-template <typename T, int NT, int PMAX, bool LF>
+template <typename T, int NT, int PMAX>
 __device__ void lds_fft(cplx<T>* buf, int lines, int ls, int es, const FftAxis& ax, const cplx<T>* tw, bool inv) {
   int Ns = 1;
   for (int s = 0; s < ax.nst; s++) {
     const int R = ax.rad[s];
     if (R == 8)
-      fft_stage<T, 8, NT, PMAX, LF>(buf, lines, ax.L, ls, es, Ns, tw, inv);
+      fft_stage<T, 8, NT, PMAX>(buf, lines, ax.L, ls, es, Ns, tw, inv);
     else if (R == 4)
-      fft_stage<T, 4, NT, PMAX, LF>(buf, lines, ax.L, ls, es, Ns, tw, inv);
+      fft_stage<T, 4, NT, PMAX>(buf, lines, ax.L, ls, es, Ns, tw, inv);
     else if (R == 3)
-      fft_stage<T, 3, NT, PMAX, LF>(buf, lines, ax.L, ls, es, Ns, tw, inv);
+      fft_stage<T, 3, NT, PMAX>(buf, lines, ax.L, ls, es, Ns, tw, inv);
     else
-      fft_stage<T, 2, NT, PMAX, LF>(buf, lines, ax.L, ls, es, Ns, tw, inv);
+      fft_stage<T, 2, NT, PMAX>(buf, lines, ax.L, ls, es, Ns, tw, inv);
     Ns *= R;
   }
 }
 
-// contiguous lines of the line passes (pitch lp odd: neighbouring lanes take
-// neighbouring lines, whose words fall in different banks)
+// rows (pitch lp, odd) of the line passes
 template <typename T>
 __device__ __forceinline__ void line_fft(cplx<T>* buf, int lines, int lp, const FftAxis& ax, const cplx<T>* tw,
                                          bool inv) {
-  lds_fft<T, kFftThreads, max_points<T>(), true>(buf, lines, lp, 1, ax, tw, inv);
+  lds_fft<T, kFftThreads, max_points<T>()>(buf, lines, lp, 1, ax, tw, inv);
 }
 
 // columns of an LDS block of `cols` columns (row pitch cols)
 template <typename T>
 __device__ __forceinline__ void col_fft(cplx<T>* buf, int cols, const FftAxis& ax, const cplx<T>* tw, bool inv) {
-  lds_fft<T, kFftThreads, max_points<T>(), true>(buf, cols, 1, cols, ax, tw, inv);
+  lds_fft<T, kFftThreads, max_points<T>()>(buf, cols, 1, cols, ax, tw, inv);
 }
 
 template <int NT, typename T>
@@ -503,7 +492,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
         s.pl[y * pp + m] = v;
       });
   lds_barrier();
-  lds_fft<T, NT, PM, true>(s.pl, ny, pp, 1, f.ax, s.twx, false);
+  lds_fft<T, NT, PM>(s.pl, ny, pp, 1, f.ax, s.twx, false);
   // split of each row, pairs (k, M - k) by one thread; X[0] + i X[M] in column 0
   const int H = M / 2 + 1;
   for (int q = threadIdx.x; q < ny * H; q += NT) {
@@ -519,7 +508,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
     }
   }
   lds_barrier();
-  lds_fft<T, NT, PM, true>(s.pl, M, 1, pp, f.ay, s.twy, false);
+  lds_fft<T, NT, PM>(s.pl, M, 1, pp, f.ay, s.twy, false);
   // spectrum rows ky-major: C[run][ky][z][kx], so that the z pass reads
   // contiguous blocks
   cplx<T>* out = spec + ((size_t)slot * ny * f.nz + z) * f.px;
@@ -563,7 +552,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_inv(const cplx<T>* __r
         s.pl[ky * pp + kx] = v;
       });
   lds_barrier();
-  lds_fft<T, NT, PM, true>(s.pl, M, 1, pp, f.ay, s.twy, true);
+  lds_fft<T, NT, PM>(s.pl, M, 1, pp, f.ay, s.twy, true);
   const int H = M / 2 + 1;
   for (int q = threadIdx.x; q < ny * H; q += NT) {
     const int y = (int)dh.div(q), k = q - y * H;
@@ -578,7 +567,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_inv(const cplx<T>* __r
     }
   }
   lds_barrier();
-  lds_fft<T, NT, PM, true>(s.pl, ny, pp, 1, f.ax, s.twx, true);
+  lds_fft<T, NT, PM>(s.pl, ny, pp, 1, f.ax, s.twx, true);
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(phi) + (size_t)plane * ny * M;
   for (int q = threadIdx.x; q < ny * M; q += NT) {
     const int y = (int)dm.div(q), m = q - y * M;
