@@ -213,8 +213,11 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       a[4] = gm1 * e;
     };
 
-    // prologue: plane k0 - 1 into the LDS centres, plane k0 into registers
+    // prologue: plane k0 into registers, the potential of plane k0 - 1 into
+    // the LDS centre, and the z- face of plane k0; from then on each plane's
+    // z- face is the previous plane's z+ face (same inputs, same bits)
     T pc_[kGasPrims], mc[3], ec, phc;
+    T Vz, Pz;  // z+ face of the previous plane
     {
       const size_t zm = plane_at(g, col.k0 - 1, g.bc[2]), z0 = nxy * (size_t)col.k0;
       double rho, rho0;
@@ -225,17 +228,12 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       phc = phi_at(phi, grav, z0, pc.xy_c);
       prims(rho, m, e, pm);
       prims(rho0, mc, ec, pc_);
-#pragma unroll
-      for (int f = 0; f < kGasPrims; f++) s_g[f][ly + 1][lx + 1] = pm[f];
+      gas_face(gas_of<2>(pm), gas_of<2>(pc_), gamma, Vz, Pz);
       s_phi[ly + 1][lx + 1] = phm;
     }
-    T Vz = T(0), Pz = T(0);  // z+ face of the previous plane
     for (int k = col.k0; k < col.k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
       const uint32_t xy_c = col.xy_c, xy_h = col.xy_h, pxy_c = pc.xy_c, pxy_h = pc.xy_h;
-      T pm[kGasPrims];
-#pragma unroll
-      for (int f = 0; f < kGasPrims; f++) pm[f] = s_g[f][ly + 1][lx + 1];
       const T phm = s_phi[ly + 1][lx + 1];
       lds_barrier();  // every thread is done with the previous plane's tiles
       double rho_h, rho_n;
@@ -272,8 +270,6 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
         dP[1] = Pp - Pm;
         dPV += Pp * Vp - Pm * Vm;
         dV += Vp - Vm;
-        // the z- face is the previous plane's z+ face (same inputs, same bits)
-        if (k == col.k0) gas_face(gas_of<2>(pm), gas_of<2>(pc_), gamma, Vz, Pz);
         Vm = Vz;
         Pm = Pz;
         gas_face(gas_of<2>(pc_), gas_of<2>(pn), gamma, Vp, Pp);
@@ -350,8 +346,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       for (int m = 0; m < 6; m++) a[4 + m] = P[m];
     };
 
-    // prologue: plane k0 - 1 into the LDS centres, plane k0 into registers
+    // prologue: plane k0 into registers, the potential of plane k0 - 1 into
+    // the LDS centre, and the z- face of plane k0; from then on each plane's
+    // z- face is the previous plane's z+ face (same inputs, same bits)
     T pc_[kBmePrims], qc[3], phc;
+    T usz[3], psz[3];  // z+ face of the previous plane
     {
       const size_t zm = plane_at(g, col.k0 - 1, g.bc[2]), z0 = nxy * (size_t)col.k0;
       double n, n0;
@@ -362,18 +361,13 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       phc = phi_at(phi, grav, z0, pc.xy_c);
       prims(n, q, P, pm);
       prims(n0, qc, P0, pc_);
-#pragma unroll
-      for (int f = 0; f < kBmePrims; f++) s_p[f][ly + 1][lx + 1] = pm[f];
+      bme_face<T, 2>(bme_of<2>(pm), bme_of<2>(pc_), usz, psz);
       s_phi[ly + 1][lx + 1] = phm;
     }
-    T usz[3], psz[3];  // z+ face of the previous plane
     for (int k = col.k0; k < col.k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
       const uint32_t xy_c = fresh(col.xy_c), xy_h = fresh(col.xy_h);
       const uint32_t pxy_c = fresh(pc.xy_c), pxy_h = fresh(pc.xy_h);
-      T pm[kBmePrims];
-#pragma unroll
-      for (int f = 0; f < kBmePrims; f++) pm[f] = s_p[f][ly + 1][lx + 1];
       const T phm = s_phi[ly + 1][lx + 1];
       lds_barrier();  // every thread is done with the previous plane's tiles
       {
@@ -421,8 +415,6 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
         bme_face_add<1>(us, ps, T(-1), C, dq, dW, dPi);
         bme_face<T, 1>(centre_side<1>(C), bme_at<1>(s_p, ly + 2, lx + 1), us, ps);
         bme_face_add<1>(us, ps, T(1), C, dq, dW, dPi);
-        // the z- face is the previous plane's z+ face (same inputs, same bits)
-        if (k == col.k0) bme_face<T, 2>(bme_of<2>(pm), centre_side<2>(C), usz, psz);
         bme_face_add<2>(usz, psz, T(-1), C, dq, dW, dPi);
         bme_face<T, 2>(centre_side<2>(C), bme_of<2>(pn), usz, psz);
         bme_face_add<2>(usz, psz, T(1), C, dq, dW, dPi);
