@@ -37,13 +37,12 @@ using namespace gp;
 namespace {
 
 // Target work items per run of the two work lists (see make_items), by
-// working precision: {stars / DM kernels, gas kernels}.  About as many items
-// as the chip keeps stars / DM workgroups resident (2 per CU in FP64).
-// Finer lists for the gas kernels, which fit 3-4 workgroups per CU, measured
-// slower at 128^3 FP64 (832 items: 0.065 -> 0.073 ms Eulerian, 0.087 -> 0.101
-// ms Lagrangian): the per-item prologue and reduction outweigh the extra
-// resident workgroups.
-constexpr long kItemsFp64[2] = {512, 512};
+// working precision: {stars / DM kernels, gas kernels}: as many items as the
+// chip keeps workgroups of those kernels resident in FP64 (2 per CU for the
+// stars / DM, 3 for the gas: 768 items took the gas Lagrangian from 0.081 to
+// 0.076 ms at 128^3).  A list that overshoots the resident slots is slower
+// (832 gas items: 0.065 -> 0.073 ms Eulerian, 0.087 -> 0.101 ms Lagrangian).
+constexpr long kItemsFp64[2] = {512, 768};
 constexpr long kItemsFp32[2] = {512, 512};
 constexpr int kTunedKernels = 4;  // the per-cell kernels
 const int kTunedIds[kTunedKernels] = {GP_K_EUL_GAS, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME};
@@ -264,17 +263,20 @@ void enqueue_finalize(gp_batch* b, int advanced, Timer* tm) {
   tdone(tm, GP_K_FINALIZE);
 }
 
-// Work lists.  A run's tile columns (64 x 4 tiles along z) are cut into
-// chunks of cz planes, cz = ncolumns nz / target clamped to 4..32, so the
-// list has about `target` items; list 0 (stars / DM kernels) and list 1 (gas
-// kernels) have their own target.  A workgroup walks its chunk plane by
+// Work lists.  A run's tile columns (64 x 4 tiles along z) are each cut into
+// about target / ncolumns chunks (rounded) of cz planes, cz clamped to 4..32,
+// so the list has about `target` items; list 0 (stars / DM kernels) and list
+// 1 (gas kernels) have their own target.  A workgroup walks its chunk plane by
 // plane, so short chunks re-read more planes at their ends, long ones leave
 // resident workgroup slots idle.  Items go x fastest, then y, then chunk: the
 // columns whose rings overlap run side by side on one XCD.  Item i of a run
 // writes partial row i.
 int chunk_planes(const RunHost& R, int prec, int list) {
   const long target = (prec == GP_FP64 ? kItemsFp64 : kItemsFp32)[list];
-  return (int)std::max<long>(4, std::min<long>(32, (long)R.ntx * R.nty * R.g.nz / target));
+  const long ncol = (long)R.ntx * R.nty;
+  const long nchunk = std::max(1L, (target + ncol / 2) / ncol);  // chunks per column, rounded
+  const long cz = (R.g.nz + nchunk - 1) / nchunk;
+  return (int)std::max<long>(4, std::min<long>(32, cz));
 }
 unsigned items_per_run(const RunHost& R, int prec, int list) {
   const int cz = chunk_planes(R, prec, list);
