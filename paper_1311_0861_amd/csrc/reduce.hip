@@ -63,18 +63,20 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
                                                           const double* __restrict__ epot,
                                                           const FinDesc* __restrict__ fin, int advanced) {
   __shared__ double tot[kNP];
-  __shared__ double ered[kRedThreads];
+  __shared__ double ered[kRedThreads / 64];
   const FinDesc F = fin[blockIdx.x];
-  reduce_rows(rows, (int)F.soff, (int)(F.soff + F.nscr), tot);
+  // the potential-energy partials are summed first (strided per thread, then
+  // across each wave and the waves in order), so that their loads overlap
+  // the reduction of the scratch rows
   double e = 0.0;
   for (unsigned b = threadIdx.x; b < F.nep; b += kRedThreads) e += epot[F.eoff + b];
-  ered[threadIdx.x] = e;
-  __syncthreads();
-  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) ered[threadIdx.x] += ered[threadIdx.x + w];
-    __syncthreads();
-  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if ((threadIdx.x & 63) == 0) ered[threadIdx.x >> 6] = e;
+  reduce_rows(rows, (int)F.soff, (int)(F.soff + F.nscr), tot);  // its barriers also order ered[]
   if (threadIdx.x != 0) return;
+  double epot_sum = ered[0];
+  for (int w = 1; w < kRedThreads / 64; w++) epot_sum += ered[w];
   DevScalars* sc = F.sc;
   const Grid& g = F.g;
   const Phys& ph = F.ph;
@@ -111,7 +113,7 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
   for (int a = 0; a < 3; a++) d.mom[a] = h3 * (tot[G + S_MOMX + a] + tot[B + S_MOMX + a]);
   d.e_gas = h3 * tot[G + S_ENERGY];
   d.e_bme = h3 * tot[B + S_ENERGY];
-  d.e_pot = 0.5 * h3 * F.epot_scale * ered[0];
+  d.e_pot = 0.5 * h3 * F.epot_scale * epot_sum;
   d.kappa_gas = h3 * tot[G + S_KAPPA];
   d.kappa_bme = h3 * tot[B + S_KAPPA];
   d.outflow_gas = sc->outflow_gas;
