@@ -62,7 +62,6 @@ struct DevScalars {
   double dt;             // step the next update uses
   double outflow_gas;    // cumulative outflow
   double outflow_bme;
-  double shift;          // FP64 mean of rho + n, removed from the Poisson source
   int64_t step;
   uint32_t err;          // latched error bits
   uint32_t ndiag;        // diagnostics records written so far

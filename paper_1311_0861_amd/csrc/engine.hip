@@ -7,13 +7,15 @@
 // Device state per run: rho and n in FP64 (two buffers that swap each step),
 // the 20 other fields in the working precision in two sets ("cur" holds the
 // state, "tmp" the post-Eulerian fields), corner velocities, device scalars
-// (t, tau, step, error bits, mean density, cumulative outflow) and a ring of
-// diagnostics records.  Runs of one grid size form a size class whose Poisson
-// source, potential and half spectrum are stored back to back, so each FFT
-// pass is one launch per class.  Per-cell stages are persistent launches over
-// a (run, tile) work list.  One step is
-//   Eulerian -> vertex -> Lagrangian(+epilogue) -> 5 FFT passes per class
-//   -> reduce -> finalize (one workgroup per run)
+// (t, tau, step, error bits, cumulative outflow) and a ring of diagnostics
+// records.  Runs of one grid size form a size class whose potential and half
+// spectrum are stored back to back, so each FFT pass is one launch per class.
+// Per-cell stages are persistent launches over a (run, tile) work list.  One
+// step is
+//   Eulerian (gas, stars) -> Lagrangian (gas, stars; corners, fluxes and
+//   per-tile partial sums) -> 3 FFT passes per class (5 where a plane does
+//   not fit in LDS; the first z pass also reduces the partial rows)
+//   -> finalize (one workgroup per run)
 // and is replayed from a captured HIP graph (one per buffer parity); tau never
 // leaves the device.  The persistent grid size of each per-cell stage is
 // picked by timing candidates during the first step (results do not depend
@@ -66,7 +68,7 @@ struct SizeClass {
   int nx = 0, ny = 0, nz = 0;
   double h = 0.0, G = 0.0;
   std::vector<int> runs;
-  SrcSlot* src = nullptr;  // per run slot: densities and mean, for the source
+  SrcSlot* src = nullptr;  // per run slot: the densities, for the source
   void* phi = nullptr;
   void* spec = nullptr;
   void* tw_x = nullptr;
@@ -211,10 +213,21 @@ void tdone(Timer* tm, int k) {
   }
 }
 
+RedJob red_job(const gp_batch* b) { return RedJob{b->partials, b->red_items, b->scratch, b->nred}; }
+
+bool any_gravity(const gp_batch* b) {
+  for (const SizeClass& c : b->classes)
+    if (c.G != 0.0) return true;
+  return false;
+}
+
+// The Poisson passes; the first z pass also runs the first level of the
+// reduction of the partial rows.
 template <typename T>
 void enqueue_poisson(gp_batch* b, Timer* tm) {
   // each pass runs over every size class before the next pass starts
   const int passes[3] = {GP_K_FFT_XY_FWD, GP_K_FFT_Z, GP_K_FFT_XY_INV};
+  bool reduced = false;
   for (int k : passes) {
     tmark(b, tm, k, 0);
     for (SizeClass& c : b->classes) {
@@ -232,7 +245,10 @@ void enqueue_poisson(gp_batch* b, Timer* tm) {
             launch_fft_y<T>(spec, c.fg, t, false, b->st);
           }
           break;
-        case GP_K_FFT_Z: launch_fft_z_green<T>(spec, c.fg, t, b->epot + c.eoff, plane, b->st); break;
+        case GP_K_FFT_Z:
+          launch_fft_z_green<T>(spec, c.fg, t, b->epot + c.eoff, plane, reduced ? RedJob{} : red_job(b), b->st);
+          reduced = true;
+          break;
         case GP_K_FFT_XY_INV:
           if (plane) {
             launch_fft_xy_inv<T>(spec, phi, c.fg, t, b->st);
@@ -248,16 +264,11 @@ void enqueue_poisson(gp_batch* b, Timer* tm) {
   }
 }
 
-// partial rows -> per-run scratch rows and the mean density of each run
-void enqueue_reduce(gp_batch* b, Timer* tm) {
-  tmark(b, tm, GP_K_REDUCE, 0);
-  launch_reduce(b->partials, b->red_items, b->nred, b->scratch, b->fin, (int)b->runs.size(), b->st);
-  tmark(b, tm, GP_K_REDUCE, 1);
-  tdone(tm, GP_K_REDUCE);
-}
-
+// partial rows -> per-run scratch rows (done by the z pass when a run has
+// gravity), then the per-run finalize
 void enqueue_finalize(gp_batch* b, int advanced, Timer* tm) {
   tmark(b, tm, GP_K_FINALIZE, 0);
+  if (!any_gravity(b)) launch_reduce(red_job(b), b->st);
   launch_finalize(b->scratch, b->epot, b->fin, (int)b->runs.size(), advanced, b->st);
   tmark(b, tm, GP_K_FINALIZE, 1);
   tdone(tm, GP_K_FINALIZE);
@@ -372,7 +383,6 @@ void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
       cell(GP_K_LAG_BME);
       if (allow_tune && b->tune) b->tuned = true;
       b->parity ^= 1;
-      enqueue_reduce(b, tm);
       break;
     case GP_STAGE_POISSON:
       enqueue_poisson<T>(b, tm);
@@ -390,7 +400,6 @@ void enqueue_prologue(gp_batch* b) {
                           b->st);
   launch_init_partials<T>(runs, b->work[0], b->nwork[0], b->parity, b->partials, COMP_BME, b->blocks[GP_K_LAG_BME],
                           b->st);
-  enqueue_reduce(b, nullptr);
   enqueue_poisson<T>(b, nullptr);
   enqueue_finalize(b, 0, nullptr);
 }
@@ -728,7 +737,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     std::vector<SrcSlot> slots;
     for (int r : c.runs) {
       const RunHost& R = b->runs[r];
-      slots.push_back({{R.dens[0][0], R.dens[1][0]}, {R.dens[0][1], R.dens[1][1]}, R.sc});
+      slots.push_back({{R.dens[0][0], R.dens[1][0]}, {R.dens[0][1], R.dens[1][1]}});
     }
     put(c.src, slots.data(), slots.size() * sizeof(SrcSlot));
     if (c.G == 0.0) continue;
@@ -930,7 +939,6 @@ double engine_bytes_per_cell(const gp_batch* b, int32_t kernel) {
     case GP_K_EUL_BME: return eul_bme;
     case GP_K_LAG_GAS: return lag_gas;
     case GP_K_LAG_BME: return lag_bme;
-    case GP_K_REDUCE:
     case GP_K_FINALIZE: return 0.0;
     case -1: {
       double t = eul_gas + eul_bme + lag_gas + lag_bme;

@@ -5,10 +5,9 @@
 //
 // Passes over a half spectrum of rows of px = nx/2 + 1 values, kx in [0, nx/2],
 // stored C[z][ky][kx] by the line passes and C[ky][z][kx] by the plane passes:
-//   xy forward : the source s = rho + n - <rho + n> is formed in FP64 from the
-//                densities (the constant leaves Phi unchanged, as its zero mode
-//                is dropped, and keeping it out of an FP32 transform keeps the
-//                other modes accurate); real rows of length nx -> complex FFT
+//   xy forward : the source s = rho + n is formed in FP64 from the densities
+//                (its mean is the zero mode, which the symbol drops, so Phi
+//                solves the equation for s - <s>); real rows of length nx -> complex FFT
 //                of length nx/2 on packed (even, odd) pairs, the even/odd
 //                split to nx/2+1 bins, then the columns along y;
 //   z fused    : forward along z, multiply by the symbol (and the inverse
@@ -25,6 +24,7 @@
 #include "column.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "reduce.hpp"
 
 namespace gp {
 
@@ -285,10 +285,9 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __rest
         const int slot = row / rows_run;  // may exceed the range of FastDiv
         const size_t c = (size_t)(row - slot * rows_run) * f.nx + 2 * m;
         const SrcSlot& S = src[slot];
-        const double shift = gload(&S.sc->shift);
         const dpair a = gload(reinterpret_cast<const dpair*>(S.rho[parity] + c));
         const dpair b = gload(reinterpret_cast<const dpair*>(S.nb[parity] + c));
-        return cplx<T>{(T)(a.x + b.x - shift), (T)(a.y + b.y - shift)};
+        return cplx<T>{(T)(a.x + b.x), (T)(a.y + b.y)};
       },
       [&](int q, cplx<T> v) {
         const int rq = (int)dm.div(q);
@@ -358,19 +357,33 @@ __device__ __forceinline__ ColBlock col_block(int b, int nchunks, int nolines) {
   return {chunk, g * 8 + (rem - chunk * r)};
 }
 
+// In the z pass the first red.n workgroups reduce partial rows instead (they
+// need nothing from the transform, and the pass has room beside it).
 template <typename T, int MODE>  // MODE 0: forward, 1: inverse, 2: forward * symbol * inverse
 __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t,
                                                          FftAxis ax, const cplx<T>* __restrict__ twg, int cb,
                                                          size_t stride, size_t outer_stride, int outer_div,
-                                                         size_t run_stride, double* __restrict__ epot_partials) {
+                                                         size_t run_stride, double* __restrict__ epot_partials,
+                                                         RedJob red) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  int bid = (int)blockIdx.x, nblk = (int)gridDim.x;
+  if constexpr (MODE == 2) {
+    if (bid < red.n) {
+      const RedItem it = red.items[bid];
+      reduce_rows(red.partials, (int)it.src_begin, (int)it.src_end, red.scratch + (size_t)bid * kNP,
+                  reinterpret_cast<double*>(smem_raw));
+      return;
+    }
+    bid -= red.n;
+    nblk -= red.n;
+  }
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int L = ax.L;
   // LDS holds the block as L rows of cb columns: element j of column c at
   // j * cb + c, so that lanes on neighbouring columns touch neighbouring words
   cplx<T>* tw = lds + cb * L;
   const int nchunks = (f.px + cb - 1) / cb;
-  const ColBlock cbk = col_block(blockIdx.x, nchunks, (int)(gridDim.x / nchunks));
+  const ColBlock cbk = col_block(bid, nchunks, nblk / nchunks);
   const int chunk = cbk.chunk, oline = cbk.oline;
   const int outer = oline % outer_div;
   const int kx0 = chunk * cb;
@@ -424,7 +437,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
     if (threadIdx.x == 0) {
       double s = 0.0;
       for (int w = 0; w < kFftThreads / 64; w++) s += red[w];
-      epot_partials[blockIdx.x] = s;
+      epot_partials[bid] = s;
     }
     col_fft(lds, cb, ax, tw, true);
   }
@@ -476,7 +489,6 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
   const int plane = blockIdx.x;  // run * nz + z
   const int slot = plane / f.nz, z = plane - slot * f.nz;
   const SrcSlot& S = src[slot];
-  const double shift = gload(&S.sc->shift);
   const size_t off = (size_t)z * ny * f.nx;
   const dpair* rho = reinterpret_cast<const dpair*>(S.rho[parity] + off);
   const dpair* nb = reinterpret_cast<const dpair*>(S.nb[parity] + off);
@@ -485,7 +497,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
       ny * M,
       [&](int q) {
         const dpair a = gload(rho + q), c = gload(nb + q);
-        return cplx<T>{(T)(a.x + c.x - shift), (T)(a.y + c.y - shift)};
+        return cplx<T>{(T)(a.x + c.x), (T)(a.y + c.y)};
       },
       [&](int q, cplx<T> v) {
         const int y = (int)dm.div(q), m = q - y * M;
@@ -631,23 +643,26 @@ void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool i
   const size_t lds = sizeof(cplx<T>) * ((size_t)cb * f.ay.L + f.ay.L);
   const size_t stride = f.px, outer = (size_t)f.px * f.ny, run = outer * f.nz;
   if (inverse)
-    k_fft_col<T, 1><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr);
+    k_fft_col<T, 1><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr,
+                                                    RedJob{});
   else
-    k_fft_col<T, 0><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr);
+    k_fft_col<T, 0><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr,
+                                                    RedJob{});
 }
 
 template <typename T>
 void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, double* epot_partials,
-                        bool ky_major, hipStream_t st) {
+                        bool ky_major, const RedJob& red, hipStream_t st) {
   const int cb = f.cols_z;
-  const int nblk = fft_blocks_z(f);
-  const size_t lds = sizeof(cplx<T>) * ((size_t)cb * f.az.L + f.az.L) + sizeof(double) * (f.az.L + cb);
+  const int nblk = fft_blocks_z(f) + red.n;
+  size_t lds = sizeof(cplx<T>) * ((size_t)cb * f.az.L + f.az.L) + sizeof(double) * (f.az.L + cb);
+  if (red.n > 0) lds = std::max(lds, sizeof(double) * kRedThreads);
   const size_t run = (size_t)f.px * f.ny * f.nz;
   // C[run][z][ky][kx] (line passes) or C[run][ky][z][kx] (plane passes)
   const size_t stride = ky_major ? (size_t)f.px : (size_t)f.px * f.ny;
   const size_t outer = ky_major ? (size_t)f.px * f.nz : (size_t)f.px;
   k_fft_col<T, 2><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, cb, stride, outer, f.ny, run,
-                                                  epot_partials);
+                                                  epot_partials, red);
 }
 
 template void launch_fft_x_fwd<double>(const SrcSlot*, int, cplx<double>*, const FftGeom&,
@@ -661,9 +676,9 @@ template void launch_fft_x_inv<float>(const cplx<float>*, float*, const FftGeom&
 template void launch_fft_y<double>(cplx<double>*, const FftGeom&, const FftTables<double>&, bool, hipStream_t);
 template void launch_fft_y<float>(cplx<float>*, const FftGeom&, const FftTables<float>&, bool, hipStream_t);
 template void launch_fft_z_green<double>(cplx<double>*, const FftGeom&, const FftTables<double>&, double*, bool,
-                                         hipStream_t);
+                                         const RedJob&, hipStream_t);
 template void launch_fft_z_green<float>(cplx<float>*, const FftGeom&, const FftTables<float>&, double*, bool,
-                                        hipStream_t);
+                                        const RedJob&, hipStream_t);
 
 template void launch_fft_xy_fwd<double>(const SrcSlot*, int, cplx<double>*, const FftGeom&,
                                         const FftTables<double>&, hipStream_t);

@@ -72,12 +72,25 @@ size_t plane_lds_bytes(const FftGeom& f, size_t csz);
 template <typename T>
 hipError_t fft_plane_prepare(int bytes);
 
-// Poisson source of each run of a size class: s = rho + n - <rho + n>, formed
-// in FP64 from the current densities (slot = run position in the class).
+// First level of the reduction of the per-tile partial rows (kNP FP64 slots
+// each): workgroup b reduces partial rows items[b] into scratch row b.  It
+// rides along in the first Poisson z pass of a step, or runs on its own when
+// no run has gravity.
+struct RedItem {
+  unsigned src_begin, src_end;  // partial rows reduced into one scratch row
+};
+struct RedJob {
+  const double* partials;
+  const RedItem* items;
+  double* scratch;
+  int n;  // workgroups; 0 = none
+};
+
+// Poisson source of each run of a size class: s = rho + n, formed in FP64
+// from the current densities (slot = run position in the class).
 struct SrcSlot {
   const double* rho[2];  // by buffer parity
   const double* nb[2];
-  const DevScalars* sc;  // holds the mean <rho + n>
 };
 template <typename T>
 void launch_fft_x_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
@@ -85,10 +98,11 @@ void launch_fft_x_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGe
 template <typename T>
 void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool inverse, hipStream_t st);
 // ky_major: the spectrum is stored C[run][ky][z][kx] (as the plane passes
-// write it) rather than C[run][z][ky][kx].
+// write it) rather than C[run][z][ky][kx].  The first red.n workgroups of the
+// launch run the reduction job instead.
 template <typename T>
 void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, double* epot_partials,
-                        bool ky_major, hipStream_t st);
+                        bool ky_major, const RedJob& red, hipStream_t st);
 template <typename T>
 void launch_fft_xy_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
                        hipStream_t st);
@@ -98,12 +112,9 @@ template <typename T>
 void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st);
 
 // ---- reductions / finalize ---------------------------------------------
-// Two-level fixed-order reduction of the per-tile partial rows, then per run
-// the CFL step, time advance and diagnostics record.  advanced = 1 after a
-// step, 0 for the initial state.
-struct RedItem {
-  unsigned src_begin, src_end;  // partial rows reduced into one scratch row
-};
+// Second level of the reduction (scratch rows of a run), then per run the CFL
+// step, time advance and diagnostics record.  advanced = 1 after a step, 0
+// for the initial state.
 struct FinDesc {
   Grid g;
   Phys ph;
@@ -113,10 +124,7 @@ struct FinDesc {
   DevScalars* sc;
   gp_diag* ring;
 };
-// First level (partial rows -> per-run scratch rows) and the per-run mean
-// density for the Poisson source; then the finalize proper.
-void launch_reduce(const double* partials, const RedItem* items, int nitems, double* scratch, const FinDesc* fin,
-                   int nruns, hipStream_t st);
+void launch_reduce(const RedJob& red, hipStream_t st);
 void launch_finalize(const double* scratch, const double* epot_partials, const FinDesc* fin, int nruns,
                      int advanced, hipStream_t st);
 

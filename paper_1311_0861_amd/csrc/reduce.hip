@@ -10,52 +10,18 @@
 // so results do not depend on scheduling.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "reduce.hpp"
 
 namespace gp {
 
-constexpr int kRedThreads = 256;
-constexpr int kLanesPerSlot = kRedThreads / kNP;  // lanes per partial slot (the rest idle)
-
-__device__ __forceinline__ double combine(int slot, double a, double b) {
-  const int s = slot % kNS;
-  if (s == S_SPEED) return fmax(a, b);
-  if (s == S_ERR) return (double)((uint32_t)a | (uint32_t)b);
-  return a + b;
-}
-
-// rows [r0, r1) of a [row][kNP] table -> one kNP row (fixed order).
-__device__ void reduce_rows(const double* in, int r0, int r1, double* out) {
-  __shared__ double red[kRedThreads];
-  const int slot = threadIdx.x % kNP, lane = threadIdx.x / kNP;
-  double v = 0.0;
-  if (lane < kLanesPerSlot)
-    for (int r = r0 + lane; r < r1; r += kLanesPerSlot) v = combine(slot, v, in[(size_t)r * kNP + slot]);
-  red[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x < kNP) {
-    double a = red[threadIdx.x];
-    for (int l = 1; l < kLanesPerSlot; l++) a = combine(threadIdx.x, a, red[l * kNP + threadIdx.x]);
-    out[threadIdx.x] = a;
-  }
-  __syncthreads();
-}
-
-// First level: workgroup b reduces partial rows [src_begin, src_end) into
-// scratch row b.
+// First level, when no Poisson z pass carries it: workgroup b reduces partial
+// rows [src_begin, src_end) into scratch row b.
 __global__ void __launch_bounds__(kRedThreads) k_reduce_rows(const double* __restrict__ in,
                                                              const RedItem* __restrict__ items,
                                                              double* __restrict__ out) {
+  __shared__ double red[kRedThreads];
   const RedItem it = items[blockIdx.x];
-  reduce_rows(in, (int)it.src_begin, (int)it.src_end, out + (size_t)blockIdx.x * kNP);
-}
-
-// Mean of rho + n of run r (workgroup r), for the Poisson source.
-__global__ void __launch_bounds__(kRedThreads) k_mean(const double* __restrict__ rows,
-                                                      const FinDesc* __restrict__ fin) {
-  __shared__ double tot[kNP];
-  const FinDesc F = fin[blockIdx.x];
-  reduce_rows(rows, (int)F.soff, (int)(F.soff + F.nscr), tot);
-  if (threadIdx.x == 0) F.sc->shift = (tot[kGasSlots + S_MASS] + tot[kBmeSlots + S_MASS]) / (double)F.g.ncell;
+  reduce_rows(in, (int)it.src_begin, (int)it.src_end, out + (size_t)blockIdx.x * kNP, red);
 }
 
 // Second level: workgroup r finishes run r.
@@ -63,17 +29,28 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
                                                           const double* __restrict__ epot,
                                                           const FinDesc* __restrict__ fin, int advanced) {
   __shared__ double tot[kNP];
+  __shared__ double red[kRedThreads];
   __shared__ double ered[kRedThreads / 64];
   const FinDesc F = fin[blockIdx.x];
   // the potential-energy partials are summed first (strided per thread, then
   // across each wave and the waves in order), so that their loads overlap
   // the reduction of the scratch rows
   double e = 0.0;
-  for (unsigned b = threadIdx.x; b < F.nep; b += kRedThreads) e += epot[F.eoff + b];
+  {
+    unsigned b = threadIdx.x;
+    for (; b + 3 * kRedThreads < F.nep; b += 4 * kRedThreads) {
+      double x[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) x[q] = epot[F.eoff + b + q * kRedThreads];
+#pragma unroll
+      for (int q = 0; q < 4; q++) e += x[q];
+    }
+    for (; b < F.nep; b += kRedThreads) e += epot[F.eoff + b];
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
   if ((threadIdx.x & 63) == 0) ered[threadIdx.x >> 6] = e;
-  reduce_rows(rows, (int)F.soff, (int)(F.soff + F.nscr), tot);  // its barriers also order ered[]
+  reduce_rows(rows, (int)F.soff, (int)(F.soff + F.nscr), tot, red);  // its barriers also order ered[]
   if (threadIdx.x != 0) return;
   double epot_sum = ered[0];
   for (int w = 1; w < kRedThreads / 64; w++) epot_sum += ered[w];
@@ -126,10 +103,8 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restri
   sc->ndiag += 1;
 }
 
-void launch_reduce(const double* partials, const RedItem* items, int nitems, double* scratch, const FinDesc* fin,
-                   int nruns, hipStream_t st) {
-  k_reduce_rows<<<nitems, kRedThreads, 0, st>>>(partials, items, scratch);
-  k_mean<<<nruns, kRedThreads, 0, st>>>(scratch, fin);
+void launch_reduce(const RedJob& red, hipStream_t st) {
+  k_reduce_rows<<<red.n, kRedThreads, 0, st>>>(red.partials, red.items, red.scratch);
 }
 
 void launch_finalize(const double* scratch, const double* epot_partials, const FinDesc* fin, int nruns,

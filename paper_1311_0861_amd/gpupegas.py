@@ -25,8 +25,7 @@ FIELD_NAMES = [
     "Wxx", "Wxy", "Wxz", "Wyy", "Wyz", "Wzz",
 ]
 GP_PHI = 22
-KERNEL_NAMES = ["eul_gas", "eul_bme", "lag_gas", "lag_bme", "reduce", "fft_xy_fwd", "fft_z_green", "fft_xy_inv",
-                "finalize"]
+KERNEL_NAMES = ["eul_gas", "eul_bme", "lag_gas", "lag_bme", "fft_xy_fwd", "fft_z_green", "fft_xy_inv", "finalize"]
 GP_FFT_AUTO, GP_FFT_LINES = 0, 1  # x and y transforms: per z plane where it fits, or separate passes
 CELL_KERNELS = ["eul_gas", "eul_bme", "lag_gas", "lag_bme"]  # persistent, launch size settable
 
