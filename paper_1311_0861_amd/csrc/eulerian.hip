@@ -231,18 +231,21 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       gas_face(gas_of<2>(pm), gas_of<2>(pc_), gamma, Vz, Pz);
       s_phi[ly + 1][lx + 1] = phm;
     }
+    // the ring of each plane is fetched a plane ahead, so staging it never
+    // waits on memory (every lane has a valid ring address)
+    double rho_h;
+    T m_h[3], e_h, phh;
+    auto load_ring = [&](int kr) {
+      const size_t zr = nxy * (size_t)kr;
+      load(zr, col.xy_h, rho_h, m_h, e_h);
+      phh = phi_at(phi, grav, zr, pc.xy_h);
+    };
+    load_ring(col.k0);
     for (int k = col.k0; k < col.k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
-      const uint32_t xy_c = col.xy_c, xy_h = col.xy_h, pxy_c = pc.xy_c, pxy_h = pc.xy_h;
+      const uint32_t xy_c = col.xy_c, pxy_c = pc.xy_c;
       const T phm = s_phi[ly + 1][lx + 1];
       lds_barrier();  // every thread is done with the previous plane's tiles
-      double rho_h, rho_n;
-      T m_h[3], e_h, m_n[3], e_n;
-      if (col.ring) load(zk, xy_h, rho_h, m_h, e_h);
-      load(zp, xy_c, rho_n, m_n, e_n);
-      const T E = ld_at(E_in, zk, xy_c);
-      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
-      const T phh = (col.ring && grav) ? ld_at(phi, zk, pxy_h) : T(0);
       if (col.ring) {
         T a[kGasPrims];
         prims(rho_h, m_h, e_h, a);
@@ -253,8 +256,14 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
 #pragma unroll
       for (int f = 0; f < kGasPrims; f++) s_g[f][ly + 1][lx + 1] = pc_[f];
       s_phi[ly + 1][lx + 1] = phc;
-      T pn[kGasPrims];
-      prims(rho_n, m_n, e_n, pn);
+      // the next plane's centres (needed by the z+ face, formed last), the
+      // next ring, then this plane's E (needed by the store)
+      double rho_n;
+      T m_n[3], e_n;
+      load(zp, xy_c, rho_n, m_n, e_n);
+      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
+      if (k + 1 < col.k1) load_ring(k + 1);
+      const T E = ld_at(E_in, zk, xy_c);
       lds_barrier();
 
       if (col.active) {
@@ -272,6 +281,8 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
         dV += Vp - Vm;
         Vm = Vz;
         Pm = Pz;
+        T pn[kGasPrims];
+        prims(rho_n, m_n, e_n, pn);
         gas_face(gas_of<2>(pc_), gas_of<2>(pn), gamma, Vp, Pp);
         Vz = Vp;
         Pz = Pp;
@@ -294,8 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
               E - r * dPV - tau * (mc[0] * grad[0] + mc[1] * grad[1] + mc[2] * grad[2]));
         st_at(as_global((T*)R.tmp[oidx(GP_EINT)]), zk, xy, ec - r * gm1 * ec * dV);
       }
-#pragma unroll
-      for (int f = 0; f < kGasPrims; f++) pc_[f] = pn[f];
+      prims(rho_n, m_n, e_n, pc_);
 #pragma unroll
       for (int d = 0; d < 3; d++) mc[d] = m_n[d];
       ec = e_n;
@@ -364,36 +374,41 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       bme_face<T, 2>(bme_of<2>(pm), bme_of<2>(pc_), usz, psz);
       s_phi[ly + 1][lx + 1] = phm;
     }
+    // the ring of each plane is fetched a plane ahead, so staging it never
+    // waits on memory (every lane has a valid ring address)
+    double n_h;
+    T q_h[3], P_h[6], phh;
+    auto load_ring = [&](int kr) {
+      const size_t zr = nxy * (size_t)kr;
+      load(zr, fresh(col.xy_h), n_h, q_h, P_h);
+      phh = phi_at(phi, grav, zr, fresh(pc.xy_h));
+    };
+    load_ring(col.k0);
     for (int k = col.k0; k < col.k1; k++) {
       const size_t zk = nxy * (size_t)k, zp = plane_at(g, k + 1, g.bc[2]);
-      const uint32_t xy_c = fresh(col.xy_c), xy_h = fresh(col.xy_h);
-      const uint32_t pxy_c = fresh(pc.xy_c), pxy_h = fresh(pc.xy_h);
+      const uint32_t xy_c = fresh(col.xy_c);
+      const uint32_t pxy_c = fresh(pc.xy_c);
       const T phm = s_phi[ly + 1][lx + 1];
       lds_barrier();  // every thread is done with the previous plane's tiles
-      {
-        double n_h;
-        T q_h[3], P_h[6];
-        if (col.ring) load(zk, xy_h, n_h, q_h, P_h);
-        const T phh = (col.ring && grav) ? ld_at(phi, zk, pxy_h) : T(0);
-        if (col.ring) {
-          T a[kBmePrims];
-          prims(n_h, q_h, P_h, a);
+      if (col.ring) {
+        T a[kBmePrims];
+        prims(n_h, q_h, P_h, a);
 #pragma unroll
-          for (int f = 0; f < kBmePrims; f++) s_p[f][col.hr][col.hc] = a[f];
-          s_phi[col.hr][col.hc] = phh;
-        }
+        for (int f = 0; f < kBmePrims; f++) s_p[f][col.hr][col.hc] = a[f];
+        s_phi[col.hr][col.hc] = phh;
       }
 #pragma unroll
       for (int f = 0; f < kBmePrims; f++) s_p[f][ly + 1][lx + 1] = pc_[f];
       s_phi[ly + 1][lx + 1] = phc;
+      // the next plane's centres (needed by the z+ face, formed last), the
+      // next ring, then this plane's W (needed by the store)
       double n_n;
       T q_n[3], P_n[6], W[6];
       load(zp, xy_c, n_n, q_n, P_n);
+      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
+      if (k + 1 < col.k1) load_ring(k + 1);
 #pragma unroll
       for (int m = 0; m < 6; m++) W[m] = ld_at(as_global((const T*)R.cur[oidx(GP_WXX + m)]), zk, xy_c);
-      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
-      T pn[kBmePrims];
-      prims(n_n, q_n, P_n, pn);
       lds_barrier();
 
       if (col.active) {
@@ -416,6 +431,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
         bme_face<T, 1>(centre_side<1>(C), bme_at<1>(s_p, ly + 2, lx + 1), us, ps);
         bme_face_add<1>(us, ps, T(1), C, dq, dW, dPi);
         bme_face_add<2>(usz, psz, T(-1), C, dq, dW, dPi);
+        T pn[kBmePrims];
+        prims(n_n, q_n, P_n, pn);
         bme_face<T, 2>(centre_side<2>(C), bme_of<2>(pn), usz, psz);
         bme_face_add<2>(usz, psz, T(1), C, dq, dW, dPi);
         T grad[3] = {T(0), T(0), T(0)};
@@ -440,8 +457,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
             st_at(as_global((T*)R.tmp[oidx(GP_PXX + m)]), zk, xy, C.P[m] - r * dPi[m]);
           }
       }
-#pragma unroll
-      for (int f = 0; f < kBmePrims; f++) pc_[f] = pn[f];
+      prims(n_n, q_n, P_n, pc_);
 #pragma unroll
       for (int d = 0; d < 3; d++) qc[d] = q_n[d];
       phc = php;

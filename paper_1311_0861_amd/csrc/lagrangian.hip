@@ -450,6 +450,20 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
       lds_barrier();
       corner_plane(s_u[(k0 + 1) & 1], s_u[k0 & 1], s_v[k0 & 1]);
     }
+    // The gas kernel fetches each plane's ring one plane ahead too (the
+    // stars / DM kernel has no registers left for it): the ring of plane k
+    // and the velocity ring of plane k + 1, held for the next plane.
+    constexpr bool kRingAhead = C == COMP_GAS;
+    double rd_n = 0.0;
+    T rf_n[NF], ru_n[3];
+    if constexpr (kRingAhead) {
+      const size_t z0 = nxy * (size_t)k0, z1 = plane(k0 + 1);
+      rd_n = ld_at(din, z0, xy_h);
+#pragma unroll
+      for (int f = 3; f < NF; f++) rf_n[f] = ld_at(fin(f), z0, xy_h);
+#pragma unroll
+      for (int f = 0; f < 3; f++) ru_n[f] = ld_at(fin(f), z1, xy_h);
+    }
 
     Acc acc;
     acc_init(acc);
@@ -472,25 +486,44 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
 #pragma unroll
       for (int f = 3; f < NF; f++) fm[f] = s_f[f - 3][ly + 1][lx + 1];
       lds_barrier();  // every thread is done with the previous plane's tiles
-      // ring loads (every lane has a valid ring address; only ring lanes
-      // store), then the plane k+2 prefetch, then the LDS writes
-      const double rd_h = ld_at(din, zk, xy_h);
-      T rf_h[NF], ru_h[3];
+      // ring of this plane (and velocity ring of the next) into LDS, from
+      // registers where it was fetched a plane ahead, else loaded now (every
+      // lane has a valid ring address; only ring lanes store); then the
+      // plane k+2 centre prefetch
+      auto stage_ring = [&](double rd, const T (&rf)[NF], const T (&ru)[3]) {
+        if (ring) {
+          s_dn[hr][hc] = rd;
 #pragma unroll
-      for (int f = 3; f < NF; f++) rf_h[f] = ld_at(fin(f), zk, xy_h);
+          for (int f = 3; f < NF; f++) s_f[f - 3][hr][hc] = rf[f];
 #pragma unroll
-      for (int f = 0; f < 3; f++) ru_h[f] = ld_at(fin(f), zp, xy_h);
-      issue_order();
-      const double dpp = ld_at(din, zpp, xy_c);
+          for (int f = 0; f < 3; f++) s_u[nu][f][hr][hc] = ru[f];
+        }
+      };
+      auto load_ring = [&](size_t zf, size_t zu, double& rd, T (&rf)[NF], T (&ru)[3]) {
+        rd = ld_at(din, zf, xy_h);
+#pragma unroll
+        for (int f = 3; f < NF; f++) rf[f] = ld_at(fin(f), zf, xy_h);
+#pragma unroll
+        for (int f = 0; f < 3; f++) ru[f] = ld_at(fin(f), zu, xy_h);
+      };
+      double dpp;
       T fpp[NF];
+      if constexpr (kRingAhead) {
+        stage_ring(rd_n, rf_n, ru_n);
+        load_ring(zp, zpp, rd_n, rf_n, ru_n);
+        issue_order();
+        dpp = ld_at(din, zpp, xy_c);
 #pragma unroll
-      for (int f = 0; f < NF; f++) fpp[f] = ld_at(fin(f), zpp, xy_c);
-      if (ring) {
-        s_dn[hr][hc] = rd_h;
+        for (int f = 0; f < NF; f++) fpp[f] = ld_at(fin(f), zpp, xy_c);
+      } else {
+        double rd_h;
+        T rf_h[NF], ru_h[3];
+        load_ring(zk, zp, rd_h, rf_h, ru_h);
+        issue_order();
+        dpp = ld_at(din, zpp, xy_c);
 #pragma unroll
-        for (int f = 3; f < NF; f++) s_f[f - 3][hr][hc] = rf_h[f];
-#pragma unroll
-        for (int f = 0; f < 3; f++) s_u[nu][f][hr][hc] = ru_h[f];
+        for (int f = 0; f < NF; f++) fpp[f] = ld_at(fin(f), zpp, xy_c);
+        stage_ring(rd_h, rf_h, ru_h);
       }
       s_dn[ly + 1][lx + 1] = dc;
 #pragma unroll
