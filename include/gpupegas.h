@@ -74,8 +74,10 @@ enum { GP_STAGE_EUL = 0, GP_STAGE_LAG = 1, GP_STAGE_POISSON = 2, GP_STAGE_FINALI
  * is three passes over the half spectrum: the x and y transforms (one kernel
  * per z plane where a plane fits in LDS, else an x and a y kernel, timed
  * together), the z transforms with the symbol (whose launch also reduces the
- * per-tile partial sums of the step), and the inverse x and y.  The finalize
- * (CFL step, diagnostics record) ends the step. */
+ * per-tile partial sums of the step), and the inverse x and y (whose launch
+ * also finishes the step: CFL step, time advance, diagnostics record).
+ * GP_K_FINALIZE times the finalize where it runs on its own: without
+ * gravity, and stage by stage (gp_debug_stage). */
 enum {
   GP_K_EUL_GAS = 0, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME, GP_K_FFT_XY_FWD,
   GP_K_FFT_Z, GP_K_FFT_XY_INV, GP_K_FINALIZE, GP_NKERNELS

@@ -221,13 +221,19 @@ bool any_gravity(const gp_batch* b) {
   return false;
 }
 
-// The Poisson passes; the first z pass also runs the first level of the
-// reduction of the partial rows.
+FinJob fin_job(const gp_batch* b, int advanced) {
+  return FinJob{b->scratch, b->epot, b->fin, (int)b->runs.size(), advanced};
+}
+
+// The Poisson passes.  The first z pass also runs the first level of the
+// reduction of the partial rows; with fin >= 0 the first inverse pass also
+// finishes the step (finalize with advanced = fin), which needs only what the
+// z passes left.
 template <typename T>
-void enqueue_poisson(gp_batch* b, Timer* tm) {
+void enqueue_poisson(gp_batch* b, Timer* tm, int fin) {
   // each pass runs over every size class before the next pass starts
   const int passes[3] = {GP_K_FFT_XY_FWD, GP_K_FFT_Z, GP_K_FFT_XY_INV};
-  bool reduced = false;
+  bool reduced = false, finished = fin < 0;
   for (int k : passes) {
     tmark(b, tm, k, 0);
     for (SizeClass& c : b->classes) {
@@ -249,14 +255,17 @@ void enqueue_poisson(gp_batch* b, Timer* tm) {
           launch_fft_z_green<T>(spec, c.fg, t, b->epot + c.eoff, plane, reduced ? RedJob{} : red_job(b), b->st);
           reduced = true;
           break;
-        case GP_K_FFT_XY_INV:
+        case GP_K_FFT_XY_INV: {
+          const FinJob fj = finished ? FinJob{} : fin_job(b, fin);
           if (plane) {
-            launch_fft_xy_inv<T>(spec, phi, c.fg, t, b->st);
+            launch_fft_xy_inv<T>(spec, phi, c.fg, t, fj, b->st);
           } else {
             launch_fft_y<T>(spec, c.fg, t, true, b->st);
-            launch_fft_x_inv<T>(spec, phi, c.fg, t, b->st);
+            launch_fft_x_inv<T>(spec, phi, c.fg, t, fj, b->st);
           }
+          finished = true;
           break;
+        }
       }
     }
     tmark(b, tm, k, 1);
@@ -265,11 +274,11 @@ void enqueue_poisson(gp_batch* b, Timer* tm) {
 }
 
 // partial rows -> per-run scratch rows (done by the z pass when a run has
-// gravity), then the per-run finalize
+// gravity), then the per-run finalize, as kernels of their own
 void enqueue_finalize(gp_batch* b, int advanced, Timer* tm) {
   tmark(b, tm, GP_K_FINALIZE, 0);
   if (!any_gravity(b)) launch_reduce(red_job(b), b->st);
-  launch_finalize(b->scratch, b->epot, b->fin, (int)b->runs.size(), advanced, b->st);
+  launch_finalize(fin_job(b, advanced), b->st);
   tmark(b, tm, GP_K_FINALIZE, 1);
   tdone(tm, GP_K_FINALIZE);
 }
@@ -385,12 +394,23 @@ void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
       b->parity ^= 1;
       break;
     case GP_STAGE_POISSON:
-      enqueue_poisson<T>(b, tm);
+      enqueue_poisson<T>(b, tm, -1);
       break;
     case GP_STAGE_FINALIZE:
       enqueue_finalize(b, 1, tm);
       break;
   }
+}
+
+// The Poisson solve and the finalize of a step (advanced = 1) or of the
+// initial state (0): the finalize rides along in the Poisson passes where
+// there are any.  Same arithmetic as the two stages run one by one.
+template <typename T>
+void enqueue_end(gp_batch* b, Timer* tm, int advanced) {
+  if (any_gravity(b))
+    enqueue_poisson<T>(b, tm, advanced);
+  else
+    enqueue_finalize(b, advanced, tm);
 }
 
 template <typename T>
@@ -400,8 +420,7 @@ void enqueue_prologue(gp_batch* b) {
                           b->st);
   launch_init_partials<T>(runs, b->work[0], b->nwork[0], b->parity, b->partials, COMP_BME, b->blocks[GP_K_LAG_BME],
                           b->st);
-  enqueue_poisson<T>(b, nullptr);
-  enqueue_finalize(b, 0, nullptr);
+  enqueue_end<T>(b, nullptr, 0);
 }
 
 void run_prologue(gp_batch* b) {
@@ -421,7 +440,12 @@ void run_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
 }
 
 void run_step_direct(gp_batch* b, Timer* tm, bool allow_tune) {
-  for (int st = 0; st < 4; st++) run_stage(b, st, tm, allow_tune);
+  run_stage(b, GP_STAGE_EUL, tm, allow_tune);
+  run_stage(b, GP_STAGE_LAG, tm, allow_tune);
+  if (b->prec == GP_FP64)
+    enqueue_end<double>(b, tm, 1);
+  else
+    enqueue_end<float>(b, tm, 1);
 }
 
 gp_status build_graph(gp_batch* b, int parity) {

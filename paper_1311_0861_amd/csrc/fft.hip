@@ -305,10 +305,16 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __rest
 }
 
 // ---- x inverse: C rows -> real rows of phi ---------------------------------
+// The first fin.n workgroups finish the step instead (one per run).
 template <typename T>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __restrict__ spec, T* __restrict__ phi,
-                                                           FftGeom f, FftTables<T> t) {
+                                                           FftGeom f, FftTables<T> t, FinJob fin) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  if ((int)blockIdx.x < fin.n) {
+    finalize_run(fin, (int)blockIdx.x, reinterpret_cast<double*>(smem_raw));
+    return;
+  }
+  const int bid = (int)blockIdx.x - fin.n;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int M = f.ax.L, xp = M | 1;  // odd row pitch
   const int RB = f.rows_per_block;
@@ -316,7 +322,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __rest
   cplx<T>* tw = xin + RB * (M + 1);
   cplx<T>* wn = tw + M;
   const int nrows = f.ny * f.nz * f.nruns;
-  const int row0 = blockIdx.x * RB;
+  const int row0 = bid * RB;
   const int rows = min(RB, nrows - row0);
   load_twiddles<kFftThreads>(tw, t.tw_x, M);
   load_twiddles<kFftThreads>(wn, t.wn_x, M + 1);
@@ -539,14 +545,20 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
   }
 }
 
+// The first fin.n workgroups finish the step instead (one per run).
 template <typename T>
 __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_inv(const cplx<T>* __restrict__ spec, T* __restrict__ phi,
-                                                             FftGeom f, FftTables<T> t) {
+                                                             FftGeom f, FftTables<T> t, FinJob fin) {
   constexpr int NT = kPlaneThreads, PM = plane_points<T>();
+  if ((int)blockIdx.x < fin.n) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    finalize_run(fin, (int)blockIdx.x, reinterpret_cast<double*>(smem_raw));
+    return;
+  }
   const PlaneLds<T> s = plane_lds(f, t);
   const int M = f.ax.L, ny = f.ny, pp = f.pp;
   const FastDiv dm(M), dh(M / 2 + 1);
-  const int plane = blockIdx.x;
+  const int plane = (int)blockIdx.x - fin.n;
   const int slot = plane / f.nz, z = plane - slot * f.nz;
   const cplx<T>* in = spec + ((size_t)slot * ny * f.nz + z) * f.px;
   const size_t kys = (size_t)f.nz * f.px;
@@ -610,8 +622,11 @@ void launch_fft_xy_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftG
 }
 
 template <typename T>
-void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st) {
-  k_fft_xy_inv<T><<<f.nz * f.nruns, kPlaneThreads, plane_lds_bytes(f, sizeof(cplx<T>)), st>>>(spec, phi, f, t);
+void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, const FinJob& fin,
+                       hipStream_t st) {
+  size_t lds = plane_lds_bytes(f, sizeof(cplx<T>));
+  if (fin.n > 0) lds = std::max(lds, sizeof(double) * kFinLds);
+  k_fft_xy_inv<T><<<f.nz * f.nruns + fin.n, kPlaneThreads, lds, st>>>(spec, phi, f, t, fin);
 }
 
 static size_t x_lds_bytes(const FftGeom& f, size_t csz, bool inv) {
@@ -630,10 +645,13 @@ void launch_fft_x_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGe
 }
 
 template <typename T>
-void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st) {
+void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, const FinJob& fin,
+                      hipStream_t st) {
   const int nrows = f.ny * f.nz * f.nruns;
-  const int nblk = (nrows + f.rows_per_block - 1) / f.rows_per_block;
-  k_fft_x_inv<T><<<nblk, kFftThreads, x_lds_bytes(f, sizeof(cplx<T>), true), st>>>(spec, phi, f, t);
+  const int nblk = (nrows + f.rows_per_block - 1) / f.rows_per_block + fin.n;
+  size_t lds = x_lds_bytes(f, sizeof(cplx<T>), true);
+  if (fin.n > 0) lds = std::max(lds, sizeof(double) * kFinLds);
+  k_fft_x_inv<T><<<nblk, kFftThreads, lds, st>>>(spec, phi, f, t, fin);
 }
 
 template <typename T>
@@ -670,9 +688,9 @@ template void launch_fft_x_fwd<double>(const SrcSlot*, int, cplx<double>*, const
 template void launch_fft_x_fwd<float>(const SrcSlot*, int, cplx<float>*, const FftGeom&, const FftTables<float>&,
                                       hipStream_t);
 template void launch_fft_x_inv<double>(const cplx<double>*, double*, const FftGeom&, const FftTables<double>&,
-                                       hipStream_t);
+                                       const FinJob&, hipStream_t);
 template void launch_fft_x_inv<float>(const cplx<float>*, float*, const FftGeom&, const FftTables<float>&,
-                                      hipStream_t);
+                                      const FinJob&, hipStream_t);
 template void launch_fft_y<double>(cplx<double>*, const FftGeom&, const FftTables<double>&, bool, hipStream_t);
 template void launch_fft_y<float>(cplx<float>*, const FftGeom&, const FftTables<float>&, bool, hipStream_t);
 template void launch_fft_z_green<double>(cplx<double>*, const FftGeom&, const FftTables<double>&, double*, bool,
@@ -685,9 +703,9 @@ template void launch_fft_xy_fwd<double>(const SrcSlot*, int, cplx<double>*, cons
 template void launch_fft_xy_fwd<float>(const SrcSlot*, int, cplx<float>*, const FftGeom&, const FftTables<float>&,
                                        hipStream_t);
 template void launch_fft_xy_inv<double>(const cplx<double>*, double*, const FftGeom&, const FftTables<double>&,
-                                        hipStream_t);
+                                        const FinJob&, hipStream_t);
 template void launch_fft_xy_inv<float>(const cplx<float>*, float*, const FftGeom&, const FftTables<float>&,
-                                       hipStream_t);
+                                       const FinJob&, hipStream_t);
 template hipError_t fft_plane_prepare<double>(int);
 template hipError_t fft_plane_prepare<float>(int);
 

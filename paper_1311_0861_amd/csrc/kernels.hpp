@@ -85,6 +85,26 @@ struct RedJob {
   double* scratch;
   int n;  // workgroups; 0 = none
 };
+// Second level and the end of the step: workgroup r finishes run r -- the
+// CFL step, time advance and diagnostics record (advanced = 1 after a step,
+// 0 for the initial state).  It rides along in the last inverse Poisson pass
+// of a step, or runs on its own.
+struct FinDesc {
+  Grid g;
+  Phys ph;
+  unsigned soff, nscr;  // scratch rows of the run
+  unsigned eoff, nep;   // potential-energy partials of the run
+  double epot_scale;    // 1 / (nx ny nz)
+  DevScalars* sc;
+  gp_diag* ring;
+};
+struct FinJob {
+  const double* scratch;
+  const double* epot;
+  const FinDesc* fin;
+  int n;  // runs (workgroups); 0 = none
+  int advanced;
+};
 
 // Poisson source of each run of a size class: s = rho + n, formed in FP64
 // from the current densities (slot = run position in the class).
@@ -107,26 +127,15 @@ template <typename T>
 void launch_fft_xy_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
                        hipStream_t st);
 template <typename T>
-void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st);
+void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, const FinJob& fin,
+                       hipStream_t st);
 template <typename T>
-void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, hipStream_t st);
+void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, const FinJob& fin,
+                      hipStream_t st);
 
 // ---- reductions / finalize ---------------------------------------------
-// Second level of the reduction (scratch rows of a run), then per run the CFL
-// step, time advance and diagnostics record.  advanced = 1 after a step, 0
-// for the initial state.
-struct FinDesc {
-  Grid g;
-  Phys ph;
-  unsigned soff, nscr;  // scratch rows of the run
-  unsigned eoff, nep;   // potential-energy partials of the run
-  double epot_scale;    // 1 / (nx ny nz)
-  DevScalars* sc;
-  gp_diag* ring;
-};
 void launch_reduce(const RedJob& red, hipStream_t st);
-void launch_finalize(const double* scratch, const double* epot_partials, const FinDesc* fin, int nruns,
-                     int advanced, hipStream_t st);
+void launch_finalize(const FinJob& job, hipStream_t st);
 
 // ---- conversions ---------------------------------------------------------
 template <typename D, typename S>
