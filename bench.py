@@ -22,8 +22,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=128, help="cells per axis")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--profile-steps", type=int, default=20, help="steps timed kernel by kernel")
