@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
     if (threadIdx.x == 0) {
       double s = 0.0;
       for (int w = 0; w < kFftThreads / 64; w++) s += red[w];
-      epot_partials[bid] = s;
+      epot_partials[(size_t)oline * nchunks + chunk] = s;  // a run's partials are contiguous
     }
     col_fft(lds, cb, ax, tw, true);
   }

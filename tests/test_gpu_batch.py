@@ -103,3 +103,29 @@ def test_ensemble_members_radix3(gp, W):
         for f in ref:
             np.testing.assert_array_equal(got[f], ref[f], err_msg="member %d field %s" % (pick[r], f))
         s.close()
+
+
+def test_same_size_runs_keep_their_potential_energy(gp, W):
+    """Two runs of one grid size whose ny (12) is not a multiple of the z
+    pass's 8-line XCD groups, so one group spans both runs: every diagnostics
+    record of each member (its potential energy among them) equals that of the
+    same run alone, bitwise."""
+    say("same-size runs, ny = 12")
+    members = [W.random_periodic(n=(16, 12, 8), seed=s) for s in (21, 22)]
+    b = gp.Batch([c for c, _ in members])
+    for r, (_, st) in enumerate(members):
+        b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
+    b.step(3)
+    b.sync()
+    for r, (cfg, st) in enumerate(members):
+        s = gp.Sim(cfg)
+        s.set_state({k: v.to("cuda") for k, v in st.items()})
+        s.step(3)
+        s.sync()
+        assert b.diag(r) == s.diag(), r
+        ref = gpu_state(s)
+        got = _batch_state(b, r)
+        for f in ref:
+            np.testing.assert_array_equal(got[f], ref[f], err_msg="run %d field %s" % (r, f))
+        s.close()
+    b.close()
