@@ -74,6 +74,7 @@ struct SizeClass {
   void* tw_x = nullptr;
   void* wn_x = nullptr;
   void* tw_y = nullptr;
+  void* tw_yh = nullptr;
   void* tw_z = nullptr;
   double* dtab[3] = {nullptr, nullptr, nullptr};
   FftGeom fg{};
@@ -194,6 +195,7 @@ FftTables<T> tables(const SizeClass& c) {
   t.tw_x = static_cast<const cplx<T>*>(c.tw_x);
   t.wn_x = static_cast<const cplx<T>*>(c.wn_x);
   t.tw_y = static_cast<const cplx<T>*>(c.tw_y);
+  t.tw_yh = static_cast<const cplx<T>*>(c.tw_yh);
   t.tw_z = static_cast<const cplx<T>*>(c.tw_z);
   t.dx = c.dtab[0];
   t.dy = c.dtab[1];
@@ -632,16 +634,22 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     // columns per workgroup: at most 8 (and the LDS budget), spread evenly
     // over the px = nx/2 + 1 half-spectrum columns so no chunk is nearly empty
     // (8 measured faster than 16, 4 or 2 at 64^3 to 256^3)
-    auto even_cols = [&](int L) {
-      const int cmax = std::max(1, std::min({8, f.px, maxpts / L}));
+    auto even_cols = [&](int L, int cap) {
+      const int cmax = std::max(1, std::min({cap, f.px, maxpts / L}));
       const int nch = (f.px + cmax - 1) / cmax;
       return (f.px + nch - 1) / nch;
     };
-    f.cols_y = even_cols(f.ay.L);
-    f.cols_z = even_cols(f.az.L);
-    // x and y transforms of a whole z plane per workgroup where it fits
-    f.pp = f.ax.L | 1;  // odd row pitch: lanes on neighbouring rows hit other banks
-    f.plane = c.G != 0.0 && plane_lds_bytes(f, 2 * es) <= (size_t)lds_max;
+    f.cols_y = even_cols(f.ay.L, 8);
+    // x and y transforms of the even or the odd rows of a z plane per
+    // workgroup where they fit
+    f.ayh = make_axis(f.ny / 2);
+    f.hp = (f.ax.L + 1) | 1;  // odd row pitch: lanes on neighbouring rows hit other banks
+    // (where two such workgroups fit on a CU; with one per CU the separate x
+    // and y passes are faster, e.g. 256^3 FP32)
+    f.plane = c.G != 0.0 && 2 * plane_lds_bytes(f, 2 * es) <= (size_t)lds_max;
+    // the z pass after the plane passes holds the columns of two ky rows; 4
+    // of each keeps its LDS and workgroup count those of 8 columns of one row
+    f.cols_z = f.plane ? even_cols(2 * f.az.L, 4) : even_cols(f.az.L, 8);
     if (f.plane && !planes_ready) {
       // one limit for every size class: the kernels are shared
       const hipError_t e =
@@ -661,6 +669,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
       c.tw_x = dalloc(b, (size_t)f.ax.L * 2 * es, &st);
       c.wn_x = dalloc(b, (size_t)(f.ax.L + 1) * 2 * es, &st);
       c.tw_y = dalloc(b, (size_t)f.ay.L * 2 * es, &st);
+      c.tw_yh = dalloc(b, (size_t)f.ayh.L * 2 * es, &st);
       c.tw_z = dalloc(b, (size_t)f.az.L * 2 * es, &st);
       c.dtab[0] = static_cast<double*>(dalloc(b, (size_t)f.px * sizeof(double), &st));
       c.dtab[1] = static_cast<double*>(dalloc(b, (size_t)f.ny * sizeof(double), &st));
@@ -769,6 +778,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     put_tw(c.tw_x, f.ax.L, f.ax.L);
     put_tw(c.wn_x, f.ax.L + 1, f.nx);
     put_tw(c.tw_y, f.ay.L, f.ay.L);
+    put_tw(c.tw_yh, f.ayh.L, f.ayh.L);
     put_tw(c.tw_z, f.az.L, f.az.L);
     put_d(c.dtab[0], f.px, f.nx);
     put_d(c.dtab[1], f.ny, f.ny);

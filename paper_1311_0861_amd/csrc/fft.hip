@@ -365,12 +365,17 @@ __device__ __forceinline__ ColBlock col_block(int b, int nchunks, int nolines) {
 
 // In the z pass the first red.n workgroups reduce partial rows instead (they
 // need nothing from the transform, and the pass has room beside it).
+// With pair set (the z pass after the plane passes) a workgroup takes the cb
+// columns of two spectrum rows, line o and line o + pair_stride / outer_stride
+// (ky and ky + ny/2), which hold E and O: it forms C[ky] = E + W^ky O and
+// C[ky + ny/2] = E - W^ky O before the z transforms, and stores e = C[ky] +
+// C[ky + ny/2] and o = (C[ky] - C[ky + ny/2]) W^-ky after them.
 template <typename T, int MODE>  // MODE 0: forward, 1: inverse, 2: forward * symbol * inverse
 __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t,
                                                          FftAxis ax, const cplx<T>* __restrict__ twg, int cb,
                                                          size_t stride, size_t outer_stride, int outer_div,
                                                          size_t run_stride, double* __restrict__ epot_partials,
-                                                         RedJob red) {
+                                                         RedJob red, int pair, size_t pair_stride) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   int bid = (int)blockIdx.x, nblk = (int)gridDim.x;
   if constexpr (MODE == 2) {
@@ -385,89 +390,140 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
   }
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int L = ax.L;
-  // LDS holds the block as L rows of cb columns: element j of column c at
-  // j * cb + c, so that lanes on neighbouring columns touch neighbouring words
-  cplx<T>* tw = lds + cb * L;
+  const int nr = (MODE == 2 && pair) ? 2 : 1;  // spectrum rows per workgroup
+  const int cw = nr * cb;                      // LDS columns: cb per row
+  // LDS holds the block as L rows of cw columns: element j of column c at
+  // j * cw + c, so that lanes on neighbouring columns touch neighbouring words
+  cplx<T>* tw = lds + cw * L;
   const int nchunks = (f.px + cb - 1) / cb;
   const ColBlock cbk = col_block(bid, nchunks, nblk / nchunks);
   const int chunk = cbk.chunk, oline = cbk.oline;
-  const int outer = oline % outer_div;
+  const int run = oline / outer_div, outer = oline - run * outer_div;
   const int kx0 = chunk * cb;
   const int ncols = min(cb, f.px - kx0);
   load_twiddles<kFftThreads>(tw, twg, L);
-  const FastDiv dcb(cb);
+  const FastDiv dcw(cw), dcb(cb);
   // z pass: the symbol's factors D(kz) and D(kx) D(ky) of this block
   double* gz = reinterpret_cast<double*>(tw + L);
   double* gxy = gz + L;
   if constexpr (MODE == 2) {
-    const double dy = gload(t.dy + outer);
-    for (int q = threadIdx.x; q < L + ncols; q += kFftThreads) {
-      if (q < L)
+    for (int q = threadIdx.x; q < L + cw; q += kFftThreads) {
+      if (q < L) {
         gz[q] = gload(t.dz + q);
-      else
-        gxy[q - L] = gload(t.dx + kx0 + q - L) * dy;
+      } else {
+        const int c = q - L, h = c >= cb ? 1 : 0, cc = c - h * cb;
+        gxy[c] = cc < ncols ? gload(t.dx + kx0 + cc) * gload(t.dy + outer + h * outer_div) : 0.0;
+      }
     }
   }
-  cplx<T>* base = spec + (size_t)(oline / outer_div) * run_stride + (size_t)outer * outer_stride + kx0;
-  staged_copy<kFftThreads, 4, cplx<T>>(
-      cb * L,
-      [&](int q) {
-        const int j = (int)dcb.div(q), c = q - j * cb;
-        const cplx<T> v = gload(base + (size_t)j * stride + min(c, ncols - 1));
-        return (c < ncols) ? v : cplx<T>{T(0), T(0)};
-      },
-      [&](int q, cplx<T> v) { lds[q] = v; });
+  cplx<T>* base = spec + (size_t)run * run_stride + (size_t)outer * outer_stride + kx0;
+  cplx<T> wk = {T(1), T(0)};  // W^ky of the row pair
+  if (nr == 2) {
+    // E and O of one (kz, kx) by one thread, combined on their way to LDS
+    wk = gload(t.tw_y + outer);
+    struct Pair {
+      cplx<T> e, o;
+    };
+    staged_copy<kFftThreads, 2, Pair>(
+        cb * L,
+        [&](int q) {
+          const int j = (int)dcb.div(q), cc = q - j * cb;
+          const cplx<T>* g = base + (size_t)j * stride + min(cc, ncols - 1);
+          Pair v{gload(g), gload(g + pair_stride)};
+          if (cc >= ncols) v = Pair{{T(0), T(0)}, {T(0), T(0)}};
+          return v;
+        },
+        [&](int q, Pair v) {
+          const int j = (int)dcb.div(q), cc = q - j * cb;
+          const cplx<T> o = cmul(v.o, wk);
+          lds[j * cw + cc] = cadd(v.e, o);
+          lds[j * cw + cb + cc] = csub(v.e, o);
+        });
+  } else {
+    staged_copy<kFftThreads, 4, cplx<T>>(
+        cw * L,
+        [&](int q) {
+          const int j = (int)dcw.div(q), c = q - j * cw;
+          const cplx<T> v = gload(base + (size_t)j * stride + min(c, ncols - 1));
+          return (c < ncols) ? v : cplx<T>{T(0), T(0)};
+        },
+        [&](int q, cplx<T> v) { lds[q] = v; });
+  }
   __syncthreads();
-  col_fft(lds, cb, ax, tw, MODE == 1);
+  col_fft(lds, cw, ax, tw, MODE == 1);
   if constexpr (MODE == 2) {
-    // z pass: outer = ky, line position = kz, column = kx
-    __shared__ double red[kFftThreads / 64];
-    double ep = 0.0;
-    for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
-      const int kz = (int)dcb.div(q), c = q - kz * cb;
-      if (c >= ncols) continue;
-      const int kx = kx0 + c;
+    // z pass: line position = kz, column = (row h, kx); the potential-energy
+    // partial of each row goes to slot (line, chunk), so that a run's
+    // partials are contiguous whichever form ran
+    __shared__ double red_ep[2][kFftThreads / 64];
+    double ep[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < cw * L; q += kFftThreads) {
+      const int kz = (int)dcw.div(q), c = q - kz * cw, h = c >= cb ? 1 : 0, cc = c - h * cb;
+      if (cc >= ncols) continue;
+      const int kx = kx0 + cc, ky = outer + h * outer_div;
       cplx<T>& v = lds[q];
       double gk = 0.0;
-      if (kx != 0 || outer != 0 || kz != 0) gk = f.green_scale / (1.0 - gxy[c] * gz[kz]);
+      if (kx != 0 || ky != 0 || kz != 0) gk = f.green_scale / (1.0 - gxy[c] * gz[kz]);
       const double w = (kx == 0 || 2 * kx == f.nx) ? 1.0 : 2.0;  // Hermitian half spectrum
-      ep += w * gk * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
+      ep[h] += w * gk * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
       const T gs = (T)(gk * f.norm);
       v.x *= gs;
       v.y *= gs;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) ep += __shfl_xor(ep, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ep;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int w = 0; w < kFftThreads / 64; w++) s += red[w];
-      epot_partials[(size_t)oline * nchunks + chunk] = s;  // a run's partials are contiguous
+    for (int h = 0; h < 2; h++) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) ep[h] += __shfl_xor(ep[h], off, 64);
+      if ((threadIdx.x & 63) == 0) red_ep[h][threadIdx.x >> 6] = ep[h];
     }
-    col_fft(lds, cb, ax, tw, true);
+    __syncthreads();
+    if (threadIdx.x < nr) {
+      const int h = threadIdx.x;
+      double s = 0.0;
+      for (int w = 0; w < kFftThreads / 64; w++) s += red_ep[h][w];
+      const size_t line = (size_t)run * outer_div * nr + outer + h * outer_div;  // spectrum row of the run
+      epot_partials[line * nchunks + chunk] = s;
+    }
+    col_fft(lds, cw, ax, tw, true);
+    if (nr == 2) {
+      // e and o of one (z, kx) by one thread, formed on their way out
+      const cplx<T> wc = {wk.x, -wk.y};
+      for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
+        const int j = (int)dcb.div(q), cc = q - j * cb;
+        if (cc >= ncols) continue;
+        const cplx<T> c0 = lds[j * cw + cc], c1 = lds[j * cw + cb + cc];
+        cplx<T>* g = base + (size_t)j * stride + cc;
+        g[0] = cadd(c0, c1);
+        g[pair_stride] = cmul(csub(c0, c1), wc);
+      }
+      return;
+    }
   }
-  for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
-    const int j = (int)dcb.div(q), c = q - j * cb;
+  for (int q = threadIdx.x; q < cw * L; q += kFftThreads) {
+    const int j = (int)dcw.div(q), c = q - j * cw;
     if (c < ncols) base[(size_t)j * stride + c] = lds[q];
   }
 }
 
-// ---- xy plane passes: both transverse transforms of one z plane in LDS -----
-// A workgroup holds the plane as ny rows of pitch pp >= M + 1 complex values
-// (M = nx / 2).  The split leaves X[0] and X[M] of every row real, so they
-// share column 0 as X[0] + i X[M]: the y transforms then run on M columns, and
-// the spectra of the two real columns are separated afterwards from
-// W = FFT_y(X[0] + i X[M]):
-//   Y0[ky] = (W[ky] + conj W[-ky]) / 2,  YM[ky] = -i (W[ky] - conj W[-ky]) / 2.
-// The inverse packs C[ky][0] + i C[ky][M] into column 0 the same way (both are
-// spectra of real columns, so their inverse transforms come out real).
+// ---- xy plane passes: the transverse transforms of half a z plane in LDS ---
+// The y transform of length ny splits by row parity (decimation in time):
+//   C[k] = E[k] + W^k O[k],  C[k + ny/2] = E[k] - W^k O[k],  k < ny/2,
+// with E, O the length-ny/2 transforms of the even and the odd rows and
+// W = exp(-2 pi i / ny).  Workgroup (plane, p) takes rows 2j + p: the x
+// transform of each row (nx/2 + 1 bins, from the half-length complex FFT and
+// the split) and the length-ny/2 transforms of the nx/2 + 1 columns, held as
+// ny/2 rows of odd pitch hp; it stores E or O in spectrum rows p ny/2 + k.
+// The z pass forms C from E and O before its transforms and returns the even
+// and odd parts e = C[k] + C[k + ny/2], o = (C[k] - C[k + ny/2]) W^-k after
+// them, so that the inverse plane pass again takes one row parity: row 2j + p
+// of the inverse y transform is the length-ny/2 inverse transform of e or o.
+// Two workgroups per plane, each with half the LDS of a whole plane.
 template <typename T>
 struct PlaneLds {
-  cplx<T>* pl;   // ny x pp plane
+  cplx<T>* pl;   // ny/2 x hp half plane
   cplx<T>* twx;  // M
   cplx<T>* wn;   // M + 1
-  cplx<T>* twy;  // ny
+  cplx<T>* twy;  // ny / 2
 };
 
 template <typename T>
@@ -476,12 +532,12 @@ __device__ __forceinline__ PlaneLds<T> plane_lds(const FftGeom& f, const FftTabl
   PlaneLds<T> s;
   const int M = f.ax.L;
   s.pl = reinterpret_cast<cplx<T>*>(smem_raw);
-  s.twx = s.pl + f.ny * f.pp;
+  s.twx = s.pl + (f.ny / 2) * f.hp;
   s.wn = s.twx + M;
   s.twy = s.wn + M + 1;
   load_twiddles<kPlaneThreads>(s.twx, t.tw_x, M);
   load_twiddles<kPlaneThreads>(s.wn, t.wn_x, M + 1);
-  load_twiddles<kPlaneThreads>(s.twy, t.tw_y, f.ny);
+  load_twiddles<kPlaneThreads>(s.twy, t.tw_yh, f.ny / 2);
   return s;
 }
 
@@ -490,35 +546,38 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
                                                              cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t) {
   constexpr int NT = kPlaneThreads, PM = plane_points<T>();
   const PlaneLds<T> s = plane_lds(f, t);
-  const int M = f.ax.L, ny = f.ny, pp = f.pp;
+  const int M = f.ax.L, hy = f.ny / 2, hp = f.hp;
   const FastDiv dm(M), dm1(M + 1), dh(M / 2 + 1);
-  const int plane = blockIdx.x;  // run * nz + z
+  const int plane = (int)blockIdx.x >> 1, p = (int)blockIdx.x & 1;  // run * nz + z, row parity
   const int slot = plane / f.nz, z = plane - slot * f.nz;
   const SrcSlot& S = src[slot];
-  const size_t off = (size_t)z * ny * f.nx;
+  // rows 2j + p of the plane, M packed (even, odd) pairs each
+  const size_t off = ((size_t)z * f.ny + p) * f.nx;
   const dpair* rho = reinterpret_cast<const dpair*>(S.rho[parity] + off);
   const dpair* nb = reinterpret_cast<const dpair*>(S.nb[parity] + off);
-  // packed (even, odd) pairs of each row of s
   staged_copy<NT, 8, cplx<T>>(
-      ny * M,
+      hy * M,
       [&](int q) {
-        const dpair a = gload(rho + q), c = gload(nb + q);
+        const int j = (int)dm.div(q);
+        const size_t e = (size_t)q + (size_t)j * M;  // pair m of row 2j + p: 2 j M + m
+        const dpair a = gload(rho + e), c = gload(nb + e);
         return cplx<T>{(T)(a.x + c.x), (T)(a.y + c.y)};
       },
       [&](int q, cplx<T> v) {
-        const int y = (int)dm.div(q), m = q - y * M;
-        s.pl[y * pp + m] = v;
+        const int j = (int)dm.div(q), m = q - j * M;
+        s.pl[j * hp + m] = v;
       });
   lds_barrier();
-  lds_fft<T, NT, PM>(s.pl, ny, pp, 1, f.ax, s.twx, false);
-  // split of each row, pairs (k, M - k) by one thread; X[0] + i X[M] in column 0
+  lds_fft<T, NT, PM>(s.pl, hy, hp, 1, f.ax, s.twx, false);
+  // split of each row into its M + 1 bins, pairs (k, M - k) by one thread
   const int H = M / 2 + 1;
-  for (int q = threadIdx.x; q < ny * H; q += NT) {
-    const int y = (int)dh.div(q), k = q - y * H;
-    cplx<T>* row = s.pl + y * pp;
+  for (int q = threadIdx.x; q < hy * H; q += NT) {
+    const int j = (int)dh.div(q), k = q - j * H;
+    cplx<T>* row = s.pl + j * hp;
     if (k == 0) {
       const cplx<T> z0 = row[0];
-      row[0] = {z0.x + z0.y, z0.x - z0.y};
+      row[0] = {z0.x + z0.y, T(0)};
+      row[M] = {z0.x - z0.y, T(0)};
     } else {
       const cplx<T> a = row[k], b = row[M - k];
       row[k] = split_fwd(a, b, s.wn[k]);
@@ -526,22 +585,14 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
     }
   }
   lds_barrier();
-  lds_fft<T, NT, PM>(s.pl, M, 1, pp, f.ay, s.twy, false);
-  // spectrum rows ky-major: C[run][ky][z][kx], so that the z pass reads
-  // contiguous blocks
-  cplx<T>* out = spec + ((size_t)slot * ny * f.nz + z) * f.px;
+  lds_fft<T, NT, PM>(s.pl, M + 1, 1, hp, f.ayh, s.twy, false);
+  // E or O into spectrum rows p ny/2 + k, ky-major: C[run][ky][z][kx], so
+  // that the z pass reads contiguous blocks
+  cplx<T>* out = spec + (((size_t)slot * f.ny + (size_t)p * hy) * f.nz + z) * f.px;
   const size_t kys = (size_t)f.nz * f.px;
-  for (int q = threadIdx.x; q < ny * (M + 1); q += NT) {
+  for (int q = threadIdx.x; q < hy * (M + 1); q += NT) {
     const int ky = (int)dm1.div(q), kx = q - ky * (M + 1);
-    cplx<T> v;
-    if (kx > 0 && kx < M) {
-      v = s.pl[ky * pp + kx];
-    } else {
-      const cplx<T> w = s.pl[ky * pp], wc = s.pl[(ky == 0 ? 0 : ny - ky) * pp];
-      v = kx == 0 ? cplx<T>{T(0.5) * (w.x + wc.x), T(0.5) * (w.y - wc.y)}
-                  : cplx<T>{T(0.5) * (w.y + wc.y), T(-0.5) * (w.x - wc.x)};
-    }
-    out[ky * kys + kx] = v;
+    out[ky * kys + kx] = s.pl[ky * hp + kx];
   }
 }
 
@@ -556,52 +607,53 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_inv(const cplx<T>* __r
     return;
   }
   const PlaneLds<T> s = plane_lds(f, t);
-  const int M = f.ax.L, ny = f.ny, pp = f.pp;
-  const FastDiv dm(M), dh(M / 2 + 1);
-  const int plane = (int)blockIdx.x - fin.n;
+  const int M = f.ax.L, hy = f.ny / 2, hp = f.hp;
+  const FastDiv dm(M), dm1(M + 1), dh(M / 2 + 1);
+  const int b = (int)blockIdx.x - fin.n;
+  const int plane = b >> 1, p = b & 1;  // run * nz + z, row parity
   const int slot = plane / f.nz, z = plane - slot * f.nz;
-  const cplx<T>* in = spec + ((size_t)slot * ny * f.nz + z) * f.px;
+  const cplx<T>* in = spec + (((size_t)slot * f.ny + (size_t)p * hy) * f.nz + z) * f.px;
   const size_t kys = (size_t)f.nz * f.px;
+  // e or o (rows p ny/2 + k, left there by the z pass)
   staged_copy<NT, 8, cplx<T>>(
-      ny * M,
+      hy * (M + 1),
       [&](int q) {
-        const int ky = (int)dm.div(q), kx = q - ky * M;
-        // column 0 takes C[ky][0] + i C[ky][M]
-        const cplx<T>* r = in + ky * kys;
-        const cplx<T> a = gload(r + kx), c = gload(r + (kx == 0 ? M : kx));
-        return kx == 0 ? cplx<T>{a.x - c.y, a.y + c.x} : a;
+        const int ky = (int)dm1.div(q), kx = q - ky * (M + 1);
+        return gload(in + ky * kys + kx);
       },
       [&](int q, cplx<T> v) {
-        const int ky = (int)dm.div(q), kx = q - ky * M;
-        s.pl[ky * pp + kx] = v;
+        const int ky = (int)dm1.div(q), kx = q - ky * (M + 1);
+        s.pl[ky * hp + kx] = v;
       });
   lds_barrier();
-  lds_fft<T, NT, PM>(s.pl, M, 1, pp, f.ay, s.twy, true);
+  lds_fft<T, NT, PM>(s.pl, M + 1, 1, hp, f.ayh, s.twy, true);
+  // complex-to-real split of each row: M + 1 bins -> M packed pairs
   const int H = M / 2 + 1;
-  for (int q = threadIdx.x; q < ny * H; q += NT) {
-    const int y = (int)dh.div(q), k = q - y * H;
-    cplx<T>* row = s.pl + y * pp;
+  for (int q = threadIdx.x; q < hy * H; q += NT) {
+    const int j = (int)dh.div(q), k = q - j * H;
+    cplx<T>* row = s.pl + j * hp;
     if (k == 0) {
-      const cplx<T> w = row[0];  // X[0] + i X[M], both real
-      row[0] = {T(0.5) * (w.x + w.y), T(0.5) * (w.x - w.y)};
+      const T x0 = row[0].x, xm = row[M].x;  // X[0] and X[M] of a real row are real
+      row[0] = {T(0.5) * (x0 + xm), T(0.5) * (x0 - xm)};
     } else {
-      const cplx<T> a = row[k], b = row[M - k];
-      row[k] = split_inv(a, b, s.wn[k]);
-      if (2 * k != M) row[M - k] = split_inv(b, a, s.wn[M - k]);
+      const cplx<T> a = row[k], c = row[M - k];
+      row[k] = split_inv(a, c, s.wn[k]);
+      if (2 * k != M) row[M - k] = split_inv(c, a, s.wn[M - k]);
     }
   }
   lds_barrier();
-  lds_fft<T, NT, PM>(s.pl, ny, pp, 1, f.ax, s.twx, true);
-  cplx<T>* dst = reinterpret_cast<cplx<T>*>(phi) + (size_t)plane * ny * M;
-  for (int q = threadIdx.x; q < ny * M; q += NT) {
-    const int y = (int)dm.div(q), m = q - y * M;
-    dst[q] = s.pl[y * pp + m];
+  lds_fft<T, NT, PM>(s.pl, hy, hp, 1, f.ax, s.twx, true);
+  // rows 2j + p of phi, M packed pairs each
+  cplx<T>* dst = reinterpret_cast<cplx<T>*>(phi) + ((size_t)plane * f.ny + p) * M;
+  for (int q = threadIdx.x; q < hy * M; q += NT) {
+    const int j = (int)dm.div(q), m = q - j * M;
+    dst[(size_t)q + (size_t)j * M] = s.pl[j * hp + m];
   }
 }
 
 size_t plane_lds_bytes(const FftGeom& f, size_t csz) {
   const size_t M = f.ax.L;
-  return csz * ((size_t)f.ny * f.pp + M + M + 1 + f.ny);
+  return csz * ((size_t)(f.ny / 2) * f.hp + M + M + 1 + f.ny / 2);
 }
 
 template <typename T>
@@ -617,8 +669,8 @@ hipError_t fft_plane_prepare(int bytes) {
 template <typename T>
 void launch_fft_xy_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
                        hipStream_t st) {
-  k_fft_xy_fwd<T><<<f.nz * f.nruns, kPlaneThreads, plane_lds_bytes(f, sizeof(cplx<T>)), st>>>(src, parity, spec,
-                                                                                              f, t);
+  k_fft_xy_fwd<T><<<2 * f.nz * f.nruns, kPlaneThreads, plane_lds_bytes(f, sizeof(cplx<T>)), st>>>(src, parity,
+                                                                                                  spec, f, t);
 }
 
 template <typename T>
@@ -626,7 +678,7 @@ void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftT
                        hipStream_t st) {
   size_t lds = plane_lds_bytes(f, sizeof(cplx<T>));
   if (fin.n > 0) lds = std::max(lds, sizeof(double) * kFinLds);
-  k_fft_xy_inv<T><<<f.nz * f.nruns + fin.n, kPlaneThreads, lds, st>>>(spec, phi, f, t, fin);
+  k_fft_xy_inv<T><<<2 * f.nz * f.nruns + fin.n, kPlaneThreads, lds, st>>>(spec, phi, f, t, fin);
 }
 
 static size_t x_lds_bytes(const FftGeom& f, size_t csz, bool inv) {
@@ -662,25 +714,30 @@ void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool i
   const size_t stride = f.px, outer = (size_t)f.px * f.ny, run = outer * f.nz;
   if (inverse)
     k_fft_col<T, 1><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr,
-                                                    RedJob{});
+                                                    RedJob{}, 0, 0);
   else
     k_fft_col<T, 0><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr,
-                                                    RedJob{});
+                                                    RedJob{}, 0, 0);
 }
 
 template <typename T>
 void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, double* epot_partials,
                         bool ky_major, const RedJob& red, hipStream_t st) {
   const int cb = f.cols_z;
-  const int nblk = fft_blocks_z(f) + red.n;
-  size_t lds = sizeof(cplx<T>) * ((size_t)cb * f.az.L + f.az.L) + sizeof(double) * (f.az.L + cb);
+  // after the plane passes (ky-major) each workgroup pairs rows ky, ky + ny/2
+  const int nr = ky_major ? 2 : 1;
+  const int lines = f.ny / nr;
+  const int nchunks = (f.px + cb - 1) / cb;
+  const int nblk = nchunks * lines * f.nruns + red.n;
+  const size_t cw = (size_t)nr * cb;
+  size_t lds = sizeof(cplx<T>) * (cw * f.az.L + f.az.L) + sizeof(double) * (f.az.L + cw);
   if (red.n > 0) lds = std::max(lds, sizeof(double) * kRedThreads);
   const size_t run = (size_t)f.px * f.ny * f.nz;
   // C[run][z][ky][kx] (line passes) or C[run][ky][z][kx] (plane passes)
   const size_t stride = ky_major ? (size_t)f.px : (size_t)f.px * f.ny;
   const size_t outer = ky_major ? (size_t)f.px * f.nz : (size_t)f.px;
-  k_fft_col<T, 2><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, cb, stride, outer, f.ny, run,
-                                                  epot_partials, red);
+  k_fft_col<T, 2><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, cb, stride, outer, lines, run,
+                                                  epot_partials, red, nr == 2, (size_t)lines * outer);
 }
 
 template void launch_fft_x_fwd<double>(const SrcSlot*, int, cplx<double>*, const FftGeom&,

@@ -45,6 +45,7 @@ struct FftTables {
   const cplx<T>* tw_x;    // exp(-2 pi i k / Mx), k < Mx = nx / 2
   const cplx<T>* wn_x;    // exp(-2 pi i k / nx), k <= nx / 2 (real-to-complex split)
   const cplx<T>* tw_y;    // exp(-2 pi i k / ny)
+  const cplx<T>* tw_yh;   // exp(-2 pi i k / (ny / 2)) (half-length y transforms of the plane passes)
   const cplx<T>* tw_z;    // exp(-2 pi i k / nz)
   const double* dx;       // D(k) = 1 - (2/3) sin^2(pi k / n) per axis
   const double* dy;
@@ -55,14 +56,17 @@ struct FftGeom {
   int nx, ny, nz, px;     // px = nx / 2 + 1 (half-spectrum row length)
   int nruns;              // runs of this size stored back to back
   FftAxis ax, ay, az;     // ax.L = nx / 2
-  int plane;              // 1: x and y transforms per z plane in LDS
-  int pp;                 // row pitch of a plane in LDS (complex values)
+  int plane;              // 1: x and y transforms per half z plane in LDS
+  FftAxis ayh;            // ayh.L = ny / 2 (plane passes)
+  int hp;                 // row pitch of a half plane in LDS (complex values, odd, >= nx/2 + 1)
   int rows_per_block;     // x passes
   int cols_y, cols_z;     // columns per block in the y / z passes
   double green_scale;     // -4 pi G h^2 / 6
   double norm;            // 2 / (nx ny nz)
 };
 
+// Potential-energy partials the z pass writes: one per (spectrum row, column
+// chunk), contiguous per run.
 int fft_blocks_z(const FftGeom& f);
 
 // LDS a workgroup of the plane passes may take (gfx950).
