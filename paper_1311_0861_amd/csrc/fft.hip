@@ -7,16 +7,18 @@
 // stored C[z][ky][kx] by the line passes and C[ky][z][kx] by the plane passes:
 //   xy forward : the source s = rho + n is formed in FP64 from the densities
 //                (its mean is the zero mode, which the symbol drops, so Phi
-//                solves the equation for s - <s>); real rows of length nx -> complex FFT
-//                of length nx/2 on packed (even, odd) pairs, the even/odd
-//                split to nx/2+1 bins, then the columns along y;
+//                solves the equation for s - <s>); real rows of length nx ->
+//                complex FFT of length nx/2 on packed (even, odd) pairs, the
+//                even/odd split to nx/2+1 bins, then the columns along y;
 //   z fused    : forward along z, multiply by the symbol (and the inverse
 //                normalisation), accumulate sum |s^|^2 G for the potential
 //                energy, inverse along z -- one read and one write of C;
 //   xy inverse : columns along y, then the complex-to-real rows.
-// Where a whole z plane of the spectrum fits in LDS, one workgroup per plane
-// does both of its transforms (three passes over C in all); otherwise the x
-// and y transforms are separate passes (five in all).
+// Where two workgroups holding half a z plane fit on a CU, the plane passes
+// split the y transform by row parity (see the plane passes below): one
+// workgroup per (plane, row parity) does both transforms, and the z pass
+// joins and splits the two halves (three passes over C in all); otherwise the
+// x and y transforms are separate passes (five in all).
 // Each workgroup stages whole lines in LDS and runs a Stockham autosort FFT
 // (radices 8, 4, 3, 2; output in natural order) with all butterflies of a stage
 // held in registers between two barriers, so the stages work in place.
