@@ -72,8 +72,9 @@ enum { GP_STAGE_EUL = 0, GP_STAGE_LAG = 1, GP_STAGE_POISSON = 2, GP_STAGE_FINALI
  * one kernel per component: the gas (rho, m, E, e) and the stars / dark
  * matter (n, q, Pi, W), which those stages never couple.  The Poisson solve
  * is three passes over the half spectrum: the x and y transforms (one kernel
- * per z plane where a plane fits in LDS, else an x and a y kernel, timed
- * together), the z transforms with the symbol (whose launch also reduces the
+ * over the even and odd rows of each z plane where two such half planes fit
+ * in a CU's LDS, else an x and a y kernel, timed together), the z transforms
+ * with the symbol (whose launch also reduces the
  * per-tile partial sums of the step), and the inverse x and y (whose launch
  * also finishes the step: CFL step, time advance, diagnostics record).
  * GP_K_FINALIZE times the finalize where it runs on its own: without
@@ -176,8 +177,9 @@ gp_status gp_set_launch(gp_sim *sim, int32_t kernel, int32_t blocks);
 gp_status gp_get_launch(gp_sim *sim, int32_t kernel, int32_t *blocks);
 
 /* Form of the x and y transforms of the Poisson solve: GP_FFT_AUTO (one
- * workgroup per z plane wherever a plane of the half spectrum fits in a
- * workgroup's LDS, else separate x and y passes) or GP_FFT_LINES (always the
+ * workgroup per z plane and row parity wherever two such half planes of the
+ * half spectrum fit in a CU's LDS, the z pass joining the two halves of the
+ * y transform; else separate x and y passes) or GP_FFT_LINES (always the
  * separate passes).  Both compute the same transform, equal to rounding. */
 enum { GP_FFT_AUTO = 0, GP_FFT_LINES = 1 };
 gp_status gp_set_fft_form(gp_sim *sim, int32_t form);

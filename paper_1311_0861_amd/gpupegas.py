@@ -26,7 +26,7 @@ FIELD_NAMES = [
 ]
 GP_PHI = 22
 KERNEL_NAMES = ["eul_gas", "eul_bme", "lag_gas", "lag_bme", "fft_xy_fwd", "fft_z_green", "fft_xy_inv", "finalize"]
-GP_FFT_AUTO, GP_FFT_LINES = 0, 1  # x and y transforms: per z plane where it fits, or separate passes
+GP_FFT_AUTO, GP_FFT_LINES = 0, 1  # x and y transforms: per half z plane where it fits, or separate passes
 CELL_KERNELS = ["eul_gas", "eul_bme", "lag_gas", "lag_bme"]  # persistent, launch size settable
 
 
