@@ -82,9 +82,14 @@ struct SizeClass {
   unsigned nep_run = 0;
 };
 
+// HIP events around each kernel (or pass) of a step.  A per-cell kernel is
+// launched `reps` times back to back between its two events (each launch
+// recomputes the same outputs from the same inputs), which spreads the
+// events' own launch and completion latency over the repeats.
 struct Timer {
   hipEvent_t ev[2 * GP_NKERNELS];
   double acc[GP_NKERNELS];
+  int reps = 1;
   bool on = false;
 };
 
@@ -206,12 +211,12 @@ FftTables<T> tables(const SizeClass& c) {
 void tmark(gp_batch* b, Timer* tm, int k, int side) {
   if (tm && tm->on) (void)hipEventRecord(tm->ev[2 * k + side], b->st);
 }
-void tdone(Timer* tm, int k) {
+void tdone(Timer* tm, int k, int reps = 1) {
   if (tm && tm->on) {
     (void)hipEventSynchronize(tm->ev[2 * k + 1]);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, tm->ev[2 * k], tm->ev[2 * k + 1]);
-    tm->acc[k] += ms;
+    tm->acc[k] += ms / reps;
   }
 }
 
@@ -379,10 +384,11 @@ template <typename T>
 void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
   auto cell = [&](int k) {
     if (allow_tune && b->tune && !b->tuned) tune_kernel<T>(b, k);
+    const int reps = (tm && tm->on) ? tm->reps : 1;
     tmark(b, tm, k, 0);
-    launch_cell_kernel<T>(b, k, b->blocks[k]);
+    for (int r = 0; r < reps; r++) launch_cell_kernel<T>(b, k, b->blocks[k]);
     tmark(b, tm, k, 1);
-    tdone(tm, k);
+    tdone(tm, k, reps);
   };
   switch (stage) {
     case GP_STAGE_EUL:
@@ -910,6 +916,7 @@ gp_status engine_time_kernels(gp_batch* b, int32_t nsteps, double* ms, int32_t m
   if (b->tune && !b->tuned) run_step_direct(b, nullptr, true);  // tune first
   Timer tm;
   tm.on = true;
+  tm.reps = 3;
   for (int k = 0; k < 2 * GP_NKERNELS; k++) HIP_TRY(b, hipEventCreate(&tm.ev[k]));
   for (int k = 0; k < GP_NKERNELS; k++) tm.acc[k] = 0.0;
   for (int t = 0; t < nsteps; t++) run_step_direct(b, &tm, false);
