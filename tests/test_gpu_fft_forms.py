@@ -1,8 +1,10 @@
 """The two forms of the x and y transforms of the FFT Poisson solve (Sec. 2.3)
-on the GPU: one workgroup per z plane (the default wherever a plane of the
-half spectrum fits in LDS) and separate x and y passes.  Both must give the
-oracle's potential, and each other's to rounding, on even and odd half-row
-lengths (nx / 2), radix-3 lengths, non-square planes and the 128^3 grid.
+on the GPU: one workgroup per z plane and row parity, the z pass joining the
+two halves of the y transform (the default wherever two such half planes fit
+on a CU), and separate x and y passes.  Both must give the oracle's potential,
+and each other's to rounding, on even and odd half-row lengths (nx / 2), even
+and odd half-column lengths (ny / 2 = 9 and 3), radix-3 lengths, non-square
+planes and the 128^3 grid.
 """
 import numpy as np
 import pytest
@@ -41,7 +43,7 @@ def _phi_and_step(gp, cfg, st, form):
 
 
 @pytest.mark.parametrize("shape,seed", [((16, 12, 8), 3), ((18, 12, 8), 5), ((96, 24, 12), 8), ((8, 36, 6), 2),
-                                        ((128, 16, 4), 7)])
+                                        ((128, 16, 4), 7), ((12, 18, 8), 11), ((16, 6, 4), 12)])
 def test_forms_match_oracle(gp, W, shape, seed):
     say("fft forms", shape)
     cfg, st = W.random_periodic(n=shape, seed=seed)
