@@ -653,9 +653,9 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     // (where two such workgroups fit on a CU; with one per CU the separate x
     // and y passes are faster, e.g. 256^3 FP32)
     f.plane = c.G != 0.0 && 2 * plane_lds_bytes(f, 2 * es) <= (size_t)lds_max;
-    // the z pass after the plane passes holds the columns of two ky rows; 4
-    // of each keeps its LDS and workgroup count those of 8 columns of one row
-    f.cols_z = f.plane ? even_cols(2 * f.az.L, 4) : even_cols(f.az.L, 8);
+    // the z pass after the plane passes holds the columns of two ky rows, 64
+    // bytes of each row per z (4 FP64 or 8 FP32 columns)
+    f.cols_z = f.plane ? even_cols(2 * f.az.L, 32 / (int)es) : even_cols(f.az.L, 8);
     if (f.plane && !planes_ready) {
       // one limit for every size class: the kernels are shared
       const hipError_t e =
