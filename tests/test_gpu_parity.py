@@ -182,6 +182,28 @@ def test_stages_equal_step(gp, W):
     b.close()
 
 
+def test_time_kernels_advances_like_step(gp, W):
+    """gp_time_kernels runs each per-cell kernel three times back to back
+    between its events; each launch recomputes the same outputs, so the state
+    and diagnostics after it equal those after the same steps of gp_step."""
+    say("time_kernels vs step")
+    cfg, st = W.random_periodic(n=(16, 12, 8), seed=13)
+    a, _ = make_pair(cfg, st)
+    b, _ = make_pair(cfg, st)
+    a.step(4)
+    a.sync()
+    b.step(1)  # the first step also picks the launch sizes
+    kt = b.time_kernels(3)
+    b.sync()
+    assert set(kt) == set(gp.KERNEL_NAMES) and all(v >= 0.0 for v in kt.values())
+    ga, gb = gpu_state(a), gpu_state(b)
+    for f in ga:
+        np.testing.assert_array_equal(ga[f], gb[f], err_msg=f)
+    assert a.diag() == b.diag()
+    a.close()
+    b.close()
+
+
 def test_resume_is_bitwise(gp, W):
     say("resume from get/set")
     cfg, st = W.gaussian_blob(16)
