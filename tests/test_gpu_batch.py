@@ -129,3 +129,32 @@ def test_same_size_runs_keep_their_potential_energy(gp, W):
             np.testing.assert_array_equal(got[f], ref[f], err_msg="run %d field %s" % (r, f))
         s.close()
     b.close()
+
+
+def test_batch_mixing_fft_forms(gp, W):
+    """A batch whose size classes take different forms of the Poisson solve: a
+    256 x 256 x 4 FP32 run (its half planes do not fit two to a CU, so it takes
+    the separate x and y passes) beside a 16 x 12 x 8 one (half planes), with
+    the reduction and finalize workgroups riding along in whichever passes come
+    first.  Each member equals the same run alone, bitwise."""
+    say("batch mixing FFT forms")
+    members = [W.random_periodic(n=(256, 256, 4), seed=31), W.random_periodic(n=(16, 12, 8), seed=32)]
+    for cfg, _ in members:
+        cfg["precision"] = "fp32"
+    b = gp.Batch([c for c, _ in members])
+    for r, (_, st) in enumerate(members):
+        b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
+    b.step(3)
+    b.sync()
+    for r, (cfg, st) in enumerate(members):
+        s = gp.Sim(cfg)
+        s.set_state({k: v.to("cuda") for k, v in st.items()})
+        s.step(3)
+        s.sync()
+        assert b.diag(r) == s.diag(), r
+        ref = gpu_state(s)
+        got = _batch_state(b, r)
+        for f in ref:
+            np.testing.assert_array_equal(got[f], ref[f], err_msg="run %d field %s" % (r, f))
+        s.close()
+    b.close()
