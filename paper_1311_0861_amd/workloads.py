@@ -240,17 +240,20 @@ def gas_shock_tube(test, n=256, axis=0, transverse=4, gamma=1.4, device="cpu", e
     return cfg, assemble(rho, v, p, one.clone(), [zero] * 3, Pi, gamma)
 
 
-def bme_shock_tube(n=256, axis=0, transverse=4, t_end=0.2, device="cpu", eta=1e-3):
+def bme_shock_tube(n=256, axis=0, transverse=4, t_end=0.2, device="cpu", eta=1e-3,
+                   left_state=(2.0, 2.0), right_state=(1.0, 1.0)):
     """Shock tube of Sec. 4.2 for the moment equations: left state n = 2,
     Pi = diag-like [2,1,1;1,1,1] (Pi_dd = 2, all other components 1), right
-    state n = 1, all Pi components 1, u = 0.  The normal axis plays x."""
+    state n = 1, all Pi components 1, u = 0.  The normal axis plays x.
+    left_state / right_state = (n, Pi_dd) on each side; every other stress
+    component is 1."""
     cfg = _tube_config(n, axis, transverse, 1.4, t_end, eta=eta)
     X = cell_centres(cfg, device)[axis]
     left = X <= 0.5
     one = torch.ones_like(X)
     zero = torch.zeros_like(X)
-    nb = torch.where(left, 2.0 * one, one)
-    pdd = torch.where(left, 2.0 * one, one)
+    nb = torch.where(left, left_state[0] * one, right_state[0] * one)
+    pdd = torch.where(left, left_state[1] * one, right_state[1] * one)
     Pi = [one.clone() for _ in range(6)]
     Pi[[0, 3, 5][axis]] = pdd
     # passive uniform gas
