@@ -124,40 +124,78 @@ typedef struct {
 
 typedef struct gp_sim gp_sim;
 
-/* Create a sim.  hip_stream: a hipStream_t to run on, or NULL for a stream
- * the sim creates and owns.  On success *out receives the handle, which the
- * caller releases with gp_destroy.  Returns GP_E_INVALID for a bad config,
- * GP_E_UNSUPPORTED for FFT lengths the kernels do not handle, GP_E_NOMEM. */
+/* Create a sim on the uniform grid of Sec. 2 (x_i = i h per axis; here cell
+ * centres lo + (i + 1/2) h) with the parameters gamma (gas EOS, Sec. 2) and G
+ * (Poisson equation, Sec. 2 and 2.3).  hip_stream: a hipStream_t to run on,
+ * or NULL for a stream the sim creates and owns.  On success *out receives
+ * the handle, which the caller releases with gp_destroy; on failure *out is
+ * NULL and nothing is allocated.  Returns GP_E_INVALID for a bad config
+ * (h not equal on all axes, n < 4, gamma <= 1, cfl <= 0, reserved != 0),
+ * GP_E_UNSUPPORTED for FFT lengths the kernels do not handle (with G != 0
+ * every n must be even and 2^a 3^b), GP_E_NOMEM, GP_E_HIP. */
 gp_status gp_create(const gp_config *cfg, void *hip_stream, gp_sim **out);
+/* Wait for the sim's stream, free its device memory (and its stream if it
+ * created it).  GP_E_INVALID for NULL. */
 gp_status gp_destroy(gp_sim *sim);
 
-/* Copy one state field in (set) or out (get).  dtype GP_FP64 or GP_FP32 is
- * the caller's element type; values convert to the sim's storage type.
- * Setting any field invalidates Phi and tau; they are recomputed from the
- * state by the next gp_step, gp_debug_stage or gp_get_field(GP_PHI). */
+/* Copy one state field in (set) or out (get): the conserved variables of the
+ * gas system (rho, rho v, rho E, rho eps; Sec. 2) and of the moment system
+ * (n, n u, Pi_ij, n E_ij; Sec. 2), ids GP_RHO .. GP_WZZ.  src / dst hold
+ * nx*ny*nz values of the caller's type dtype (GP_FP64 or GP_FP32), x fastest;
+ * values convert to the sim's storage type.  The library reads or writes the
+ * caller's buffer only during the call (device buffers: in stream order on
+ * the sim's stream) and never keeps the pointer.  Setting any field
+ * invalidates Phi and tau; they are recomputed from the state by the next
+ * gp_step, gp_debug_stage, gp_get_potential or gp_get_field(GP_PHI).
+ * gp_get_field also takes GP_PHI (as gp_get_potential).  GP_E_INVALID for a
+ * bad id, dtype or NULL pointer; GP_E_STATE for a set between the stages of
+ * gp_debug_stage; gp_get_field returns the latched device status as
+ * gp_sync does, after the copy. */
 gp_status gp_set_field(gp_sim *sim, int32_t field, const void *src, int32_t dtype,
                        int32_t on_device);
 gp_status gp_get_field(gp_sim *sim, int32_t field, void *dst, int32_t dtype,
                        int32_t on_device);
 
-/* Enqueue nsteps full steps (asynchronous).  Argument errors return at once;
- * device errors are latched for the next synchronising call. */
+/* Potential Phi of the current state (Sec. 2.3: Laplace(Phi) = 4 pi G
+ * (rho + n) on the 27-point stencil, solved by FFT on the periodic grid with
+ * the zero mode removed), nx*ny*nz values of type dtype into dst (host or
+ * device as on_device says).  Computed first if the state was set since the
+ * last step.  Returns the latched device status after the copy, as
+ * gp_get_field. */
+gp_status gp_get_potential(gp_sim *sim, void *dst, int32_t dtype, int32_t on_device);
+
+/* Enqueue nsteps full steps (asynchronous): each step is the Eulerian stage
+ * (Sec. 2.1 gas, Sec. 2.2 stars / dark matter), the Lagrangian FlIC stage
+ * (Sec. 2.1), the energy balance and correctness integrals (Sec. 2.4), the
+ * FFT Poisson solve (Sec. 2.3), and the CFL step (not in the paper: tau =
+ * C h / max signal speed) with the diagnostics record.  Argument errors
+ * (nsteps < 0: GP_E_INVALID; mid-way through gp_debug_stage: GP_E_STATE)
+ * return at once; device errors are latched for the next synchronising
+ * call. */
 gp_status gp_step(gp_sim *sim, int32_t nsteps);
 
 /* Wait for the sim's stream; returns the latched device error, if any. */
 gp_status gp_sync(gp_sim *sim);
 
-/* Copy the most recent min(max, available) diagnostics records, oldest first.
- * The device keeps the last 4096 records. */
+/* Copy the most recent min(max, available) diagnostics records (the
+ * conservation sums and the Sec. 2.4 correctness integrals kappa of each
+ * step), oldest first, into out[0 .. *count - 1].  The device keeps the last
+ * 4096 records.  Synchronises, and returns the latched device status as
+ * gp_sync does: the records are delivered either way, and each record's err
+ * bits say from which step on an error was latched. */
 gp_status gp_get_diag(gp_sim *sim, gp_diag *out, int32_t max, int32_t *count);
 
-/* Set (t, step) of the current state, e.g. when resuming from saved fields. */
+/* Set (t, step) of the current state, e.g. when resuming from saved fields;
+ * tau is recomputed from the state.  gp_get_time returns the time, the step
+ * the next update will use and the step count (NULL outputs are skipped). */
 gp_status gp_set_time(gp_sim *sim, double t, int64_t step);
 gp_status gp_get_time(gp_sim *sim, double *t, double *dt, int64_t *step);
 
-/* Run one stage of a step (GP_STAGE_*), in order, for per-stage checks.
- * Between GP_STAGE_EUL and GP_STAGE_LAG, gp_get_field returns the
- * post-Eulerian fields.  GP_E_STATE if called out of order. */
+/* Run one stage of a step (GP_STAGE_*: Eulerian, Sec. 2.1 and 2.2;
+ * Lagrangian with the Sec. 2.4 balance; Poisson, Sec. 2.3; finalize: CFL step
+ * and diagnostics), in order, for per-stage checks.  Between GP_STAGE_EUL and
+ * GP_STAGE_LAG, gp_get_field returns the post-Eulerian fields.  GP_E_STATE if
+ * called out of order. */
 gp_status gp_debug_stage(gp_sim *sim, int32_t stage);
 
 /* Run nsteps steps kernel by kernel with HIP events around every launch and
@@ -197,7 +235,9 @@ const char *gp_last_error(const gp_sim *sim);
  * graph replay.  Every run keeps its own tau, time, diagnostics and error bits,
  * and evolves exactly as it would in its own gp_sim.  Fields, diagnostics and
  * errors are addressed by run index 0..nruns-1; other conventions are those of
- * the single-run calls above. */
+ * the single-run calls above.  gp_batch_sync returns an error latched by any
+ * run; gp_batch_get_field, gp_batch_get_potential and gp_batch_get_diag
+ * return the one latched by that run. */
 typedef struct gp_batch gp_batch;
 
 gp_status gp_batch_create(const gp_config *cfgs, int32_t nruns, void *hip_stream, gp_batch **out);
@@ -206,6 +246,7 @@ gp_status gp_batch_set_field(gp_batch *b, int32_t run, int32_t field, const void
                              int32_t on_device);
 gp_status gp_batch_get_field(gp_batch *b, int32_t run, int32_t field, void *dst, int32_t dtype,
                              int32_t on_device);
+gp_status gp_batch_get_potential(gp_batch *b, int32_t run, void *dst, int32_t dtype, int32_t on_device);
 gp_status gp_batch_step(gp_batch *b, int32_t nsteps);
 gp_status gp_batch_sync(gp_batch *b);
 gp_status gp_batch_get_diag(gp_batch *b, int32_t run, gp_diag *out, int32_t max, int32_t *count);

@@ -126,13 +126,15 @@ __device__ __forceinline__ WorkItem load_item(const WorkItem* work, unsigned w) 
 // work items (a block of tiles that share halos, in the order the host lists
 // them); its workgroups stride through that range together, so tiles sharing
 // halos run on the same XCD close in time.  Which workgroup takes a tile never
-// changes a result.
+// changes a result.  A grid of fewer than kNumXcd workgroups leaves some XCDs
+// without a workgroup, so it walks the whole list with a plain grid stride.
 constexpr unsigned kNumXcd = 8;
 struct WorkRange {
   unsigned first, end, stride;
 };
 __device__ __forceinline__ WorkRange xcd_range(unsigned nwork) {
   const unsigned G = gridDim.x, b = blockIdx.x;
+  if (G < kNumXcd) return WorkRange{b, nwork, G};
   const unsigned x = b % kNumXcd, slot = b / kNumXcd;
   const unsigned nb_x = (G - x + kNumXcd - 1) / kNumXcd;  // workgroups on XCD x
   const unsigned q = nwork / kNumXcd, rem = nwork % kNumXcd;

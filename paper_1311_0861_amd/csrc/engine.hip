@@ -480,11 +480,13 @@ void drop_graphs(gp_batch* b) {
   }
 }
 
-gp_status latched(gp_batch* b) {
+// Latched device error of run `only` (or of any run, only < 0) as a status.
+gp_status latched(gp_batch* b, int only = -1) {
   uint32_t err = 0;
-  for (const RunHost& r : b->runs) {
+  for (int r = 0; r < (int)b->runs.size(); r++) {
+    if (only >= 0 && r != only) continue;
     DevScalars h{};
-    HIP_TRY(b, hipMemcpy(&h, r.sc, sizeof(h), hipMemcpyDeviceToHost));
+    HIP_TRY(b, hipMemcpy(&h, b->runs[r].sc, sizeof(h), hipMemcpyDeviceToHost));
     err |= h.err;
   }
   if (err & ERR_NONFINITE) {
@@ -871,7 +873,7 @@ gp_status engine_get_field(gp_batch* b, int r, int32_t field, void* dst, int32_t
   }
   HIP_TRY(b, hipStreamSynchronize(b->st));
   HIP_TRY(b, hipGetLastError());
-  return latched(b);
+  return latched(b, r);
 }
 
 gp_status engine_step(gp_batch* b, int32_t nsteps) {
@@ -906,20 +908,24 @@ gp_status engine_get_diag(gp_batch* b, int r, gp_diag* out, int32_t max, int32_t
   HIP_TRY(b, hipMemcpy(all.data(), b->runs[r].ring, sizeof(gp_diag) * kDiagCap, hipMemcpyDeviceToHost));
   for (int t = 0; t < n; t++) out[t] = all[(h.ndiag - n + t) % kDiagCap];
   *count = n;
-  return GP_OK;
+  // the records are delivered either way; the status reports what the device
+  // latched for this run (each record's err field says from which step on)
+  return latched(b, r);
 }
 
 gp_status engine_time_kernels(gp_batch* b, int32_t nsteps, double* ms, int32_t max) {
   if (!ms || nsteps <= 0 || max < 0) return GP_E_INVALID;
   if (b->next_stage != GP_STAGE_EUL) return GP_E_STATE;
   if (b->need_prologue) run_prologue(b);
-  if (b->tune && !b->tuned) run_step_direct(b, nullptr, true);  // tune first
   Timer tm;
   tm.on = true;
   tm.reps = 3;
   for (int k = 0; k < 2 * GP_NKERNELS; k++) HIP_TRY(b, hipEventCreate(&tm.ev[k]));
   for (int k = 0; k < GP_NKERNELS; k++) tm.acc[k] = 0.0;
-  for (int t = 0; t < nsteps; t++) run_step_direct(b, &tm, false);
+  // An untuned sim picks its launch sizes during the first timed step: the
+  // candidates run before that kernel's first event, so the step is timed
+  // with the picked sizes and the state advances by exactly nsteps.
+  for (int t = 0; t < nsteps; t++) run_step_direct(b, &tm, true);
   for (int k = 0; k < 2 * GP_NKERNELS; k++) (void)hipEventDestroy(tm.ev[k]);
   for (int k = 0; k < std::min<int>(max, GP_NKERNELS); k++) ms[k] = tm.acc[k] / nsteps;
   HIP_TRY(b, hipGetLastError());
@@ -1048,6 +1054,11 @@ gp_status gp_step(gp_sim* s, int32_t nsteps) {
   return engine_step(s, nsteps);
 }
 
+gp_status gp_get_potential(gp_sim* s, void* dst, int32_t dtype, int32_t on_device) {
+  if (!s) return GP_E_INVALID;
+  return engine_get_field(s, 0, GP_PHI, dst, dtype, on_device);
+}
+
 gp_status gp_sync(gp_sim* s) {
   if (!s) return GP_E_INVALID;
   HIP_TRY(s, hipStreamSynchronize(s->st));
@@ -1158,6 +1169,11 @@ gp_status gp_batch_get_field(gp_batch* b, int32_t run, int32_t field, void* dst,
                              int32_t on_device) {
   if (!b) return GP_E_INVALID;
   return engine_get_field(b, run, field, dst, dtype, on_device);
+}
+
+gp_status gp_batch_get_potential(gp_batch* b, int32_t run, void* dst, int32_t dtype, int32_t on_device) {
+  if (!b) return GP_E_INVALID;
+  return engine_get_field(b, run, GP_PHI, dst, dtype, on_device);
 }
 
 gp_status gp_batch_step(gp_batch* b, int32_t nsteps) {

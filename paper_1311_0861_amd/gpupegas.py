@@ -85,6 +85,7 @@ def _load():
         "gp_destroy": ([vp], i32),
         "gp_set_field": ([vp, i32, vp, i32, i32], i32),
         "gp_get_field": ([vp, i32, vp, i32, i32], i32),
+        "gp_get_potential": ([vp, vp, i32, i32], i32),
         "gp_step": ([vp, i32], i32),
         "gp_sync": ([vp], i32),
         "gp_get_diag": ([vp, ctypes.POINTER(gp_diag), i32, ctypes.POINTER(i32)], i32),
@@ -103,6 +104,7 @@ def _load():
         "gp_batch_destroy": ([vp], i32),
         "gp_batch_set_field": ([vp, i32, i32, vp, i32, i32], i32),
         "gp_batch_get_field": ([vp, i32, i32, vp, i32, i32], i32),
+        "gp_batch_get_potential": ([vp, i32, vp, i32, i32], i32),
         "gp_batch_step": ([vp, i32], i32),
         "gp_batch_sync": ([vp], i32),
         "gp_batch_get_diag": ([vp, i32, ctypes.POINTER(gp_diag), i32, ctypes.POINTER(i32)], i32),
@@ -189,6 +191,12 @@ def gp_set_field(sim, field, src):
 def gp_get_field(sim, field, dst):
     p, code, dev = _buffer(dst)
     _check(sim, lib.gp_get_field(sim, int(field), p, code, dev))
+    return dst
+
+
+def gp_get_potential(sim, dst):
+    p, code, dev = _buffer(dst)
+    _check(sim, lib.gp_get_potential(sim, p, code, dev))
     return dst
 
 
@@ -280,6 +288,12 @@ def gp_batch_get_field(b, run, field, dst):
     return dst
 
 
+def gp_batch_get_potential(b, run, dst):
+    p, code, dev = _buffer(dst)
+    _check(b, lib.gp_batch_get_potential(b, int(run), p, code, dev), True)
+    return dst
+
+
 def gp_batch_step(b, nsteps=1):
     _check(b, lib.gp_batch_step(b, int(nsteps)), True)
 
@@ -365,6 +379,12 @@ class Sim:
     def get_state(self, device="cuda", dtype=None):
         return {k: self.get_field(k, device=device, dtype=dtype) for k in FIELD_NAMES}
 
+    def get_potential(self, out=None, device="cuda", dtype=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=dtype or torch.float64, device=device)
+        return gp_get_potential(self._h, out)
+
     def step(self, n=1):
         gp_step(self._h, n)
 
@@ -446,6 +466,12 @@ class Batch:
 
     def get_state(self, run, device="cuda", dtype=None):
         return {k: self.get_field(run, k, device=device, dtype=dtype) for k in FIELD_NAMES}
+
+    def get_potential(self, run, out=None, device="cuda", dtype=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shapes[run], dtype=dtype or torch.float64, device=device)
+        return gp_batch_get_potential(self._h, run, out)
 
     def step(self, n=1):
         gp_batch_step(self._h, n)

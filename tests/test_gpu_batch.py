@@ -62,22 +62,29 @@ def test_batch_members_equal_standalone_runs(gp, W, prec):
 
 
 def test_batch_result_independent_of_launch_size(gp, W):
+    """Persistent grids of 1, 3 and 7 workgroups (fewer than the 8 XCDs, so
+    some XCDs get no workgroup), 8, 13 and 24, and one workgroup per item,
+    all give the same bits."""
     say("launch size independence")
     members = _members(W)
     runs = []
-    for blocks in (0, 8, 24):
+    sizes = (0, 1, 3, 7, 8, 13, 24)
+    for blocks in sizes:
         b = gp.Batch([c for c, _ in members])
         for r, (_, st) in enumerate(members):
             b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
         for k in gp.CELL_KERNELS:
             b.set_launch(k, blocks)
+        for k in gp.CELL_KERNELS:
+            assert b.get_launch(k) == blocks or blocks == 0
         b.step(5)
         runs.append([_batch_state(b, r) for r in range(len(members))])
         b.close()
-    for r in range(len(members)):
-        for f in runs[0][r]:
-            np.testing.assert_array_equal(runs[1][r][f], runs[0][r][f])
-            np.testing.assert_array_equal(runs[2][r][f], runs[0][r][f])
+    for q in range(1, len(sizes)):
+        for r in range(len(members)):
+            for f in runs[0][r]:
+                np.testing.assert_array_equal(runs[q][r][f], runs[0][r][f],
+                                              err_msg="blocks %d run %d field %s" % (sizes[q], r, f))
 
 
 def test_ensemble_members_radix3(gp, W):

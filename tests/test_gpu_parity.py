@@ -270,3 +270,48 @@ def test_fp32_input_conversion(gp, W):
     sim.set_state({k: v.to("cuda", torch.float32) for k, v in st.items()})
     got = sim.get_field("rho").cpu().numpy()
     np.testing.assert_array_equal(got, st["rho"].float().double().numpy())
+
+
+def test_potential_reader_and_latched_diag_status(gp, W):
+    """gp_get_potential returns the Sec. 2.3 potential (equal to the oracle's
+    and bitwise to gp_get_field(GP_PHI)); gp_get_diag delivers its records and
+    reports an error the device latched (a NaN planted in the state), per run
+    in a batch."""
+    import ctypes
+    import torch
+    say("potential reader, latched diag status")
+    cfg, st = W.random_periodic(n=(16, 12, 8), seed=17)
+    sim, orc = make_pair(cfg, st)
+    sim.step(2)
+    orc.step(2)
+    phi = sim.get_potential().cpu().numpy()
+    np.testing.assert_array_equal(phi, sim.get_field("phi").cpu().numpy())
+    ref = orc.get_field("phi")
+    assert np.abs(phi - ref).sum() / np.abs(ref).sum() < 1e-12
+    host = np.empty(sim.shape, dtype=np.float32)
+    gp.gp_get_potential(sim._h, host)  # host FP32 destination
+    np.testing.assert_allclose(host, phi, rtol=1e-6, atol=1e-7 * np.abs(phi).max())
+
+    bad = dict(st)
+    bad["e"] = st["e"].clone()
+    bad["e"][3, 5, 7] = float("nan")
+    b = gp.Batch([cfg, cfg])
+    b.set_state(0, {k: v.to("cuda") for k, v in st.items()})
+    b.set_state(1, {k: v.to("cuda") for k, v in bad.items()})
+    b.step(2)
+    buf = (gp.gp_diag * 8)()
+    cnt = ctypes.c_int32()
+    assert gp.lib.gp_batch_get_diag(b._h, 0, buf, 8, ctypes.byref(cnt)) == gp.GP_OK
+    assert cnt.value == 3 and buf[2].err == 0
+    assert gp.lib.gp_batch_get_diag(b._h, 1, buf, 8, ctypes.byref(cnt)) == gp.GP_E_NONFINITE
+    assert cnt.value == 3 and buf[2].step == 2 and (buf[2].err & 1)
+    assert gp.lib.gp_batch_sync(b._h) == gp.GP_E_NONFINITE
+    got = b.get_potential(0).cpu().numpy()
+    np.testing.assert_array_equal(got, phi)
+    b.close()
+    sim1, _ = make_pair(cfg, bad)
+    sim1.step(1)
+    assert gp.lib.gp_get_diag(sim1._h, buf, 8, ctypes.byref(cnt)) == gp.GP_E_NONFINITE
+    assert cnt.value == 2 and (buf[1].err & 1)
+    out = torch.empty(sim1.shape, dtype=torch.float64, device="cuda")
+    assert gp.lib.gp_get_potential(sim1._h, ctypes.c_void_p(out.data_ptr()), gp.GP_FP64, 1) == gp.GP_E_NONFINITE
