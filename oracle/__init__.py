@@ -5,5 +5,5 @@ Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
 """
 from .oracle import (  # noqa: F401
     Oracle, OracleConfig, build, lib_path, riemann_gas, riemann_bme, dft3,
-    poisson, DIAG_FIELDS, FIELD_NAMES, set_threads, get_threads,
+    poisson, poisson_isolated, DIAG_FIELDS, FIELD_NAMES, set_threads, get_threads,
 )

@@ -14,6 +14,9 @@
  *   Lagrangian (FlIC) stage flux .............. Sec. 2.1 (flux F_{i+1/2,kl}, Fig. "lagrange")
  *   Eulerian stage, BME face state ............ Sec. 2.2 (closed-form solution)
  *   Poisson by FFT, 27-point symbol ........... Sec. 2.3
+ *   isolated Poisson boundaries ............... zero-padded convolution with
+ *       the sampled point-mass potential (Hockney and Eastwood, whose method
+ *       Sec. 1 cites among the Poisson solvers of other codes)
  *   correctness integrals kappa ............... Sec. 2.4
  *
  * Where the paper is silent the oracle takes these readings (each is also
@@ -32,7 +35,9 @@
  *   - energy balance: dual-energy synchronisation with threshold eta, applied
  *     after kappa is measured; CFL step C h / max signal speed.
  *   - hydrodynamic boundaries: outflow = clamped (zero-gradient) index,
- *     periodic = wrapped index.  Phi always wraps.
+ *     periodic = wrapped index.  A periodic Phi wraps; an isolated Phi is
+ *     evaluated on a one-cell ring outside the grid as well, and the gravity
+ *     of the outermost cells takes its values there.
  *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC
  */
@@ -75,6 +80,7 @@ typedef struct {
   double eta;         /* energy-balance threshold (negative disables)        */
   double fixed_dt;    /* > 0: use this step instead of the CFL step          */
   double t_end;       /* > 0: never step past this time                      */
+  int32_t poisson;    /* 0 = periodic (Sec. 2.3), 1 = isolated               */
 } orc_config;
 
 typedef struct {
@@ -87,6 +93,8 @@ typedef struct {
   double *vel[6];      /* cell velocities v'(3), u'(3) for the FlIC stage    */
   double *vtx[6];      /* corner velocities, (nx+1)(ny+1)(nz+1) each         */
   double *phi, *s;
+  double *phi_ext;     /* isolated: Phi on the grid and a one-cell ring       */
+  double *ghat;        /* isolated: spectrum of the padded Green function      */
   double t, dt;
   int64_t step;
   int need_prologue;
@@ -121,6 +129,14 @@ static size_t nbr(const orc_sim *s, int i, int j, int k, int d, int o) {
   const int n[3] = {s->nx, s->ny, s->nz};
   c[d] = bcix(c[d] + o, n[d], s->c.bc[d]);
   return cidx(s, c[0], c[1], c[2]);
+}
+
+/* cell (i, j, k) + o e_d of the isolated potential's extended grid, which
+ * holds the cells -1 .. n on each axis */
+static size_t ext_nbr(const orc_sim *s, int i, int j, int k, int d, int o) {
+  int c[3] = {i + 1, j + 1, k + 1};
+  c[d] += o;
+  return (size_t)c[0] + (size_t)(s->nx + 2) * ((size_t)c[1] + (size_t)(s->ny + 2) * (size_t)c[2]);
 }
 
 static size_t nbr_wrap(const orc_sim *s, int i, int j, int k, int d, int o) {
@@ -224,8 +240,9 @@ static void stage_eulerian(orc_sim *s) {
         const size_t c = cidx(s, i, j, k);
         double grad[3];
         for (int d = 0; d < 3; d++)
-          grad[d] = (s->phi[nbr_wrap(s, i, j, k, d, +1)] -
-                     s->phi[nbr_wrap(s, i, j, k, d, -1)]) / (2.0 * h);
+          grad[d] = s->c.poisson == 1
+                        ? (s->phi_ext[ext_nbr(s, i, j, k, d, +1)] - s->phi_ext[ext_nbr(s, i, j, k, d, -1)]) / (2.0 * h)
+                        : (s->phi[nbr_wrap(s, i, j, k, d, +1)] - s->phi[nbr_wrap(s, i, j, k, d, -1)]) / (2.0 * h);
 
         /* gas */
         double dP[3], dPV = 0.0, dV = 0.0;
@@ -555,8 +572,109 @@ int orc_poisson(int nx, int ny, int nz, double h, double G, const double *src,
   return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Isolated boundaries: Phi(x_i) = sum_j g(x_i - x_j) s_j, the free-space
+ * potential of the cell masses, with the sampled point-mass potential
+ *   g(d) = -G h^3 / (h |d|)  for a displacement of d != 0 cells,
+ *   g(0) = -G h^2 c0,  c0 = 6 ln((1 + sqrt 3) / sqrt 2) - pi / 2,
+ * c0 h^2 being the integral of 1/|x| over a cube of side h about its centre
+ * (reading: a cell's own mass is spread uniformly over the cell).  Following
+ * Hockney and Eastwood, the source is zero-padded to (2nx, 2ny, 2nz) and g is
+ * sampled on that lattice at the minimum-image displacement (|d_a| <= n_a on
+ * each axis); the cyclic convolution of the two then equals the free-space
+ * sum at every output whose displacement to every source is at most n_a on
+ * each axis, which covers the grid and its one-cell ring (cells -1 .. n).
+ * Phi_ext holds those (nx+2)(ny+2)(nz+2) values, cell i at index i + 1. */
+static double cube_centre_integral(void) {
+  return 6.0 * log((1.0 + sqrt(3.0)) / sqrt(2.0)) - M_PI / 2.0;
+}
+
+/* the DFT of the padded Green function, which is real (g is even) */
+static int iso_green_spectrum(int nx, int ny, int nz, double h, double G, double *ghat) {
+  const int P[3] = {2 * nx, 2 * ny, 2 * nz};
+  const size_t np = (size_t)P[0] * P[1] * P[2];
+  double *re = malloc(np * sizeof(double)), *im = calloc(np, sizeof(double));
+  const double c0 = cube_centre_integral();
+#pragma omp parallel for schedule(static)
+  for (int mz = 0; mz < P[2]; mz++)
+    for (int my = 0; my < P[1]; my++)
+      for (int mx = 0; mx < P[0]; mx++) {
+        const double dx = mx <= nx ? mx : mx - P[0];
+        const double dy = my <= ny ? my : my - P[1];
+        const double dz = mz <= nz ? mz : mz - P[2];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        re[(size_t)mx + (size_t)P[0] * ((size_t)my + (size_t)P[1] * mz)] =
+            r == 0.0 ? -G * h * h * c0 : -G * h * h / r;
+      }
+  const int rc = orc_dft3(P[0], P[1], P[2], re, im, -1);
+  if (rc == 0) memcpy(ghat, re, np * sizeof(double));
+  free(re);
+  free(im);
+  return rc;
+}
+
+static int iso_convolve(int nx, int ny, int nz, const double *ghat, const double *src, double *phi_ext) {
+  const int P[3] = {2 * nx, 2 * ny, 2 * nz};
+  const size_t np = (size_t)P[0] * P[1] * P[2];
+  double *re = calloc(np, sizeof(double)), *im = calloc(np, sizeof(double));
+  for (int k = 0; k < nz; k++)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++)
+        re[(size_t)i + (size_t)P[0] * ((size_t)j + (size_t)P[1] * k)] =
+            src[(size_t)i + (size_t)nx * ((size_t)j + (size_t)ny * k)];
+  int rc = orc_dft3(P[0], P[1], P[2], re, im, -1);
+  if (rc == 0) {
+    for (size_t c = 0; c < np; c++) {
+      re[c] *= ghat[c];
+      im[c] *= ghat[c];
+    }
+    orc_dft3(P[0], P[1], P[2], re, im, +1);
+    for (int k = -1; k <= nz; k++)
+      for (int j = -1; j <= ny; j++)
+        for (int i = -1; i <= nx; i++) {
+          const size_t q = (size_t)wrap(i, P[0]) + (size_t)P[0] * ((size_t)wrap(j, P[1]) + (size_t)P[1] * wrap(k, P[2]));
+          phi_ext[(size_t)(i + 1) + (size_t)(nx + 2) * ((size_t)(j + 1) + (size_t)(ny + 2) * (k + 1))] =
+              re[q] / (double)np;
+        }
+  }
+  free(re);
+  free(im);
+  return rc;
+}
+
+/* Isolated potential of src on the grid and its one-cell ring, phi_ext of
+ * (nx+2)(ny+2)(nz+2) values.  Returns 0, or -1 for an unsupported length. */
+int orc_poisson_isolated(int nx, int ny, int nz, double h, double G, const double *src, double *phi_ext) {
+  const size_t ne = (size_t)(nx + 2) * (ny + 2) * (nz + 2);
+  if (G == 0.0) {
+    memset(phi_ext, 0, ne * sizeof(double));
+    return 0;
+  }
+  double *ghat = malloc((size_t)8 * nx * ny * nz * sizeof(double));
+  int rc = iso_green_spectrum(nx, ny, nz, h, G, ghat);
+  if (rc == 0) rc = iso_convolve(nx, ny, nz, ghat, src, phi_ext);
+  free(ghat);
+  return rc;
+}
+
 static void stage_poisson(orc_sim *s) {
-  orc_poisson(s->nx, s->ny, s->nz, s->h, s->c.G, s->s, s->phi);
+  if (s->c.poisson != 1) {
+    orc_poisson(s->nx, s->ny, s->nz, s->h, s->c.G, s->s, s->phi);
+    return;
+  }
+  const int nx = s->nx, ny = s->ny, nz = s->nz;
+  if (s->c.G == 0.0) {
+    memset(s->phi_ext, 0, (size_t)(nx + 2) * (ny + 2) * (nz + 2) * sizeof(double));
+  } else {
+    if (!s->ghat) {
+      s->ghat = malloc((size_t)8 * s->ncell * sizeof(double));
+      iso_green_spectrum(nx, ny, nz, s->h, s->c.G, s->ghat);
+    }
+    iso_convolve(nx, ny, nz, s->ghat, s->s, s->phi_ext);
+  }
+  for (int k = 0; k < nz; k++)
+    for (int j = 0; j < ny; j++)
+      for (int i = 0; i < nx; i++) s->phi[cidx(s, i, j, k)] = s->phi_ext[ext_nbr(s, i, j, k, 0, 0)];
 }
 
 /* ------------------------------------------------------------------------- */
@@ -710,6 +828,7 @@ orc_sim *orc_create(const orc_config *cfg) {
   if (cfg->G != 0.0)
     for (int d = 0; d < 3; d++)
       if (!fft_len_ok(cfg->n[d])) return NULL;
+  if (cfg->poisson != 0 && cfg->poisson != 1) return NULL;
   orc_sim *s = calloc(1, sizeof(orc_sim));
   s->c = *cfg;
   s->nx = cfg->n[0];
@@ -728,6 +847,7 @@ orc_sim *orc_create(const orc_config *cfg) {
   }
   s->phi = calloc(s->ncell, sizeof(double));
   s->s = calloc(s->ncell, sizeof(double));
+  if (cfg->poisson == 1) s->phi_ext = calloc((size_t)(s->nx + 2) * (s->ny + 2) * (s->nz + 2), sizeof(double));
   s->need_prologue = 1;
   s->next_stage = ST_EUL;
   return s;
@@ -745,6 +865,8 @@ void orc_destroy(orc_sim *s) {
   }
   free(s->phi);
   free(s->s);
+  free(s->phi_ext);
+  free(s->ghat);
   free(s->diag);
   free(s);
 }
@@ -765,6 +887,14 @@ int orc_get_field(orc_sim *s, int id, double *dst) {
   }
   if (id < 0 || id >= NF) return -1;
   memcpy(dst, s->f[id], s->ncell * sizeof(double));
+  return 0;
+}
+
+/* isolated potential on the grid and its one-cell ring ((nx+2)(ny+2)(nz+2)) */
+int orc_get_phi_ext(orc_sim *s, double *dst) {
+  if (s->c.poisson != 1) return -1;
+  if (s->need_prologue) prologue(s);
+  memcpy(dst, s->phi_ext, (size_t)(s->nx + 2) * (s->ny + 2) * (s->nz + 2) * sizeof(double));
   return 0;
 }
 

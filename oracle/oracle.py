@@ -57,6 +57,7 @@ class OracleConfig(ctypes.Structure):
         ("eta", ctypes.c_double),
         ("fixed_dt", ctypes.c_double),
         ("t_end", ctypes.c_double),
+        ("poisson", ctypes.c_int32),
     ]
 
 
@@ -87,6 +88,8 @@ def _load():
                                   ctypes.c_int, dp, dp]
     L.orc_dft3.argtypes = [ctypes.c_int] * 3 + [dp, dp, ctypes.c_int]
     L.orc_poisson.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double, dp, dp]
+    L.orc_poisson_isolated.argtypes = [ctypes.c_int] * 3 + [ctypes.c_double, ctypes.c_double, dp, dp]
+    L.orc_get_phi_ext.argtypes = [ctypes.c_void_p, dp]
     L.orc_diag_count.argtypes = [ctypes.c_void_p]
     L.orc_set_threads.argtypes = [ctypes.c_int]
     L.orc_get_threads.restype = ctypes.c_int
@@ -144,6 +147,18 @@ def poisson(s, h, G=1.0):
     return phi
 
 
+def poisson_isolated(s, h, G=1.0):
+    """Isolated potential of s (nz, ny, nx) on the grid and its one-cell
+    ring: shape (nz + 2, ny + 2, nx + 2), cell i at index i + 1."""
+    L = _load()
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    nz, ny, nx = s.shape
+    phi = np.zeros((nz + 2, ny + 2, nx + 2))
+    if L.orc_poisson_isolated(nx, ny, nz, float(h), float(G), _dp(s), _dp(phi)) != 0:
+        raise ValueError("length not of the form 2^a 3^b")
+    return phi
+
+
 class Oracle:
     """One oracle simulation.  ``cfg`` is a dict with keys n, lo, hi, gamma, G,
     cfl, eta, fixed_dt, t_end, bc (0 outflow, 1 periodic per axis)."""
@@ -162,6 +177,7 @@ class Oracle:
         c.eta = float(cfg.get("eta", 1e-3))
         c.fixed_dt = float(cfg.get("fixed_dt", 0.0))
         c.t_end = float(cfg.get("t_end", 0.0))
+        c.poisson = {"periodic": 0, "isolated": 1}[cfg.get("poisson", "periodic")]
         self._cfg = c
         self._h = L.orc_create(ctypes.byref(c))
         if not self._h:
@@ -201,6 +217,13 @@ class Oracle:
 
     def get_state(self):
         return {k: self.get_field(k) for k in FIELD_NAMES}
+
+    def get_phi_ext(self):
+        """Isolated potential on the grid and its one-cell ring."""
+        out = np.empty(tuple(v + 2 for v in self.shape), dtype=np.float64)
+        if self._L.orc_get_phi_ext(self._h, _dp(out)) != 0:
+            raise ValueError("not an isolated-boundary run")
+        return out
 
     def set_time(self, t, step=0):
         self._L.orc_set_time(self._h, float(t), int(step))

@@ -30,15 +30,16 @@ DEFAULT_GAMMA = 5.0 / 3.0
 
 
 def base_config(n, lo=-1.0, hi=1.0, gamma=DEFAULT_GAMMA, G=1.0, cfl=0.2,
-                eta=1e-3, bc=(0, 0, 0), fixed_dt=0.0, t_end=0.0, precision="fp64"):
-    """Run configuration as a plain dict (both the library and the oracle read it)."""
+                eta=1e-3, bc=(0, 0, 0), fixed_dt=0.0, t_end=0.0, precision="fp64", poisson="periodic"):
+    """Run configuration as a plain dict (both the library and the oracle read
+    it).  poisson: "periodic" or "isolated" boundaries of the potential."""
     if isinstance(n, int):
         n = (n, n, n)
     lo = tuple(lo) if isinstance(lo, (tuple, list)) else (lo,) * 3
     hi = tuple(hi) if isinstance(hi, (tuple, list)) else (hi,) * 3
     return dict(n=tuple(int(v) for v in n), lo=lo, hi=hi, gamma=gamma, G=G,
                 cfl=cfl, eta=eta, bc=tuple(bc), fixed_dt=fixed_dt, t_end=t_end,
-                precision=precision)
+                precision=precision, poisson=poisson)
 
 
 def cell_centres(cfg, device="cpu"):
