@@ -27,7 +27,8 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="cells per axis")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--profile-steps", type=int, default=20, help="steps timed kernel by kernel")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle sample")
+    ap.add_argument("--error-steps", type=int, default=100,
+                    help="steps of the oracle reference run (its all-thread timing is the CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32 (256^3, 512^3) and 48-run ensemble measurements")
@@ -52,6 +53,22 @@ def rel_l1_max(got, ref):
         den = sum(float(np.abs(ref[f]).sum()) for f in g)
         for f in g:
             e = float(np.abs(got[f] - ref[f]).sum()) / den
+            if e > worst:
+                worst, where = e, f
+    return worst, where
+
+
+def rel_elem_max(got, ref):
+    """Largest element-wise error of any field, over the largest |value| of
+    its group (grouped as rel_l1_max)."""
+    import numpy as np
+    groups = [["rho"], ["mx", "my", "mz"], ["E"], ["e"], ["n"], ["qx", "qy", "qz"],
+              ["Pxx", "Pxy", "Pxz", "Pyy", "Pyz", "Pzz"], ["Wxx", "Wxy", "Wxz", "Wyy", "Wyz", "Wzz"]]
+    worst, where = 0.0, None
+    for g in groups:
+        den = max(float(np.abs(ref[f]).max()) for f in g)
+        for f in g:
+            e = float(np.abs(got[f] - ref[f]).max()) / den
             if e > worst:
                 worst, where = e, f
     return worst, where
@@ -106,16 +123,77 @@ def recorded_traffic(kernel, n, precision, path=None):
     return None
 
 
-def cpu_model():
-    """Host CPU model name (for the stated CPU baseline)."""
+def cpu_info():
+    """Host CPU as lscpu states it (model name, logical CPUs, threads per
+    core, cores per socket, sockets), for the stated CPU baseline."""
+    import subprocess
+    keys = {"Model name": "model", "CPU(s)": "logical_cpus", "Thread(s) per core": "threads_per_core",
+            "Core(s) per socket": "cores_per_socket", "Socket(s)": "sockets"}
+    out = {}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        text = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in text.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys and keys[k.strip()] not in out:
+                out[keys[k.strip()]] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return None
+    if "model" not in out:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        out["model"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return out
+
+
+def oracle_baseline(cfg, st, ncell, err_steps):
+    """The oracle (plain C + OpenMP, FP64, untuned) on the host cores.
+
+    All threads: the `err_steps`-step reference run of the error figures,
+    timed in three equal segments; the rate is the median segment.  One
+    thread: three samples of one step each from the initial state; the rate
+    is their median.  Returns (baseline record, oracle after err_steps)."""
+    import statistics
+    import oracle
+    from paper_1311_0861_amd import workloads as W
+    oracle.build(force=False)
+    threads = oracle.get_threads()
+    orc = oracle.Oracle(cfg)
+    orc.set_state(W.to_numpy(st))
+    orc.dt()  # prologue (Phi^0, tau^0) outside the timed samples
+    seg = [err_steps // 3, err_steps // 3, err_steps - 2 * (err_steps // 3)]
+    rates = []
+    for k in seg:
+        c0 = time.perf_counter()
+        orc.step(k)
+        rates.append(ncell * k / (time.perf_counter() - c0) / 1e6)
+    oracle.set_threads(1)
+    one = oracle.Oracle(cfg)
+    one.set_state(W.to_numpy(st))
+    one.dt()
+    rates1 = []
+    for _ in range(3):
+        c0 = time.perf_counter()
+        one.step(1)
+        rates1.append(ncell / (time.perf_counter() - c0) / 1e6)
+    one.close()
+    oracle.set_threads(threads)
+    n = round(ncell ** (1.0 / 3.0))
+    base = {"value": round(statistics.median(rates), 4), "unit": "Mcell-updates/s", "cores": threads,
+            "kind": "oracle", "statistic": "median of 3",
+            "sample": "%d steps of the %d^3 two-disk workload from its initial state (FP64, plain C + OpenMP "
+                      "on %d threads), timed as three segments of %s steps" % (err_steps, n, threads, seg),
+            "segments": [round(r, 4) for r in rates],
+            "single_thread": {"value": round(statistics.median(rates1), 4), "unit": "Mcell-updates/s",
+                              "cores": 1, "statistic": "median of 3",
+                              "sample": "3 x 1 step of the same workload from its initial state",
+                              "samples": [round(r, 4) for r in rates1]},
+            "cpu": cpu_info()}
+    return base, orc
 
 
 def timed_steps(obj, steps, warmup):
@@ -284,35 +362,27 @@ def main():
     launch = {k: sim.get_launch(k) for k in gp.CELL_KERNELS}
     sim.close()
 
-    # ---- CPU oracle on a bounded sample of the same workload -----------------
+    # ---- CPU oracle: reference run of the error figures, and the baseline -----
     cpu = None
     error = None
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        orc = oracle.Oracle(cfg_cpu)
-        orc.set_state(W.to_numpy(st_cpu))
-        orc.dt()  # prologue outside the timed sample
-        steps, c0 = 0, time.perf_counter()
-        while True:
-            orc.step(1)
-            steps += 1
-            if time.perf_counter() - c0 >= args.cpu_seconds or steps >= 50:
-                break
-        csec = time.perf_counter() - c0
-        cpu = {"value": round(ncell * steps / csec / 1e6, 4), "unit": "Mcell-updates/s",
-               "cores": oracle.get_threads(), "kind": "oracle", "cpu_model": cpu_model(),
-               "sample": "%d steps of the same %d^3 two-disk workload from its initial state, FP64, "
-                         "plain C + OpenMP" % (steps, n)}
-        # the same steps on the GPU from the same inputs give the stated error
-        s2 = fresh_sim()
-        s2.step(steps)
-        s2.sync()
-        got = {k: v.cpu().numpy() for k, v in s2.get_state().items()}
-        s2.close()
-        worst, field = rel_l1_max(got, orc.get_state())
-        error = {"vs": "oracle", "metric": "max per-field relative L1", "value": worst, "field": field,
-                 "steps": steps}
+        cpu, orc = oracle_baseline(cfg_cpu, st_cpu, ncell, args.error_steps)
+        ref = orc.get_state()
+        error = {"vs": "oracle", "metric": "max per-field relative L1 (and element-wise max error over the "
+                                          "group's largest value)", "steps": args.error_steps}
+        # the same steps on the GPU from the same inputs, in both precisions
+        for prec in ("fp64", "fp32"):
+            s2 = gp.Sim(dict(cfg_cpu, precision=prec))
+            s2.set_state({k: v.to("cuda") for k, v in st_cpu.items()})
+            s2.step(args.error_steps)
+            s2.sync()
+            got = {k: v.cpu().numpy() for k, v in s2.get_state().items()}
+            s2.close()
+            worst, field = rel_l1_max(got, ref)
+            wmax, fmax = rel_elem_max(got, ref)
+            error[prec] = {"value": worst, "field": field, "elementwise": wmax, "elementwise_field": fmax}
+        error["value"] = error[args.precision]["value"]
+        error["field"] = error[args.precision]["field"]
 
     forms = None
     if not args.no_forms:

@@ -43,9 +43,56 @@ def make_pair(cfg, state):
     return sim, orc
 
 
-def assert_close_fields(got, ref, tol, what=""):
+def rel_max(got, ref):
+    """Per-field element-wise error: max |a - b| over the cells, divided by
+    the largest |b| of the field's group (as rel_l1 normalises by its sum).
+    Unlike the relative L1, an error confined to a few cells is not diluted
+    by the grid size."""
+    out = {}
+    for grp in GROUPS:
+        den = max(float(np.abs(ref[f]).max()) for f in grp)
+        for f in grp:
+            d = float(np.abs(got[f] - ref[f]).max())
+            out[f] = d / den if den > 0 else d
+    return out
+
+
+def boundary_slabs(cfg):
+    """Index tuples of the first and last two planes on every outflow axis of
+    a (nz, ny, nx) field, where the clamped-index boundary rule acts."""
+    out = []
+    for d in range(3):
+        if int(cfg.get("bc", (0, 0, 0))[d]) != 0:
+            continue
+        ax = 2 - d
+        for sl in (slice(0, 2), slice(-2, None)):
+            idx = [slice(None)] * 3
+            idx[ax] = sl
+            out.append(("xyz"[d], "lo" if sl.start == 0 else "hi", tuple(idx)))
+    return out
+
+
+def assert_close_fields(got, ref, tol, what="", cfg=None, max_tol=None):
+    """Every field within `tol` relative L1 of the reference, within `max_tol`
+    (default 10 tol) element-wise (rel_max), and, for each outflow axis of
+    cfg, within `tol` relative L1 on its first and last two planes alone."""
+    max_tol = 10.0 * tol if max_tol is None else max_tol
     err = rel_l1(got, ref)
     worst = max(err, key=err.get)
     assert err[worst] <= tol, "%s: worst field %s rel L1 %.3e > %.1e; all %s" % (
         what, worst, err[worst], tol, {k: "%.1e" % v for k, v in err.items()})
+    em = rel_max(got, ref)
+    wm = max(em, key=em.get)
+    assert em[wm] <= max_tol, "%s: worst field %s element-wise %.3e > %.1e; all %s" % (
+        what, wm, em[wm], max_tol, {k: "%.1e" % v for k, v in em.items()})
+    worst_slab = 0.0
+    if cfg is not None:
+        for axis, side, idx in boundary_slabs(cfg):
+            es = rel_l1({k: got[k][idx] for k in got}, {k: ref[k][idx] for k in ref})
+            ws = max(es, key=es.get)
+            worst_slab = max(worst_slab, es[ws])
+            assert es[ws] <= tol, "%s: %s-%s boundary planes, field %s rel L1 %.3e > %.1e" % (
+                what, axis, side, ws, es[ws], tol)
+    say("%s: rel L1 %.2e (%s), element-wise %.2e (%s), boundary planes %.2e" % (
+        what, err[worst], worst, em[wm], wm, worst_slab))
     return err

@@ -7,7 +7,7 @@ bitwise, whatever persistent grid sizes are used."""
 import numpy as np
 import pytest
 
-from gpu_helpers import gpu_state, say
+from gpu_helpers import assert_close_fields, gpu_state, say
 
 pytestmark = pytest.mark.gpu
 
@@ -110,6 +110,38 @@ def test_ensemble_members_radix3(gp, W):
         for f in ref:
             np.testing.assert_array_equal(got[f], ref[f], err_msg="member %d field %s" % (pick[r], f))
         s.close()
+
+
+def test_ensemble_members_against_oracle(gp, W):
+    """Three members of the 48-run ensemble (64^3, 96^3 with its radix-3 FFT,
+    128^3), FP32, advanced together as one batch in the benchmark's launch
+    configuration, each against the FP64 oracle after 4 steps: within 1e-5
+    relative L1 per field (FP32 rounding over a few steps), element-wise and
+    on the outflow planes too; potential and time as well."""
+    import oracle
+    say("ensemble members 64/96/128 FP32 batched vs the oracle, 4 steps")
+    sizes = W.ensemble_sizes(48)
+    pick = [sizes.index(n) for n in (64, 96, 128)]
+    members = [W.ensemble_member(r) for r in pick]
+    b = gp.Batch([c for c, _ in members])
+    for r, (_, st) in enumerate(members):
+        b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
+    b.step(4)
+    b.sync()
+    for r, (cfg, st) in enumerate(members):
+        orc = oracle.Oracle(cfg)
+        orc.set_state(W.to_numpy(st))
+        orc.step(4)
+        assert_close_fields(_batch_state(b, r), orc.get_state(), 1e-5, "member %d (%d^3)" % (pick[r], cfg["n"][0]),
+                            cfg)
+        phi = b.get_potential(r).cpu().numpy()
+        ref = orc.get_field("phi")
+        assert np.abs(phi - ref).sum() / np.abs(ref).sum() < 1e-5
+        dg, do = b.diag(r)[-1], orc.diag()[-1]
+        assert dg["step"] == 4 and dg["err"] == 0
+        assert dg["t"] == pytest.approx(do["t"], rel=1e-5)
+        orc.close()
+    b.close()
 
 
 def test_same_size_runs_keep_their_potential_energy(gp, W):

@@ -7,7 +7,7 @@ steps; mass (plus what left through outflow faces) conserved to 1e-12."""
 import numpy as np
 import pytest
 
-from gpu_helpers import gpu_state, make_pair, rel_l1, say
+from gpu_helpers import assert_close_fields, gpu_state, make_pair, rel_l1, say
 
 pytestmark = pytest.mark.gpu
 
@@ -43,9 +43,7 @@ def test_fp32_blob_against_oracle(gp, W):
     sim.step(100)
     sim.sync()
     orc.step(100)
-    err = rel_l1(gpu_state(sim), orc.get_state())
-    say("fp32 vs oracle worst", max(err, key=err.get), max(err.values()))
-    assert max(err.values()) <= 1e-4, err
+    assert_close_fields(gpu_state(sim), orc.get_state(), 1e-4, "fp32 blob 100 steps", cfg)
     drift = _mass_drift(sim.diag())
     say("mass drift", drift)
     assert drift <= 1e-12
@@ -87,9 +85,7 @@ def test_fp32_two_disk_against_fp64_gpu(gp, W):
         s.sync()
         sims[prec] = s
     torch.cuda.synchronize()
-    err = rel_l1(gpu_state(sims["fp32"]), gpu_state(sims["fp64"]))
-    say("fp32 vs fp64 worst", max(err, key=err.get), max(err.values()))
-    assert max(err.values()) <= 1e-4, err
+    assert_close_fields(gpu_state(sims["fp32"]), gpu_state(sims["fp64"]), 1e-4, "fp32 vs fp64 GPU, 100 steps", cfg)
     assert _mass_drift(sims["fp32"].diag()) <= 1e-12
     d32, d64 = sims["fp32"].diag()[-1], sims["fp64"].diag()[-1]
     assert d32["t"] == pytest.approx(d64["t"], rel=1e-5)

@@ -76,10 +76,8 @@ def test_fp32_two_disk_256(gp, W):
     orc.set_state(W.to_numpy(st))
     orc.step(3)
     ref = orc.get_state()
-    err64 = assert_close_fields(g64, ref, 1e-12, "FP64 GPU vs oracle, 256^3")
-    err32 = rel_l1(g32, ref)
-    say("worst FP64 %.2e, worst FP32 %.2e" % (max(err64.values()), max(err32.values())))
-    assert max(err32.values()) <= 1e-5, err32
+    assert_close_fields(g64, ref, 1e-12, "FP64 GPU vs oracle, 256^3", cfg)
+    assert_close_fields(g32, ref, 1e-5, "FP32 GPU vs oracle, 256^3", cfg)
     assert max(rel_l1(g32, g64).values()) <= 1e-5
     assert _mass_drift(d32) <= 1e-12
     assert d32[-1]["err"] == 0 and d32[-1]["step"] == 3

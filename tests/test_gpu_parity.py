@@ -51,10 +51,10 @@ def test_stage_by_stage_parity(gp, W, case):
     for step in range(2):
         sim.stage(gp.GP_STAGE_EUL)
         orc.stage(0)
-        assert_close_fields(gpu_state(sim), orc.get_state(), 1e-13, "eulerian step %d" % step)
+        assert_close_fields(gpu_state(sim), orc.get_state(), 1e-13, "eulerian step %d" % step, cfg)
         sim.stage(gp.GP_STAGE_LAG)
         orc.stage(1)
-        assert_close_fields(gpu_state(sim), orc.get_state(), 1e-13, "lagrangian step %d" % step)
+        assert_close_fields(gpu_state(sim), orc.get_state(), 1e-13, "lagrangian step %d" % step, cfg)
         sim.stage(gp.GP_STAGE_POISSON)
         orc.stage(2)
         assert _phi_rel(sim, orc) < 1e-12  # FFT rounding grows with log N
@@ -77,7 +77,7 @@ def test_full_step_parity_blob_100_steps(gp, W):
     sim.step(100)
     sim.sync()
     orc.step(100)
-    err = assert_close_fields(gpu_state(sim), orc.get_state(), 1e-9, "blob 100 steps")
+    err = assert_close_fields(gpu_state(sim), orc.get_state(), 1e-9, "blob 100 steps", cfg)
     say("max rel L1", max(err.values()))
     dg, do = sim.diag()[-1], orc.diag()[-1]
     assert dg["step"] == 100 and do["step"] == 100
@@ -95,11 +95,46 @@ def test_parity_two_disk_collision_128(gp, W):
     sim.step(5)
     sim.sync()
     orc.step(5)
-    err = assert_close_fields(gpu_state(sim), orc.get_state(), 1e-11, "two-disk 5 steps")
+    err = assert_close_fields(gpu_state(sim), orc.get_state(), 1e-11, "two-disk 5 steps", cfg)
     say("max rel L1", max(err.values()))
     phi_g = sim.get_field("phi").cpu().numpy()
     phi_o = orc.get_field("phi")
     assert np.abs(phi_g - phi_o).sum() / np.abs(phi_o).sum() < 1e-11
+
+
+def test_parity_two_disk_collision_128_100_steps(gp, W):
+    """The benchmark workload over 100 steps, in the launch configuration the
+    benchmark times, against one 100-step oracle run: the FP64 step within
+    1e-9 relative L1 per field, the FP32 form (rho and n in FP64) within
+    1e-4, element-wise and on the outflow planes too; FP32 mass balance to
+    1e-12."""
+    import torch
+    say("parity: two-disk collision 128^3, 100 steps, FP64 and FP32 vs the oracle")
+    import oracle
+    cfg, st = W.two_disk_collision(128)
+    orc = oracle.Oracle(cfg)
+    orc.set_state(W.to_numpy(st))
+    orc.step(100)
+    ref = orc.get_state()
+    phi_ref = orc.get_field("phi")
+    d_ref = orc.diag()[-1]
+    for prec, tol in (("fp64", 1e-9), ("fp32", 1e-4)):
+        c = dict(cfg, precision=prec)
+        sim = gp.Sim(c)
+        sim.set_state({k: v.to("cuda") for k, v in st.items()})
+        sim.step(100)
+        sim.sync()
+        assert_close_fields(gpu_state(sim), ref, tol, "two-disk 128^3 %s, 100 steps" % prec, cfg)
+        phi = sim.get_potential().cpu().numpy()
+        assert np.abs(phi - phi_ref).sum() / np.abs(phi_ref).sum() < tol
+        d = sim.diag()
+        assert d[-1]["step"] == 100 and d[-1]["err"] == 0
+        assert d[-1]["t"] == pytest.approx(d_ref["t"], rel=tol)
+        for comp in ("gas", "bme"):
+            m0 = d[0]["mass_" + comp]
+            assert max(abs(r["mass_" + comp] + r["outflow_" + comp] - m0) for r in d) <= 1e-12 * m0
+        sim.close()
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
@@ -111,7 +146,7 @@ def test_shock_tube_parity_no_gravity(gp, W, axis):
     sim.step(60)
     sim.sync()
     orc.step(60)
-    assert_close_fields(gpu_state(sim), orc.get_state(), 1e-11, "tube axis %d" % axis)
+    assert_close_fields(gpu_state(sim), orc.get_state(), 1e-11, "tube axis %d" % axis, cfg)
 
 
 def test_periodic_conservation_on_gpu(gp, W):
