@@ -72,11 +72,26 @@ def boundary_slabs(cfg):
     return out
 
 
-def assert_close_fields(got, ref, tol, what="", cfg=None, max_tol=None):
+# Relative-L1 bar of the outflow boundary planes for an FP32 run against an
+# FP64 reference.  The disk workloads' outermost planes are near-vacuum
+# (density floor 1e-6, pressure ~1e-11), where the Riemann fluxes and the
+# energy balance cancel: rounding only the inputs to FP32 moves those planes
+# by up to 1.1e-5 in the oracle itself after 4 steps (ensemble members of
+# 64^3 and 96^3; 9e-6 for the 256^3 two-disk state after 3 steps, 4e-6 for
+# the 128^3 one after 100), and the FP32 step, which rounds every
+# intermediate, moved the 64^3 member's by 6.7e-5.  Index errors at the
+# boundary are caught by the FP64 comparisons, which run the same templated
+# code at 1e-9 to 1e-13.
+FP32_SLAB_TOL = 1e-3
+
+
+def assert_close_fields(got, ref, tol, what="", cfg=None, max_tol=None, slab_tol=None):
     """Every field within `tol` relative L1 of the reference, within `max_tol`
     (default 10 tol) element-wise (rel_max), and, for each outflow axis of
-    cfg, within `tol` relative L1 on its first and last two planes alone."""
+    cfg, within `slab_tol` (default tol) relative L1 on its first and last two
+    planes alone."""
     max_tol = 10.0 * tol if max_tol is None else max_tol
+    slab_tol = tol if slab_tol is None else slab_tol
     err = rel_l1(got, ref)
     worst = max(err, key=err.get)
     assert err[worst] <= tol, "%s: worst field %s rel L1 %.3e > %.1e; all %s" % (
@@ -91,8 +106,8 @@ def assert_close_fields(got, ref, tol, what="", cfg=None, max_tol=None):
             es = rel_l1({k: got[k][idx] for k in got}, {k: ref[k][idx] for k in ref})
             ws = max(es, key=es.get)
             worst_slab = max(worst_slab, es[ws])
-            assert es[ws] <= tol, "%s: %s-%s boundary planes, field %s rel L1 %.3e > %.1e" % (
-                what, axis, side, ws, es[ws], tol)
+            assert es[ws] <= slab_tol, "%s: %s-%s boundary planes, field %s rel L1 %.3e > %.1e" % (
+                what, axis, side, ws, es[ws], slab_tol)
     say("%s: rel L1 %.2e (%s), element-wise %.2e (%s), boundary planes %.2e" % (
         what, err[worst], worst, em[wm], wm, worst_slab))
     return err
