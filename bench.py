@@ -277,6 +277,33 @@ def precision_forms(args):
     return out
 
 
+def isolated_form(args):
+    """The headline workload with isolated (zero-padded) Poisson boundaries:
+    two-disk collision 128^3 FP64, the free-space potential each step."""
+    import torch
+    from paper_1311_0861_amd import gpupegas as gp
+    from paper_1311_0861_amd import workloads as W
+    cfg, st = W.two_disk_collision(128, device="cuda")
+    cfg["poisson"] = "isolated"
+    s = gp.Sim(cfg)
+    s.set_state(st)
+    del st
+    sec = timed_steps(s, args.form_steps, 5)
+    kt = s.time_kernels(3)
+    n = 128 ** 3
+    fft = sum(kt[k] for k in ("fft_xy_fwd", "fft_z_green", "fft_xy_inv"))
+    out = {"workload": "two-disk collision 128^3 FP64, isolated Poisson boundaries (zero padding to 256^3)",
+           "value": round(n * args.form_steps / sec / 1e6, 2), "unit": "Mcell-updates/s",
+           "steps": args.form_steps, "ms_per_step": round(sec / args.form_steps * 1e3, 5),
+           "poisson_ms": round(fft, 5), "mass_drift": mass_drift(s.diag()),
+           "kernels": {k: {"ms": round(v, 5),
+                           "GB/s": round(s.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * n / (v * 1e-3) / 1e9, 1)
+                           if v > 0 else None} for k, v in kt.items()}}
+    s.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_form(args):
     """48 independent two-disk runs (64^3 / 96^3 / 128^3, FP32) advanced together."""
     import torch
@@ -330,8 +357,13 @@ def main():
         s.set_state({k: v.to("cuda") for k, v in st_cpu.items()})
         return s
 
-    # ---- timed run: warmup, then exactly K graph-replayed steps ------------
     sim = fresh_sim()
+    # a kernel-by-kernel pass first: it picks the launch sizes and brings the
+    # GPU to its working clocks before the timed steps (its timings are
+    # discarded; the roofline is taken again after the timed run)
+    sim.time_kernels(args.profile_steps)
+
+    # ---- timed run: warmup, then exactly K graph-replayed steps ------------
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -387,6 +419,7 @@ def main():
     forms = None
     if not args.no_forms:
         forms = precision_forms(args)
+        forms["isolated_128"] = isolated_form(args)
         forms["batch48"] = batch_form(args)
 
     out = {

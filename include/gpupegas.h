@@ -53,6 +53,15 @@ typedef enum {
 } gp_status;
 
 enum { GP_BC_OUTFLOW = 0, GP_BC_PERIODIC = 1 };
+/* Boundary of the potential.  Periodic: the FFT solve of the 27-point
+ * Poisson equation with its printed Fourier symbol (Sec. 2.3), zero-mean
+ * potential.  Isolated: the free-space potential of the cell masses, sum over
+ * cells of -G m / r with the cell's own term taken as a uniform cube, by zero
+ * padding to twice the grid on each axis (Hockney and Eastwood's method,
+ * which Sec. 1 cites among the Poisson solvers of other codes); the gravity
+ * of the outermost cells then reads the potential on a one-cell ring outside
+ * the grid, which the solve also delivers. */
+enum { GP_POISSON_PERIODIC = 0, GP_POISSON_ISOLATED = 1 };
 enum { GP_FP64 = 0, GP_FP32 = 1 };
 
 /* State fields, in this order.  GP_PHI (the potential) is read-only. */
@@ -87,8 +96,8 @@ enum {
 typedef struct {
   int32_t n[3];      /* cells per axis; >= 4.  With G != 0 each must be even and
                         of the form 2^a 3^b (FFT lengths)                    */
-  int32_t bc[3];     /* GP_BC_OUTFLOW (clamped, zero-gradient) or GP_BC_PERIODIC;
-                        the potential is always periodic                     */
+  int32_t bc[3];     /* GP_BC_OUTFLOW (clamped, zero-gradient) or GP_BC_PERIODIC
+                        for the hydrodynamics; the potential has its own     */
   double lo[3], hi[3];
   double gamma;      /* adiabatic index, > 1                                 */
   double G;          /* gravitational constant; 0 switches gravity off       */
@@ -98,7 +107,7 @@ typedef struct {
   double t_end;      /* > 0: the step is clipped so that t never exceeds it  */
   int32_t precision; /* GP_FP64, or GP_FP32 (rho and n stay FP64; CFL, sums
                         and the Poisson zero mode stay FP64)                  */
-  int32_t reserved;  /* must be 0                                            */
+  int32_t poisson;   /* GP_POISSON_PERIODIC (0) or GP_POISSON_ISOLATED        */
 } gp_config;
 
 /* One diagnostics record per step (and one for the initial state).  Sums are
@@ -130,9 +139,11 @@ typedef struct gp_sim gp_sim;
  * or NULL for a stream the sim creates and owns.  On success *out receives
  * the handle, which the caller releases with gp_destroy; on failure *out is
  * NULL and nothing is allocated.  Returns GP_E_INVALID for a bad config
- * (h not equal on all axes, n < 4, gamma <= 1, cfl <= 0, reserved != 0),
- * GP_E_UNSUPPORTED for FFT lengths the kernels do not handle (with G != 0
- * every n must be even and 2^a 3^b), GP_E_NOMEM, GP_E_HIP. */
+ * (h not equal on all axes, n < 4, gamma <= 1, cfl <= 0, poisson not one
+ * of GP_POISSON_*), GP_E_UNSUPPORTED for FFT lengths the kernels do not
+ * handle (with G != 0 every n must be even and 2^a 3^b), GP_E_NOMEM, GP_E_HIP.
+ * With isolated boundaries and G != 0 the sim also computes the DFT of the
+ * sampled Green function of its padded grid here (once, on the GPU). */
 gp_status gp_create(const gp_config *cfg, void *hip_stream, gp_sim **out);
 /* Wait for the sim's stream, free its device memory (and its stream if it
  * created it).  GP_E_INVALID for NULL. */
@@ -156,10 +167,12 @@ gp_status gp_set_field(gp_sim *sim, int32_t field, const void *src, int32_t dtyp
 gp_status gp_get_field(gp_sim *sim, int32_t field, void *dst, int32_t dtype,
                        int32_t on_device);
 
-/* Potential Phi of the current state (Sec. 2.3: Laplace(Phi) = 4 pi G
- * (rho + n) on the 27-point stencil, solved by FFT on the periodic grid with
- * the zero mode removed), nx*ny*nz values of type dtype into dst (host or
- * device as on_device says).  Computed first if the state was set since the
+/* Potential Phi of the current state, nx*ny*nz values of type dtype into dst
+ * (host or device as on_device says): with GP_POISSON_PERIODIC the solution
+ * of Laplace(Phi) = 4 pi G (rho + n) on the 27-point stencil by FFT on the
+ * periodic grid with the zero mode removed (Sec. 2.3); with
+ * GP_POISSON_ISOLATED the free-space potential of the cell masses (see
+ * GP_POISSON_ISOLATED; the ring outside the grid is not returned).  Computed first if the state was set since the
  * last step.  Returns the latched device status after the copy, as
  * gp_get_field. */
 gp_status gp_get_potential(gp_sim *sim, void *dst, int32_t dtype, int32_t on_device);

@@ -68,6 +68,20 @@ __device__ __forceinline__ Column make_column(const Grid& g, int ntx, const Work
   return c;
 }
 
+// The potential's geometry.  Periodic: nx ny nz values, wrapped on every
+// axis.  Isolated: the grid and its one-cell ring, (nx+2)(ny+2)(nz+2) values
+// with cell i at index i + 1 on each axis; tile positions beyond the ring
+// (ragged edge tiles) are never read and take the ring's last cell.
+__device__ __forceinline__ Column make_phi_column(const Grid& g, int ntx, const WorkItem& it) {
+  Column c = make_column(g, ntx, it, true);
+  if (g.phi_iso) {
+    const uint32_t ex = (uint32_t)g.nx + 2;
+    c.xy_c = (uint32_t)(min(c.i, g.nx) + 1) + ex * (uint32_t)(min(c.j, g.ny) + 1);
+    c.xy_h = (uint32_t)(min(c.i0 + c.hc - 1, g.nx) + 1) + ex * (uint32_t)(min(c.j0 + c.hr - 1, g.ny) + 1);
+  }
+  return c;
+}
+
 // Re-issues a lane offset inside a plane loop.  Without it the compiler
 // hoists "array base + lane offset" out of the loop as one 64-bit vector
 // pointer per array and adds the plane offset to each of them every
@@ -99,6 +113,12 @@ __device__ __forceinline__ void issue_order() { asm volatile("" ::: "memory"); }
 // Element offset of plane k under the z boundary rule.
 __device__ __forceinline__ size_t plane_at(const Grid& g, int k, int bc) {
   return (size_t)g.nx * (size_t)g.ny * (size_t)bc_index(k, g.nz, bc);
+}
+
+// Element offset of plane k (-1 .. nz) of the potential (see make_phi_column).
+__device__ __forceinline__ size_t phi_plane(const Grid& g, int k) {
+  if (g.phi_iso) return (size_t)(g.nx + 2) * (size_t)(g.ny + 2) * (size_t)(k + 1);
+  return plane_at(g, k, GP_BC_PERIODIC);
 }
 
 }  // namespace gp

@@ -47,7 +47,8 @@ struct Fields {
 
 struct Grid {
   int nx, ny, nz;
-  int bc[3];  // GP_BC_OUTFLOW / GP_BC_PERIODIC
+  int bc[3];    // GP_BC_OUTFLOW / GP_BC_PERIODIC
+  int phi_iso;  // 1: the potential has isolated boundaries and is stored with a one-cell ring
   double h;
   size_t ncell;
 };

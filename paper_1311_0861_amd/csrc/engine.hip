@@ -47,6 +47,10 @@ namespace {
 constexpr long kItemsFp64[2] = {512, 768};
 constexpr long kItemsFp32[2] = {512, 512};
 constexpr int kTunedKernels = 4;  // the per-cell kernels
+// Largest grid axis with isolated Poisson boundaries: a padded line of 2n
+// complex values (and an x row of n packed pairs with its bins) stays within
+// 64 KiB of LDS in FP64.
+constexpr int kIsoMaxN = 512;
 const int kTunedIds[kTunedKernels] = {GP_K_EUL_GAS, GP_K_EUL_BME, GP_K_LAG_GAS, GP_K_LAG_BME};
 
 struct RunHost {
@@ -78,6 +82,10 @@ struct SizeClass {
   void* tw_z = nullptr;
   double* dtab[3] = {nullptr, nullptr, nullptr};
   FftGeom fg{};
+  // isolated boundaries: padded geometry and the Green spectrum (FP64)
+  int iso = 0;
+  IsoGeom ig{};
+  double* green = nullptr;
   unsigned eoff = 0;  // first potential-energy partial of the class
   unsigned nep_run = 0;
 };
@@ -152,17 +160,6 @@ bool fft_len_ok(int n) {
   return n == 1;
 }
 
-FftAxis make_axis(int L) {
-  FftAxis a{};
-  a.L = L;
-  int m = L;
-  while (m % 8 == 0 && m > 1) { a.rad[a.nst++] = 8; m /= 8; }
-  while (m % 4 == 0) { a.rad[a.nst++] = 4; m /= 4; }
-  while (m % 2 == 0) { a.rad[a.nst++] = 2; m /= 2; }
-  while (m % 3 == 0) { a.rad[a.nst++] = 3; m /= 3; }
-  return a;
-}
-
 size_t esize(int prec) { return prec == GP_FP64 ? sizeof(double) : sizeof(float); }
 
 void* dalloc(gp_batch* b, size_t bytes, gp_status* st) {
@@ -186,11 +183,15 @@ gp_status validate(const gp_config* cfg) {
   const double h = (cfg->hi[0] - cfg->lo[0]) / cfg->n[0];
   for (int d = 1; d < 3; d++)
     if (std::fabs((cfg->hi[d] - cfg->lo[d]) / cfg->n[d] - h) > 1e-12 * h) return GP_E_INVALID;
-  if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0) || cfg->reserved != 0) return GP_E_INVALID;
+  if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return GP_E_INVALID;
+  if (cfg->poisson != GP_POISSON_PERIODIC && cfg->poisson != GP_POISSON_ISOLATED) return GP_E_INVALID;
   if (cfg->precision != GP_FP64 && cfg->precision != GP_FP32) return GP_E_INVALID;
   if (cfg->G != 0.0)
-    for (int d = 0; d < 3; d++)
+    for (int d = 0; d < 3; d++) {
       if (!fft_len_ok(cfg->n[d]) || cfg->n[d] % 2 != 0) return GP_E_UNSUPPORTED;
+      // the padded solve keeps a padded line of 2n values in LDS
+      if (cfg->poisson == GP_POISSON_ISOLATED && cfg->n[d] > kIsoMaxN) return GP_E_UNSUPPORTED;
+    }
   return GP_OK;
 }
 
@@ -206,6 +207,47 @@ FftTables<T> tables(const SizeClass& c) {
   t.dy = c.dtab[1];
   t.dz = c.dtab[2];
   return t;
+}
+
+template <typename T>
+IsoTables<T> iso_tables(const SizeClass& c) {
+  IsoTables<T> t{};
+  t.tw_x = static_cast<const cplx<T>*>(c.tw_x);
+  t.wn_x = static_cast<const cplx<T>*>(c.wn_x);
+  t.tw_y = static_cast<const cplx<T>*>(c.tw_y);
+  t.tw_z = static_cast<const cplx<T>*>(c.tw_z);
+  t.green = c.green;
+  return t;
+}
+
+// Padded geometry of a size class with isolated boundaries, for complex
+// values of 2 * es bytes: line passes of at most 32 KiB of LDS data, as the
+// periodic line passes.
+IsoGeom make_iso_geom(int nx, int ny, int nz, int nruns, size_t es) {
+  IsoGeom f{};
+  f.nx = nx;
+  f.ny = ny;
+  f.nz = nz;
+  f.px = nx + 1;
+  f.py = 2 * ny;
+  f.pz = 2 * nz;
+  f.nruns = nruns;
+  f.ax = make_axis(nx);
+  f.ay = make_axis(2 * ny);
+  f.az = make_axis(2 * nz);
+  const int maxpts = 32768 / (int)(2 * es);
+  f.rows_per_block = std::max(1, maxpts / (2 * nx));
+  auto even_cols = [&](int L) {
+    const int cmax = std::max(1, std::min({8, f.px, maxpts / L}));
+    const int nch = (f.px + cmax - 1) / cmax;
+    return (f.px + nch - 1) / nch;
+  };
+  f.cols_y = even_cols(f.ay.L);
+  f.cols_z = even_cols(f.az.L);
+  f.run_stride = (size_t)(nz + 2) * f.py * f.px;
+  f.ext_cells = (size_t)(nx + 2) * (ny + 2) * (nz + 2);
+  f.norm = 2.0 / (8.0 * (double)nx * (double)ny * (double)nz);
+  return f;
 }
 
 void tmark(gp_batch* b, Timer* tm, int k, int side) {
@@ -245,9 +287,26 @@ void enqueue_poisson(gp_batch* b, Timer* tm, int fin) {
     tmark(b, tm, k, 0);
     for (SizeClass& c : b->classes) {
       if (c.G == 0.0) continue;
-      const FftTables<T> t = tables<T>(c);
       auto* spec = static_cast<cplx<T>*>(c.spec);
       T* phi = static_cast<T*>(c.phi);
+      if (c.iso) {
+        const IsoTables<T> t = iso_tables<T>(c);
+        switch (k) {
+          case GP_K_FFT_XY_FWD:
+            launch_iso_fwd<T>(c.src, b->parity, spec, c.ig, t, b->st);
+            break;
+          case GP_K_FFT_Z:
+            launch_iso_z<T>(spec, c.ig, t, b->epot + c.eoff, reduced ? RedJob{} : red_job(b), b->st);
+            reduced = true;
+            break;
+          case GP_K_FFT_XY_INV:
+            launch_iso_inv<T>(spec, phi, c.ig, t, finished ? FinJob{} : fin_job(b, fin), b->st);
+            finished = true;
+            break;
+        }
+        continue;
+      }
+      const FftTables<T> t = tables<T>(c);
       const bool plane = c.fg.plane && b->fft_form == GP_FFT_AUTO;
       switch (k) {
         case GP_K_FFT_XY_FWD:
@@ -543,6 +602,59 @@ RunDev<T> make_rundev(const RunHost& r) {
   return d;
 }
 
+// exp(-2 pi i k / L), k < n, as (re, im) pairs, from host FP64 libm
+std::vector<double> twiddle_table(int n, int L) {
+  std::vector<double> d(2 * (size_t)n);
+  for (int k = 0; k < n; k++) {
+    const double a = 2.0 * M_PI * (double)k / (double)L;
+    d[2 * k] = std::cos(a);
+    d[2 * k + 1] = -std::sin(a);
+  }
+  return d;
+}
+
+// The Green spectrum of a size class with isolated boundaries, computed once
+// in FP64 (whatever the working precision) with temporary twiddle tables and
+// a temporary spectrum of all 2nz padded planes, freed before returning.
+gp_status iso_green_spectrum(gp_batch* b, SizeClass& c) {
+  IsoGeom g = make_iso_geom(c.nx, c.ny, c.nz, 1, sizeof(double));
+  g.run_stride = (size_t)g.pz * g.py * g.px;
+  std::vector<void*> tmp;
+  hipError_t e = hipSuccess;
+  auto talloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    tmp.push_back(p);
+    return p;
+  };
+  auto tw = [&](int n, int L) -> const cplx<double>* {
+    const std::vector<double> d = twiddle_table(n, L);
+    void* p = talloc(d.size() * sizeof(double));
+    if (p && e == hipSuccess) e = hipMemcpy(p, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice);
+    return static_cast<const cplx<double>*>(p);
+  };
+  IsoTables<double> t{};
+  t.tw_x = tw(g.ax.L, g.ax.L);
+  t.wn_x = tw(g.ax.L + 1, 2 * g.nx);
+  t.tw_y = tw(g.ay.L, g.ay.L);
+  t.tw_z = tw(g.az.L, g.az.L);
+  auto* work = static_cast<cplx<double>*>(talloc(g.run_stride * sizeof(cplx<double>)));
+  gp_status st = GP_OK;
+  if (!t.tw_x || !t.wn_x || !t.tw_y || !t.tw_z || !work) {
+    st = GP_E_NOMEM;
+    b->last_error = "device allocation for the isolated Green spectrum failed";
+  } else if (e != hipSuccess) {
+    st = hip_fail(b, e, "isolated Green spectrum tables");
+  } else {
+    launch_iso_green(work, g, t, c.green, c.h, c.G, b->st);
+    e = hipStreamSynchronize(b->st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) st = hip_fail(b, e, "isolated Green spectrum");
+  }
+  for (void* p : tmp) (void)hipFree(p);
+  return st;
+}
+
 gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip_stream) {
   if (!cfgs || nruns < 1) return GP_E_INVALID;
   for (int r = 0; r < nruns; r++) {
@@ -565,7 +677,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   gp_status st = GP_OK;
 
   // runs and size classes (same grid, cell size and G share FFT launches)
-  std::map<std::tuple<int, int, int, double, double>, int> cls_of;
+  std::map<std::tuple<int, int, int, double, double, int>, int> cls_of;
   b->runs.resize(nruns);
   unsigned row = 0;
   for (int r = 0; r < nruns; r++) {
@@ -577,6 +689,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     for (int d = 0; d < 3; d++) R.g.bc[d] = cfgs[r].bc[d];
     R.g.h = (cfgs[r].hi[0] - cfgs[r].lo[0]) / cfgs[r].n[0];
     R.g.ncell = (size_t)R.g.nx * R.g.ny * R.g.nz;
+    R.g.phi_iso = cfgs[r].poisson == GP_POISSON_ISOLATED ? 1 : 0;
     R.ph = Phys{cfgs[r].gamma, cfgs[r].G, cfgs[r].cfl, cfgs[r].eta, cfgs[r].fixed_dt, cfgs[r].t_end};
     R.ntx = (R.g.nx + kTX - 1) / kTX;
     R.nty = (R.g.ny + kTY - 1) / kTY;
@@ -586,7 +699,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     R.nrows = std::max(items_per_run(R, b->prec, 0), items_per_run(R, b->prec, 1));
     R.row0 = row;
     row += R.nrows;
-    const auto key = std::make_tuple(R.g.nx, R.g.ny, R.g.nz, R.g.h, R.ph.G);
+    const auto key = std::make_tuple(R.g.nx, R.g.ny, R.g.nz, R.g.h, R.ph.G, R.g.phi_iso);
     auto it = cls_of.find(key);
     if (it == cls_of.end()) {
       SizeClass c;
@@ -595,6 +708,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
       c.nz = R.g.nz;
       c.h = R.g.h;
       c.G = R.ph.G;
+      c.iso = R.g.phi_iso;
       b->classes.push_back(c);
       it = cls_of.emplace(key, (int)b->classes.size() - 1).first;
     }
@@ -620,59 +734,33 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   b->staging = dalloc(b, max_cells * sizeof(double), &st);
 
   // size classes: contiguous source / potential / spectrum, FFT tables
-  const int maxpts = 32768 / (int)(2 * es);
-  int dev = 0, lds_dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&lds_dev, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-    lds_dev = 0;
-  const int lds_max = std::min(kPlaneLdsMax, lds_dev);
-  bool planes_ready = false;
   unsigned eoff = 0;
   for (SizeClass& c : b->classes) {
     FftGeom& f = c.fg;
-    f.nx = c.nx;
-    f.ny = c.ny;
-    f.nz = c.nz;
-    f.nruns = (int)c.runs.size();
-    f.px = f.nx / 2 + 1;
-    f.ax = make_axis(f.nx / 2);
-    f.ay = make_axis(f.ny);
-    f.az = make_axis(f.nz);
-    f.rows_per_block = std::max(1, maxpts / (2 * f.ax.L));
-    // columns per workgroup: at most 8 (and the LDS budget), spread evenly
-    // over the px = nx/2 + 1 half-spectrum columns so no chunk is nearly empty
-    // (8 measured faster than 16, 4 or 2 at 64^3 to 256^3)
-    auto even_cols = [&](int L, int cap) {
-      const int cmax = std::max(1, std::min({cap, f.px, maxpts / L}));
-      const int nch = (f.px + cmax - 1) / cmax;
-      return (f.px + nch - 1) / nch;
-    };
-    f.cols_y = even_cols(f.ay.L, 8);
-    // x and y transforms of the even or the odd rows of a z plane per
-    // workgroup where they fit
-    f.ayh = make_axis(f.ny / 2);
-    f.hp = (f.ax.L + 1) | 1;  // odd row pitch: lanes on neighbouring rows hit other banks
-    // (where two such workgroups fit on a CU; with one per CU the separate x
-    // and y passes are faster, e.g. 256^3 FP32)
-    f.plane = c.G != 0.0 && 2 * plane_lds_bytes(f, 2 * es) <= (size_t)lds_max;
-    // the z pass after the plane passes holds the columns of two ky rows, 64
-    // bytes of each row per z (4 FP64 or 8 FP32 columns)
-    f.cols_z = f.plane ? even_cols(2 * f.az.L, 32 / (int)es) : even_cols(f.az.L, 8);
-    if (f.plane && !planes_ready) {
-      // one limit for every size class: the kernels are shared
-      const hipError_t e =
-          b->prec == GP_FP64 ? fft_plane_prepare<double>(lds_max) : fft_plane_prepare<float>(lds_max);
-      planes_ready = e == hipSuccess;
-      if (!planes_ready) (void)hipGetLastError();
-    }
-    if (!planes_ready) f.plane = 0;
+    f = make_fft_geom(c.nx, c.ny, c.nz, (int)c.runs.size(), b->prec, c.G != 0.0 && !c.iso);
     f.green_scale = -4.0 * M_PI * c.G * c.h * c.h / 6.0;
-    f.norm = 2.0 / ((double)f.nx * f.ny * f.nz);
     const size_t nc = (size_t)c.nx * c.ny * c.nz, R = c.runs.size();
     c.src = static_cast<SrcSlot*>(dalloc(b, R * sizeof(SrcSlot), &st));
-    c.phi = dalloc(b, R * nc * es, &st);
+    // the potential of a run: nc values, or with isolated boundaries the
+    // grid and its one-cell ring
+    size_t phi_cells = nc;
+    if (c.iso) {
+      c.ig = make_iso_geom(c.nx, c.ny, c.nz, (int)R, es);
+      phi_cells = c.ig.ext_cells;
+    }
+    c.phi = dalloc(b, R * phi_cells * es, &st);
     c.eoff = eoff;
-    if (c.G != 0.0) {
+    if (c.G != 0.0 && c.iso) {
+      const IsoGeom& g = c.ig;
+      c.spec = dalloc(b, R * g.run_stride * 2 * es, &st);
+      c.tw_x = dalloc(b, (size_t)g.ax.L * 2 * es, &st);
+      c.wn_x = dalloc(b, (size_t)(g.ax.L + 1) * 2 * es, &st);
+      c.tw_y = dalloc(b, (size_t)g.ay.L * 2 * es, &st);
+      c.tw_z = dalloc(b, (size_t)g.az.L * 2 * es, &st);
+      c.green = static_cast<double*>(dalloc(b, (size_t)g.px * (g.ny + 1) * (g.nz + 1) * sizeof(double), &st));
+      c.nep_run = (unsigned)(iso_blocks_z(g) / g.nruns);
+      eoff += (unsigned)iso_blocks_z(g);
+    } else if (c.G != 0.0) {
       c.spec = dalloc(b, R * (size_t)f.px * f.ny * f.nz * 2 * es, &st);
       c.tw_x = dalloc(b, (size_t)f.ax.L * 2 * es, &st);
       c.wn_x = dalloc(b, (size_t)(f.ax.L + 1) * 2 * es, &st);
@@ -688,7 +776,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     if (st != GP_OK) return st;
     for (size_t k = 0; k < R; k++) {
       RunHost& run = b->runs[c.runs[k]];
-      run.phi = static_cast<char*>(c.phi) + k * nc * es;
+      run.phi = static_cast<char*>(c.phi) + k * phi_cells * es;
     }
   }
   b->nepot = eoff;
@@ -716,7 +804,8 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     const SizeClass& c = b->classes[R.cls];
     fd.eoff = c.eoff + (unsigned)R.slot * c.nep_run;
     fd.nep = (c.G != 0.0) ? c.nep_run : 0u;
-    fd.epot_scale = 1.0 / (double)R.g.ncell;
+    // Parseval over the transformed lattice: the padded one when isolated
+    fd.epot_scale = 1.0 / ((R.g.phi_iso ? 8.0 : 1.0) * (double)R.g.ncell);
     fd.sc = R.sc;
     fd.ring = R.ring;
     fins.push_back(fd);
@@ -752,13 +841,7 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     put(b->runs_dev, rd.data(), rd.size() * sizeof(rd[0]));
   }
   auto put_tw = [&](void* dst, int n, int L) {
-    // exp(-2 pi i k / L), k < n, from host FP64 libm
-    std::vector<double> d(2 * (size_t)n);
-    for (int k = 0; k < n; k++) {
-      const double a = 2.0 * M_PI * (double)k / (double)L;
-      d[2 * k] = std::cos(a);
-      d[2 * k + 1] = -std::sin(a);
-    }
+    const std::vector<double> d = twiddle_table(n, L);
     if (b->prec == GP_FP64) {
       put(dst, d.data(), d.size() * sizeof(double));
     } else {
@@ -782,6 +865,14 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     }
     put(c.src, slots.data(), slots.size() * sizeof(SrcSlot));
     if (c.G == 0.0) continue;
+    if (c.iso) {
+      const IsoGeom& g = c.ig;
+      put_tw(c.tw_x, g.ax.L, g.ax.L);
+      put_tw(c.wn_x, g.ax.L + 1, 2 * g.nx);
+      put_tw(c.tw_y, g.ay.L, g.ay.L);
+      put_tw(c.tw_z, g.az.L, g.az.L);
+      continue;
+    }
     const FftGeom& f = c.fg;
     put_tw(c.tw_x, f.ax.L, f.ax.L);
     put_tw(c.wn_x, f.ax.L + 1, f.nx);
@@ -794,6 +885,11 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(b, e, "engine upload");
+  for (SizeClass& c : b->classes) {
+    if (!c.iso || c.G == 0.0) continue;
+    const gp_status gs = iso_green_spectrum(b, c);
+    if (gs != GP_OK) return gs;
+  }
   for (int k = 0; k < GP_NKERNELS; k++) b->blocks[k] = 0;
   for (int k : kTunedIds) b->blocks[k] = work_count(b, k);
   return GP_OK;
@@ -845,6 +941,23 @@ gp_status engine_get_field(gp_batch* b, int r, int32_t field, void* dst, int32_t
   const void* src = field_ptr(b, r, field, &src_double);
   const bool dst_double = dtype == GP_FP64;
   const size_t nc = b->runs[r].g.ncell;
+  if (field == GP_PHI && b->runs[r].g.phi_iso) {
+    // the potential is stored with its ring: copy out the grid part
+    const Grid& g = b->runs[r].g;
+    void* out = on_device ? dst : b->staging;
+    if (src_double) {
+      if (dst_double) launch_phi_interior<double, double>((double*)out, (const double*)src, g.nx, g.ny, g.nz, b->st);
+      else launch_phi_interior<float, double>((float*)out, (const double*)src, g.nx, g.ny, g.nz, b->st);
+    } else {
+      if (dst_double) launch_phi_interior<double, float>((double*)out, (const float*)src, g.nx, g.ny, g.nz, b->st);
+      else launch_phi_interior<float, float>((float*)out, (const float*)src, g.nx, g.ny, g.nz, b->st);
+    }
+    if (!on_device)
+      HIP_TRY(b, hipMemcpyAsync(dst, b->staging, nc * (dst_double ? 8 : 4), hipMemcpyDeviceToHost, b->st));
+    HIP_TRY(b, hipStreamSynchronize(b->st));
+    HIP_TRY(b, hipGetLastError());
+    return latched(b, r);
+  }
   const bool mid = b->next_stage == GP_STAGE_LAG;
   const bool gas_mom = field >= GP_MX && field <= GP_MZ, bme_mom = field >= GP_QX && field <= GP_QZ;
   if (mid && (gas_mom || bme_mom)) {
@@ -960,6 +1073,23 @@ double fft_bytes_per_cell(const gp_batch* b, int k) {
   for (const RunHost& R : b->runs) {
     cells += (double)R.g.ncell;
     if (R.ph.G == 0.0) continue;
+    if (R.g.phi_iso) {
+      // padded spectrum values (complex, 2 es bytes) each pass reads or writes
+      const double nx = R.g.nx, ny = R.g.ny, nz = R.g.nz, cs = 2.0 * es;
+      const double px = nx + 1, py = 2.0 * ny;
+      const double rows_src = px * ny * nz;            // x forward output, y forward input
+      const double planes_src = px * py * nz;          // y forward output, z input
+      const double planes_kept = px * py * (nz + 2);   // z output, y inverse input
+      const double rows_kept = px * (ny + 2) * (nz + 2);  // y inverse output, x inverse input
+      double v = 0.0;
+      switch (k) {
+        case GP_K_FFT_XY_FWD: v = 16.0 * nx * ny * nz + cs * (2.0 * rows_src + planes_src); break;
+        case GP_K_FFT_Z: v = cs * (planes_src + planes_kept) + 8.0 * px * (ny + 1) * (nz + 1); break;
+        case GP_K_FFT_XY_INV: v = cs * (planes_kept + 2.0 * rows_kept) + es * (nx + 2) * (ny + 2) * (nz + 2); break;
+      }
+      bytes += v;
+      continue;
+    }
     const double spec = 2.0 * es * (R.g.nx / 2 + 1) / R.g.nx;
     double v = 0.0;
     switch (k) {

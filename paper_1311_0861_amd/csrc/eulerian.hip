@@ -166,7 +166,9 @@ __device__ __forceinline__ BmeSide<T> bme_of(const T (&a)[kBmePrims]) {
   return o;
 }
 
-// Potential of the cell at (z, xy), zero without gravity.
+// Potential at plane offset z and in-plane offset xy (phi_plane and
+// make_phi_column give both for either boundary of the potential), zero
+// without gravity.
 template <typename T>
 __device__ __forceinline__ T phi_at(gptr<const T> phi, bool grav, size_t z, uint32_t xy) {
   return grav ? ld_at(phi, z, xy) : T(0);
@@ -185,7 +187,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
     const RunDev<T>& R = runs[run];
     const Grid& g = R.g;
     const Column col = make_column(g, R.ntx, it, false);
-    const Column pc = make_column(g, R.ntx, it, true);
+    const Column pc = make_phi_column(g, R.ntx, it);
     const bool grav = R.ph.G != 0.0;
     const size_t nxy = (size_t)g.nx * g.ny;
     const double tau_d = R.sc->dt;
@@ -224,8 +226,8 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       T m[3], e, pm[kGasPrims];
       load(zm, col.xy_c, rho, m, e);
       load(z0, col.xy_c, rho0, mc, ec);
-      const T phm = phi_at(phi, grav, plane_at(g, col.k0 - 1, GP_BC_PERIODIC), pc.xy_c);
-      phc = phi_at(phi, grav, z0, pc.xy_c);
+      const T phm = phi_at(phi, grav, phi_plane(g, col.k0 - 1), pc.xy_c);
+      phc = phi_at(phi, grav, phi_plane(g, col.k0), pc.xy_c);
       prims(rho, m, e, pm);
       prims(rho0, mc, ec, pc_);
       gas_face(gas_of<2>(pm), gas_of<2>(pc_), gamma, Vz, Pz);
@@ -238,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
     auto load_ring = [&](int kr) {
       const size_t zr = nxy * (size_t)kr;
       load(zr, col.xy_h, rho_h, m_h, e_h);
-      phh = phi_at(phi, grav, zr, pc.xy_h);
+      phh = phi_at(phi, grav, phi_plane(g, kr), pc.xy_h);
     };
     load_ring(col.k0);
     for (int k = col.k0; k < col.k1; k++) {
@@ -261,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
       double rho_n;
       T m_n[3], e_n;
       load(zp, xy_c, rho_n, m_n, e_n);
-      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
+      const T php = phi_at(phi, grav, phi_plane(g, k + 1), pxy_c);
       if (k + 1 < col.k1) load_ring(k + 1);
       const T E = ld_at(E_in, zk, xy_c);
       lds_barrier();
@@ -328,7 +330,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
     const RunDev<T>& R = runs[run];
     const Grid& g = R.g;
     const Column col = make_column(g, R.ntx, it, false);
-    const Column pc = make_column(g, R.ntx, it, true);
+    const Column pc = make_phi_column(g, R.ntx, it);
     const bool grav = R.ph.G != 0.0;
     const size_t nxy = (size_t)g.nx * g.ny;
     const double tau_d = R.sc->dt;
@@ -367,8 +369,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       T q[3], P[6], P0[6], pm[kBmePrims];
       load(zm, col.xy_c, n, q, P);
       load(z0, col.xy_c, n0, qc, P0);
-      const T phm = phi_at(phi, grav, plane_at(g, col.k0 - 1, GP_BC_PERIODIC), pc.xy_c);
-      phc = phi_at(phi, grav, z0, pc.xy_c);
+      const T phm = phi_at(phi, grav, phi_plane(g, col.k0 - 1), pc.xy_c);
+      phc = phi_at(phi, grav, phi_plane(g, col.k0), pc.xy_c);
       prims(n, q, P, pm);
       prims(n0, qc, P0, pc_);
       bme_face<T, 2>(bme_of<2>(pm), bme_of<2>(pc_), usz, psz);
@@ -381,7 +383,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
     auto load_ring = [&](int kr) {
       const size_t zr = nxy * (size_t)kr;
       load(zr, fresh(col.xy_h), n_h, q_h, P_h);
-      phh = phi_at(phi, grav, zr, fresh(pc.xy_h));
+      phh = phi_at(phi, grav, phi_plane(g, kr), fresh(pc.xy_h));
     };
     load_ring(col.k0);
     for (int k = col.k0; k < col.k1; k++) {
@@ -405,7 +407,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
       double n_n;
       T q_n[3], P_n[6], W[6];
       load(zp, xy_c, n_n, q_n, P_n);
-      const T php = phi_at(phi, grav, plane_at(g, k + 1, GP_BC_PERIODIC), pxy_c);
+      const T php = phi_at(phi, grav, phi_plane(g, k + 1), pxy_c);
       if (k + 1 < col.k1) load_ring(k + 1);
 #pragma unroll
       for (int m = 0; m < 6; m++) W[m] = ld_at(as_global((const T*)R.cur[oidx(GP_WXX + m)]), zk, xy_c);

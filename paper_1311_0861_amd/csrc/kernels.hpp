@@ -65,6 +65,14 @@ struct FftGeom {
   double norm;            // 2 / (nx ny nz)
 };
 
+// Radix plan (8s, then 4, 2, 3) of a complex transform of length L = 2^a 3^b.
+FftAxis make_axis(int L);
+// Geometry of the periodic solve for nruns runs of nx*ny*nz in precision prec
+// (GP_FP64 / GP_FP32): line and column blocking, and the per-half-plane x and
+// y transforms where planes is set and two such workgroups fit on a CU (this
+// also raises the plane kernels' dynamic-LDS limit).  green_scale is left 0.
+FftGeom make_fft_geom(int nx, int ny, int nz, int nruns, int prec, bool planes);
+
 // Potential-energy partials the z pass writes: one per (spectrum row, column
 // chunk), contiguous per run.
 int fft_blocks_z(const FftGeom& f);
@@ -136,6 +144,60 @@ void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftT
 template <typename T>
 void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTables<T>& t, const FinJob& fin,
                       hipStream_t st);
+
+// ---- isolated-boundary Poisson (zero padding to 2n on each axis) ----------
+// Geometry of one size class: the source occupies the first nx, ny, nz cells
+// of each padded axis; the spectrum of a run is C[z][y][kx], rows of px bins,
+// py rows per plane, nz + 2 planes (the z pass keeps nz + 2 of its 2nz
+// outputs, the y inverse ny + 2 of its 2ny).
+struct IsoGeom {
+  int nx, ny, nz;       // grid
+  int px;               // nx + 1: bins of a padded row (real length 2 nx)
+  int py, pz;           // 2 ny, 2 nz
+  int nruns;            // runs of this size stored back to back
+  FftAxis ax, ay, az;   // complex lengths nx (packed pairs of a padded row), 2 ny, 2 nz
+  int rows_per_block;   // x passes
+  int cols_y, cols_z;   // columns per workgroup of the column passes
+  size_t run_stride;    // spectrum values per run
+  size_t ext_cells;     // (nx + 2)(ny + 2)(nz + 2): potential on the grid and its ring
+  double norm;          // 2 / (8 nx ny nz): inverse normalisation of the packed real transforms
+};
+template <typename T>
+struct IsoTables {
+  const cplx<T>* tw_x;  // exp(-2 pi i k / nx), k < nx
+  const cplx<T>* wn_x;  // exp(-2 pi i k / (2 nx)), k <= nx
+  const cplx<T>* tw_y;  // exp(-2 pi i k / (2 ny))
+  const cplx<T>* tw_z;  // exp(-2 pi i k / (2 nz))
+  const double* green;  // DFT of the sampled Green function at kx <= nx, ky <= ny,
+                        // kz <= nz: (nz + 1)(ny + 1) rows of px values
+};
+// Potential-energy partials of the isolated z pass (one per ky line and
+// column chunk), contiguous per run.
+int iso_blocks_z(const IsoGeom& f);
+// One step's passes.  x and y forward: s = rho + n of every run of the class
+// -> its zero-padded spectrum.  z: forward, times the Green spectrum, inverse,
+// potential-energy partials (the first red.n workgroups run the reduction job
+// instead).  y and x inverse: -> the potential on the grid and its one-cell
+// ring, (nx + 2)(ny + 2)(nz + 2) values per run, cell i at index i + 1 on each
+// axis (the first fin.n workgroups of the x pass finish the step instead).
+template <typename T>
+void launch_iso_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const IsoGeom& f, const IsoTables<T>& t,
+                    hipStream_t st);
+template <typename T>
+void launch_iso_z(cplx<T>* spec, const IsoGeom& f, const IsoTables<T>& t, double* epot_partials, const RedJob& red,
+                  hipStream_t st);
+template <typename T>
+void launch_iso_inv(cplx<T>* spec, T* phi_ext, const IsoGeom& f, const IsoTables<T>& t, const FinJob& fin,
+                    hipStream_t st);
+// The Green spectrum of a class (FP64): samples g on the padded lattice into
+// `work` (pz planes of py rows of px values), transforms it along x, y and z,
+// and keeps the real part at kx <= nx, ky <= ny, kz <= nz in t.green.  f is
+// the class geometry laid out for FP64 with nruns = 1.
+void launch_iso_green(cplx<double>* work, const IsoGeom& f, const IsoTables<double>& t, double* green, double h,
+                      double G, hipStream_t st);
+// dst = the grid part of a potential stored with its ring (nx ny nz values)
+template <typename D, typename S>
+void launch_phi_interior(D* dst, const S* ext, int nx, int ny, int nz, hipStream_t st);
 
 // ---- reductions / finalize ---------------------------------------------
 void launch_reduce(const RedJob& red, hipStream_t st);

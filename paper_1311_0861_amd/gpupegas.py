@@ -17,6 +17,7 @@ GP_OK, GP_E_INVALID, GP_E_NOMEM, GP_E_HIP, GP_E_NONFINITE, GP_E_NONPOSITIVE, GP_
     0, -1, -2, -3, -4, -5, -6, -7)
 GP_BC_OUTFLOW, GP_BC_PERIODIC = 0, 1
 GP_FP64, GP_FP32 = 0, 1
+GP_POISSON_PERIODIC, GP_POISSON_ISOLATED = 0, 1
 GP_STAGE_EUL, GP_STAGE_LAG, GP_STAGE_POISSON, GP_STAGE_FINALIZE = 0, 1, 2, 3
 FIELD_NAMES = [
     "rho", "mx", "my", "mz", "E", "e",
@@ -43,7 +44,7 @@ class gp_config(ctypes.Structure):
         ("fixed_dt", ctypes.c_double),
         ("t_end", ctypes.c_double),
         ("precision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("poisson", ctypes.c_int32),
     ]
 
 
@@ -136,7 +137,7 @@ def _check(sim, status, batch=False):
 
 def make_config(cfg):
     """gp_config from the workload dict (keys n, lo, hi, gamma, G, cfl, eta,
-    fixed_dt, t_end, bc, precision)."""
+    fixed_dt, t_end, bc, precision, poisson)."""
     c = gp_config()
     for d in range(3):
         c.n[d] = int(cfg["n"][d])
@@ -151,7 +152,8 @@ def make_config(cfg):
     c.t_end = float(cfg.get("t_end", 0.0))
     prec = cfg.get("precision", "fp64")
     c.precision = GP_FP32 if prec in ("fp32", GP_FP32) else GP_FP64
-    c.reserved = 0
+    pois = cfg.get("poisson", "periodic")
+    c.poisson = {"periodic": GP_POISSON_PERIODIC, "isolated": GP_POISSON_ISOLATED}.get(pois, pois)
     return c
 
 
