@@ -81,6 +81,9 @@ typedef struct {
   double fixed_dt;    /* > 0: use this step instead of the CFL step          */
   double t_end;       /* > 0: never step past this time                      */
   int32_t poisson;    /* 0 = periodic (Sec. 2.3), 1 = isolated               */
+  double cool_lambda; /* cooling q = lambda rho^2 theta^alpha, theta = p/rho   */
+  double cool_alpha;  /*   (0 switches cooling off)                           */
+  double cool_theta_min; /* no cooling at or below this theta                 */
 } orc_config;
 
 typedef struct {
@@ -227,7 +230,13 @@ static void bme_face(const orc_sim *s, size_t L, size_t R, int d, double *us,
  *                      - tau (q_i g_j + q_j g_i)
  *         Pi_ij'= Pi_ij - tau/h sum_d (Pi_jd d_d u*_i + Pi_id d_d u*_j)
  * where d_d X = X(face c+1/2 e_d) - X(face c-1/2 e_d), g = grad Phi by central
- * difference; rho and n are unchanged. */
+ * difference; rho and n are unchanged.  The gas energy equations of Sec. 2
+ * also lose the cooling function q, which Sec. 2.1 assigns to this stage:
+ * E' and e' each take - tau q.  The paper's q is tabulated (Sutherland and
+ * Dopita); the tables are not at hand, so q is a stand-in power law of the
+ * density and theta = p / rho (proportional to the temperature):
+ *   q = lambda rho^2 theta^alpha  for theta > theta_min,  0 otherwise,
+ * evaluated from U^n like the other sources; lambda = 0 switches it off. */
 static void stage_eulerian(orc_sim *s) {
   for (int q = 0; q < NF; q++) memcpy(s->old[q], s->f[q], s->ncell * sizeof(double));
   const double tau = s->dt, h = s->h, gam = s->c.gamma, r = tau / h;
@@ -262,9 +271,14 @@ static void stage_eulerian(orc_sim *s) {
         const double m[3] = {s->old[MX][c], s->old[MY][c], s->old[MZ][c]};
         for (int d = 0; d < 3; d++)
           s->f[MX + d][c] = m[d] - r * dP[d] - tau * rho * grad[d];
+        double qc = 0.0;
+        if (s->c.cool_lambda != 0.0) {
+          const double theta = (gam - 1.0) * s->old[EI][c] / rho;
+          if (theta > s->c.cool_theta_min) qc = s->c.cool_lambda * rho * rho * pow(theta, s->c.cool_alpha);
+        }
         s->f[EN][c] = s->old[EN][c] - r * dPV -
-                      tau * (m[0] * grad[0] + m[1] * grad[1] + m[2] * grad[2]);
-        s->f[EI][c] = s->old[EI][c] - r * (gam - 1.0) * s->old[EI][c] * dV;
+                      tau * (m[0] * grad[0] + m[1] * grad[1] + m[2] * grad[2]) - tau * qc;
+        s->f[EI][c] = s->old[EI][c] - r * (gam - 1.0) * s->old[EI][c] * dV - tau * qc;
 
         /* BME */
         const double n = s->old[NB][c];

@@ -58,6 +58,9 @@ class OracleConfig(ctypes.Structure):
         ("fixed_dt", ctypes.c_double),
         ("t_end", ctypes.c_double),
         ("poisson", ctypes.c_int32),
+        ("cool_lambda", ctypes.c_double),
+        ("cool_alpha", ctypes.c_double),
+        ("cool_theta_min", ctypes.c_double),
     ]
 
 
@@ -161,7 +164,9 @@ def poisson_isolated(s, h, G=1.0):
 
 class Oracle:
     """One oracle simulation.  ``cfg`` is a dict with keys n, lo, hi, gamma, G,
-    cfl, eta, fixed_dt, t_end, bc (0 outflow, 1 periodic per axis)."""
+    cfl, eta, fixed_dt, t_end, bc (0 outflow, 1 periodic per axis), poisson
+    ("periodic" / "isolated") and the cooling law cool_lambda, cool_alpha,
+    cool_theta_min (absent: no cooling)."""
 
     def __init__(self, cfg):
         L = _load()
@@ -178,6 +183,9 @@ class Oracle:
         c.fixed_dt = float(cfg.get("fixed_dt", 0.0))
         c.t_end = float(cfg.get("t_end", 0.0))
         c.poisson = {"periodic": 0, "isolated": 1}[cfg.get("poisson", "periodic")]
+        c.cool_lambda = float(cfg.get("cool_lambda", 0.0))
+        c.cool_alpha = float(cfg.get("cool_alpha", 0.0))
+        c.cool_theta_min = float(cfg.get("cool_theta_min", 0.0))
         self._cfg = c
         self._h = L.orc_create(ctypes.byref(c))
         if not self._h:
