@@ -84,6 +84,7 @@ typedef struct {
   double cool_lambda; /* cooling q = lambda rho^2 theta^alpha, theta = p/rho   */
   double cool_alpha;  /*   (0 switches cooling off)                           */
   double cool_theta_min; /* no cooling at or below this theta                 */
+  double gext[3];     /* uniform external gravitational acceleration          */
 } orc_config;
 
 typedef struct {
@@ -236,7 +237,10 @@ static void bme_face(const orc_sim *s, size_t L, size_t R, int d, double *us,
  * Dopita); the tables are not at hand, so q is a stand-in power law of the
  * density and theta = p / rho (proportional to the temperature):
  *   q = lambda rho^2 theta^alpha  for theta > theta_min,  0 otherwise,
- * evaluated from U^n like the other sources; lambda = 0 switches it off. */
+ * evaluated from U^n like the other sources; lambda = 0 switches it off.
+ * A uniform external gravitational acceleration gext (the free fall of the
+ * Rayleigh-Taylor test of Sec. 4.4) adds to the self-gravity: the sources
+ * above take g_d = d_d Phi - gext_d. */
 static void stage_eulerian(orc_sim *s) {
   for (int q = 0; q < NF; q++) memcpy(s->old[q], s->f[q], s->ncell * sizeof(double));
   const double tau = s->dt, h = s->h, gam = s->c.gamma, r = tau / h;
@@ -249,9 +253,10 @@ static void stage_eulerian(orc_sim *s) {
         const size_t c = cidx(s, i, j, k);
         double grad[3];
         for (int d = 0; d < 3; d++)
-          grad[d] = s->c.poisson == 1
-                        ? (s->phi_ext[ext_nbr(s, i, j, k, d, +1)] - s->phi_ext[ext_nbr(s, i, j, k, d, -1)]) / (2.0 * h)
-                        : (s->phi[nbr_wrap(s, i, j, k, d, +1)] - s->phi[nbr_wrap(s, i, j, k, d, -1)]) / (2.0 * h);
+          grad[d] = (s->c.poisson == 1
+                         ? (s->phi_ext[ext_nbr(s, i, j, k, d, +1)] - s->phi_ext[ext_nbr(s, i, j, k, d, -1)]) / (2.0 * h)
+                         : (s->phi[nbr_wrap(s, i, j, k, d, +1)] - s->phi[nbr_wrap(s, i, j, k, d, -1)]) / (2.0 * h)) -
+                    s->c.gext[d];
 
         /* gas */
         double dP[3], dPV = 0.0, dV = 0.0;

@@ -61,6 +61,7 @@ class OracleConfig(ctypes.Structure):
         ("cool_lambda", ctypes.c_double),
         ("cool_alpha", ctypes.c_double),
         ("cool_theta_min", ctypes.c_double),
+        ("gext", ctypes.c_double * 3),
     ]
 
 
@@ -166,7 +167,8 @@ class Oracle:
     """One oracle simulation.  ``cfg`` is a dict with keys n, lo, hi, gamma, G,
     cfl, eta, fixed_dt, t_end, bc (0 outflow, 1 periodic per axis), poisson
     ("periodic" / "isolated") and the cooling law cool_lambda, cool_alpha,
-    cool_theta_min (absent: no cooling)."""
+    cool_theta_min (absent: no cooling), and gext, a uniform external
+    gravitational acceleration (absent: none)."""
 
     def __init__(self, cfg):
         L = _load()
@@ -186,6 +188,8 @@ class Oracle:
         c.cool_lambda = float(cfg.get("cool_lambda", 0.0))
         c.cool_alpha = float(cfg.get("cool_alpha", 0.0))
         c.cool_theta_min = float(cfg.get("cool_theta_min", 0.0))
+        for d in range(3):
+            c.gext[d] = float(cfg.get("gext", (0.0, 0.0, 0.0))[d])
         self._cfg = c
         self._h = L.orc_create(ctypes.byref(c))
         if not self._h:

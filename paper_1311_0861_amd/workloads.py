@@ -325,5 +325,105 @@ def hydrostatic_sphere(n=32, L=2.0, device="cpu", floor=1e-3):
     return cfg, assemble(rho, [zero] * 3, p, tiny, [zero] * 3, Pi, cfg["gamma"])
 
 
+# --------------------------------------------------------------------------
+# Instability tests (Sec. 4.4) and the author's cloud collision (Sec. 4.5)
+
+def _plane_config(n, nz, gamma, bc, G=0.0):
+    """[-0.5, 0.5]^2 in x, y on n x n cells; nz cells of the same size along a
+    periodic z (the two-dimensional tests run on a thin slab)."""
+    h = 1.0 / n
+    return base_config((n, n, nz), lo=(-0.5, -0.5, -0.5 * nz * h), hi=(0.5, 0.5, 0.5 * nz * h),
+                       gamma=gamma, G=G, bc=bc)
+
+
+def _cold_trace(like):
+    """Stars / dark matter as a cold, static trace (these tests are gas only)."""
+    zero = torch.zeros_like(like)
+    tiny = torch.full_like(like, 1e-6)
+    return tiny, [zero] * 3, [tiny * 1e-3, zero, zero, tiny * 1e-3, zero, tiny * 1e-3]
+
+
+def kelvin_helmholtz(n=128, nz=4, device="cpu", gamma=1.4):
+    """Kelvin-Helmholtz instability of Sec. 4.4 on [-0.5, 0.5]^2, periodic on
+    every axis, gamma = 1.4, p = 2.5, no gravity.  v_x = 0.5 in the band
+    |y| <= 0.25 and -0.5 outside; v_y = A(y) (1 + cos 8 pi x)(1 + cos 8 pi y)
+    with A = 0.01 where ||y| - 0.25| <= 0.01, else 0.  The printed density
+    repeats the Rayleigh-Taylor one with a garbled argument; the reading is
+    density 2 in the band and 1 outside."""
+    cfg = _plane_config(n, nz, gamma, (1, 1, 1))
+    X, Y, _ = cell_centres(cfg, device)
+    band = Y.abs() <= 0.25
+    one = torch.ones_like(X)
+    rho = torch.where(band, 2.0 * one, one)
+    vx = torch.where(band, 0.5 * one, -0.5 * one)
+    A = torch.where(((Y.abs() - 0.25).abs() <= 0.01), 0.01 * one, 0.0 * one)
+    vy = A * (1.0 + torch.cos(8.0 * math.pi * X)) * (1.0 + torch.cos(8.0 * math.pi * Y))
+    nb, u, Pi = _cold_trace(X)
+    return cfg, assemble(rho, [vx, vy, torch.zeros_like(X)], 2.5 * one, nb, u, Pi, gamma)
+
+
+def rayleigh_taylor(n=128, nz=4, device="cpu", gamma=1.4, g=0.1):
+    """Rayleigh-Taylor instability of Sec. 4.4 on [-0.5, 0.5]^2, gamma = 1.4:
+    density 1 for y <= 0 and 2 above, the hydrostatic pressure
+    p = 2.5 - rho g y under a uniform downward gravity g (not printed; the
+    reading is 0.1), v_y = A(y) (1 + cos 2 pi x)(1 + cos 2 pi y) with A = 0.01
+    where |y| <= 0.01, else 0.  Periodic in x and z, outflow in y, no
+    self-gravity; the field enters as the external acceleration (0, -g, 0)."""
+    cfg = _plane_config(n, nz, gamma, (1, 0, 1))
+    cfg["gext"] = (0.0, -g, 0.0)
+    X, Y, _ = cell_centres(cfg, device)
+    one = torch.ones_like(X)
+    rho = torch.where(Y <= 0.0, one, 2.0 * one)
+    p = 2.5 - rho * g * Y
+    A = torch.where(Y.abs() <= 0.01, 0.01 * one, 0.0 * one)
+    vy = A * (1.0 + torch.cos(2.0 * math.pi * X)) * (1.0 + torch.cos(2.0 * math.pi * Y))
+    zero = torch.zeros_like(X)
+    nb, u, Pi = _cold_trace(X)
+    return cfg, assemble(rho, [zero, vy, zero], p, nb, u, Pi, gamma)
+
+
+def sphere_profile(r):
+    """The hydrostatic gas sphere of Sec. 4.5 (G = 1): density 1 - r,
+    pressure p0(r) and potential Phi0(r) inside r <= 1; 0, 0 and -pi / (3 r)
+    outside."""
+    inside = r <= 1.0
+    zero = torch.zeros_like(r)
+    rho = torch.where(inside, 1.0 - r, zero)
+    p = torch.where(inside, -(math.pi * r * r / 36.0) * (9 * r * r - 28 * r + 24) + 5 * math.pi / 36.0, zero)
+    phi = torch.where(inside, -(math.pi / 3.0) * (r ** 3 - 2 * r * r) - 2 * math.pi / 3.0,
+                      -math.pi / (3.0 * r.clamp(min=1e-12)))
+    return rho, p, phi
+
+
+def cloud_collision(n=(96, 64, 64), device="cpu", L0=2.4, v_collide=1.0, floor=1e-3, poisson="isolated",
+                    precision="fp64"):
+    """The author's cloud collision of Sec. 4.5: two hydrostatic spheres
+    (density 1 - r, pressure p0(r); G = 1) whose centres start L0 = 2.4 apart
+    on the x axis and close at v_collide = 1 (each moving at 1/2).  Reading:
+    domain [-2.4, 2.4] x [-1.6, 1.6]^2 (cubic cells for the default n),
+    gamma = 5/3, density and pressure floored outside the spheres (1e-3 and
+    1e-4), isolated potential; the stars / dark matter are a cold static
+    trace.  The setup is mirror-symmetric in x."""
+    h = 4.8 / n[0]
+    cfg = base_config(n, lo=(-2.4, -0.5 * n[1] * h, -0.5 * n[2] * h), hi=(2.4, 0.5 * n[1] * h, 0.5 * n[2] * h),
+                      G=1.0, poisson=poisson, precision=precision)
+    X, Y, Z = cell_centres(cfg, device)
+    rho = torch.zeros_like(X)
+    p = torch.zeros_like(X)
+    mom = torch.zeros_like(X)
+    for cx, vx in ((-0.5 * L0, 0.5 * v_collide), (0.5 * L0, -0.5 * v_collide)):
+        r = torch.sqrt((X - cx) ** 2 + Y * Y + Z * Z)
+        rs, ps, _ = sphere_profile(r)
+        rho = rho + rs
+        p = p + ps
+        mom = mom + rs * vx
+    rho = rho.clamp(min=floor)
+    vx = mom / rho
+    p = p.clamp(min=floor * 0.1)
+    zero = torch.zeros_like(X)
+    nb, u, Pi = _cold_trace(X)
+    return cfg, assemble(rho, [vx, zero, zero], p, nb, u, Pi, cfg["gamma"])
+
+
 def to_numpy(state):
     return {k: v.detach().cpu().numpy() for k, v in state.items()}
