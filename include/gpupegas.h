@@ -276,6 +276,30 @@ const char *gp_batch_last_error(const gp_batch *b);
  * per-kernel split.  kernel = GP_K_* or -1 for the whole step. */
 double gp_algorithmic_bytes_per_cell(const gp_sim *sim, int32_t kernel);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * periodic potential gp_get_potential returns (the same Poisson kernels), of
+ * densities the caller holds, with no device allocation and no sim.
+ *   cfg      grid (n, lo, hi; cubic cells), G != 0, precision (the type of
+ *            phi: double for GP_FP64, float for GP_FP32), poisson must be
+ *            GP_POISSON_PERIODIC; the other fields are not used.
+ *   rho, n   device pointers, nx*ny*nz FP64 values each, x fastest (read).
+ *   phi      device pointer, nx*ny*nz values of the working type (written).
+ *   hip_stream  a hipStream_t, or NULL for the null stream; the call only
+ *            enqueues kernels there (no copy, memset or host wait), so it can
+ *            be captured.  The caller owns every buffer.
+ * The spectrum, tables and partial sums live in a fixed workspace of 64 MiB
+ * per GPU (a static device array, held until the process ends): grids whose
+ * workspace exceeds it -- about px ny nz complex values plus small tables,
+ * px = nx/2 + 1: cubic grids up to 192^3 in FP64 or 216^3 in FP32 -- return
+ * GP_E_UNSUPPORTED before anything is enqueued, as do isolated boundaries
+ * and FFT lengths other than even 2^a 3^b.  GP_E_INVALID for NULL pointers
+ * or a bad config; GP_E_HIP for a launch failure.  All calls on one GPU share
+ * its workspace: calls that overlap there (other streams or host threads)
+ * race; calls ordered on one stream do not. */
+gp_status gp_potential_noalloc(const gp_config *cfg, const double *rho, const double *n, void *phi,
+                               void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

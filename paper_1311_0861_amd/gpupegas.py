@@ -116,6 +116,7 @@ def _load():
         "gp_batch_algorithmic_bytes_per_cell": ([vp, i32], dbl),
         "gp_batch_cells": ([vp], i64),
         "gp_batch_last_error": ([vp], ctypes.c_char_p),
+        "gp_potential_noalloc": ([ctypes.POINTER(gp_config), vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -200,6 +201,20 @@ def gp_get_potential(sim, dst):
     p, code, dev = _buffer(dst)
     _check(sim, lib.gp_get_potential(sim, p, code, dev))
     return dst
+
+
+def gp_potential_noalloc(cfg, rho, n, phi, stream=None):
+    """Periodic potential of the device densities rho and n (FP64) into the
+    device buffer phi (the config's precision), with no device allocation;
+    enqueued on `stream` (a hipStream_t handle, None for the null stream)."""
+    c = cfg if isinstance(cfg, gp_config) else make_config(cfg)
+    (pr, cr, dr), (pn, cn, dn), (pp, cp, dp) = _buffer(rho), _buffer(n), _buffer(phi)
+    if not (dr and dn and dp):
+        raise ValueError("gp_potential_noalloc takes device buffers only")
+    if cr != GP_FP64 or cn != GP_FP64 or cp != c.precision:
+        raise ValueError("densities must be FP64 and phi of the config's precision")
+    _check(None, lib.gp_potential_noalloc(ctypes.byref(c), pr, pn, pp, stream))
+    return phi
 
 
 def gp_step(sim, nsteps=1):
