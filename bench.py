@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the FP32 (256^3, 512^3) and 48-run ensemble measurements")
     ap.add_argument("--form-steps", type=int, default=100, help="timed steps of the extra forms")
+    ap.add_argument("--only-form", choices=["fp32_512", "isolated_128", "batch48"], default=None,
+                    help="run only this extra form and print its record (for profiler runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run the library's plain copy kernel over MIB MiB of FP64 data "
                          "(calibrates HBM counters) and exit")
@@ -106,21 +108,40 @@ def library_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, n, precision, path=None):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (a line 'traffic: <kernel> <n> <precision> <bytes> <source hash>'), or
-    None when there is none for this kernel, size and library source."""
-    path = path or os.path.join(ROOT, "profiles", "hbm_traffic_two_disk_%d_%s.md" % (n, precision))
+def recorded_traffic(kernel, workload, path=None):
+    """HBM bytes per launch of `kernel` on `workload` (e.g. two_disk_128_fp64)
+    from the committed counter summary profiles/hbm_traffic_<workload>.md (a
+    line 'traffic: <kernel> <workload> <bytes> <source hash>'), or None when
+    there is none for this kernel, workload and library source."""
+    path = path or os.path.join(ROOT, "profiles", "hbm_traffic_%s.md" % workload)
     if not os.path.exists(path):
         return None
     want = library_source_hash()
     with open(path) as f:
         for line in f:
             parts = line.strip().strip("`").split()
-            if len(parts) == 6 and parts[0] == "traffic:" and parts[1] == kernel and parts[2] == str(n) \
-                    and parts[3] == precision and parts[5] == want:
-                return int(parts[4])
+            if len(parts) == 5 and parts[0] == "traffic:" and parts[1] == kernel and parts[2] == workload \
+                    and parts[4] == want:
+                return int(parts[3])
     return None
+
+
+def kernel_table(obj, kt, cells, workload):
+    """Per-kernel time, algorithmic GB/s and, where the counter summary for
+    this workload and source is committed, the measured HBM bytes per launch
+    and the GB/s they make."""
+    from paper_1311_0861_amd import gpupegas as gp
+    out = {}
+    for k, v in kt.items():
+        alg = obj.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * cells
+        row = {"ms": round(v, 5), "GB/s": round(alg / (v * 1e-3) / 1e9, 1) if v > 0 else None}
+        tr = recorded_traffic(k, workload)
+        if tr is not None and v > 0:
+            row["hbm_bytes"] = tr
+            row["hbm_GB/s"] = round(tr / (v * 1e-3) / 1e9, 1)
+            row["hbm_over_algorithmic"] = round(tr / alg, 3)
+        out[k] = row
+    return out
 
 
 def cpu_info():
@@ -237,10 +258,12 @@ def precision_forms(args):
         if prec == "fp32":
             drift = mass_drift(s.diag())
             sec = timed_steps(s, args.form_steps, 5)
+            kt = s.time_kernels(3)
             out["fp32_256"] = {"workload": "two-disk collision 256^3 FP32 (rho, n FP64)",
                                "value": round(256 ** 3 * args.form_steps / sec / 1e6, 2),
                                "unit": "Mcell-updates/s", "steps": args.form_steps,
-                               "mass_drift_100_steps": drift}
+                               "mass_drift_100_steps": drift,
+                               "kernels": kernel_table(s, kt, 256 ** 3, "two_disk_256_fp32")}
         else:
             sec = timed_steps(s, args.form_steps, 5)
             out["fp64_256"] = {"workload": "two-disk collision 256^3 FP64",
@@ -257,7 +280,14 @@ def precision_forms(args):
     out["fp32_256"]["rel_l1_max"] = max(err.values())
     del states
     torch.cuda.empty_cache()
+    return out
 
+
+def form_512(args):
+    """The FP32 three-disk collision at 512^3 with per-kernel bandwidth."""
+    import torch
+    from paper_1311_0861_amd import gpupegas as gp
+    from paper_1311_0861_amd import workloads as W
     cfg, st = W.three_disk_collision(512, device="cuda", precision="fp32")
     s = gp.Sim(cfg)
     s.set_state(st)
@@ -266,15 +296,14 @@ def precision_forms(args):
     sec = timed_steps(s, 50, 2)
     kt = s.time_kernels(3)
     n = 512 ** 3
-    out["fp32_512"] = {"workload": "three-disk collision 512^3 FP32 (rho, n FP64), 50 steps",
-                       "value": round(n * 50 / sec / 1e6, 2), "unit": "Mcell-updates/s",
-                       "mass_drift": mass_drift(s.diag()),
-                       "kernels": {k: {"ms": round(v, 4),
-                                       "GB/s": round(s.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * n / (v * 1e-3) / 1e9, 1)
-                                       if v > 0 else None} for k, v in kt.items()}}
+    out = {"workload": "three-disk collision 512^3 FP32 (rho, n FP64), 50 steps",
+           "value": round(n * 50 / sec / 1e6, 2), "unit": "Mcell-updates/s",
+           "mass_drift": mass_drift(s.diag()),
+           "kernels": kernel_table(s, kt, n, "three_disk_512_fp32")}
     s.close()
     torch.cuda.empty_cache()
     return out
+
 
 
 def isolated_form(args):
@@ -296,9 +325,7 @@ def isolated_form(args):
            "value": round(n * args.form_steps / sec / 1e6, 2), "unit": "Mcell-updates/s",
            "steps": args.form_steps, "ms_per_step": round(sec / args.form_steps * 1e3, 5),
            "poisson_ms": round(fft, 5), "mass_drift": mass_drift(s.diag()),
-           "kernels": {k: {"ms": round(v, 5),
-                           "GB/s": round(s.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * n / (v * 1e-3) / 1e9, 1)
-                           if v > 0 else None} for k, v in kt.items()}}
+           "kernels": kernel_table(s, kt, n, "two_disk_128_fp64_isolated")}
     s.close()
     torch.cuda.empty_cache()
     return out
@@ -322,9 +349,7 @@ def batch_form(args):
            "cells": cells, "value": round(cells * args.form_steps / sec / 1e6, 2), "unit": "Mcell-updates/s",
            "steps": args.form_steps,
            "launch": {k: b.get_launch(k) for k in gp.CELL_KERNELS},
-           "kernels": {k: {"ms": round(v, 4),
-                           "GB/s": round(b.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * cells / (v * 1e-3) / 1e9, 1)
-                           if v > 0 else None} for k, v in kt.items()}}
+           "kernels": kernel_table(b, kt, cells, "ensemble48_fp32")}
     b.close()
     torch.cuda.empty_cache()
     return out
@@ -347,6 +372,10 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.only_form:
+        fn = {"fp32_512": form_512, "isolated_128": isolated_form, "batch48": batch_form}[args.only_form]
+        print(json.dumps({"form": args.only_form, **fn(args)}), flush=True)
         return
     n = args.n
     cfg_cpu, st_cpu = W.two_disk_collision(n, device="cpu", precision=args.precision)
@@ -383,13 +412,12 @@ def main():
     kid = gp.KERNEL_NAMES.index(dom)
     bpc = sim.bytes_per_cell(kid)
     achieved = bpc * ncell / (kt[dom] * 1e-3) / 1e9
-    traffic = recorded_traffic(dom, n, args.precision, args.traffic)
+    workload = "two_disk_%d_%s" % (n, args.precision)
+    traffic = recorded_traffic(dom, workload, args.traffic)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernel_ms": round(kt[dom], 5), "bytes_per_cell": bpc}
-    kernels = {k: {"ms": round(v, 5),
-                   "GB/s": round(sim.bytes_per_cell(gp.KERNEL_NAMES.index(k)) * ncell / (v * 1e-3) / 1e9, 1)
-                   if v > 0 else None} for k, v in kt.items()}
+    kernels = kernel_table(sim, kt, ncell, workload)
     step_bytes = sim.bytes_per_cell(-1)
     launch = {k: sim.get_launch(k) for k in gp.CELL_KERNELS}
     sim.close()
@@ -419,6 +447,7 @@ def main():
     forms = None
     if not args.no_forms:
         forms = precision_forms(args)
+        forms["fp32_512"] = form_512(args)
         forms["isolated_128"] = isolated_form(args)
         forms["batch48"] = batch_form(args)
 
