@@ -108,6 +108,20 @@ typedef struct {
   int32_t precision; /* GP_FP64, or GP_FP32 (rho and n stay FP64; CFL, sums
                         and the Poisson zero mode stay FP64)                  */
   int32_t poisson;   /* GP_POISSON_PERIODIC (0) or GP_POISSON_ISOLATED        */
+  /* Cooling q of the gas energy equations (Sec. 2; applied in the Eulerian
+   * stage, Sec. 2.1, to rho E and rho eps alike, from the state at t^n).  The
+   * paper tabulates q (Sutherland and Dopita); this library takes the
+   * power-law stand-in q = cool_lambda rho^2 theta^cool_alpha for
+   * theta = p / rho > cool_theta_min, and q = 0 at or below it.
+   * cool_lambda = 0 switches cooling off.  The step is not limited by the
+   * cooling time: a tau q above rho eps latches GP_E_NONPOSITIVE. */
+  double cool_lambda;    /* >= 0                                               */
+  double cool_alpha;     /* any finite exponent                                */
+  double cool_theta_min; /* >= 0                                               */
+  /* Uniform external gravitational acceleration, added to the self-gravity
+   * -grad Phi in the Eulerian sources of both components (the free fall g of
+   * the Rayleigh-Taylor test of Sec. 4.4); zeros for none. */
+  double gext[3];
 } gp_config;
 
 /* One diagnostics record per step (and one for the initial state).  Sums are

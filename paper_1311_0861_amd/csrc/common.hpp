@@ -55,6 +55,8 @@ struct Grid {
 
 struct Phys {
   double gamma, G, cfl, eta, fixed_dt, t_end;
+  double cool_lambda, cool_alpha, cool_theta_min;  // cooling q = lambda rho^2 theta^alpha (theta = p / rho)
+  double gext[3];                                  // uniform external gravitational acceleration
 };
 
 // Scalars the step reads and writes on the device (no host round trip).

@@ -134,6 +134,7 @@ struct gp_batch {
   bool tuned = false;
   bool tune = true;
   int fft_form = GP_FFT_AUTO;
+  bool cooling = false;  // some run has a cooling source
   std::string last_error;
 };
 
@@ -185,6 +186,11 @@ gp_status validate(const gp_config* cfg) {
     if (std::fabs((cfg->hi[d] - cfg->lo[d]) / cfg->n[d] - h) > 1e-12 * h) return GP_E_INVALID;
   if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return GP_E_INVALID;
   if (cfg->poisson != GP_POISSON_PERIODIC && cfg->poisson != GP_POISSON_ISOLATED) return GP_E_INVALID;
+  if (!(cfg->cool_lambda >= 0.0) || !std::isfinite(cfg->cool_lambda) || !std::isfinite(cfg->cool_alpha) ||
+      !(cfg->cool_theta_min >= 0.0) || !std::isfinite(cfg->cool_theta_min))
+    return GP_E_INVALID;
+  for (int d = 0; d < 3; d++)
+    if (!std::isfinite(cfg->gext[d])) return GP_E_INVALID;
   if (cfg->precision != GP_FP64 && cfg->precision != GP_FP32) return GP_E_INVALID;
   if (cfg->G != 0.0)
     for (int d = 0; d < 3; d++) {
@@ -388,10 +394,10 @@ void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
   switch (k) {
     case GP_K_EUL_GAS:
-      launch_eulerian<T>(runs, b->work[1], b->nwork[1], b->parity, COMP_GAS, nblocks, b->st);
+      launch_eulerian<T>(runs, b->work[1], b->nwork[1], b->parity, COMP_GAS, b->cooling, nblocks, b->st);
       break;
     case GP_K_EUL_BME:
-      launch_eulerian<T>(runs, b->work[0], b->nwork[0], b->parity, COMP_BME, nblocks, b->st);
+      launch_eulerian<T>(runs, b->work[0], b->nwork[0], b->parity, COMP_BME, false, nblocks, b->st);
       break;
     case GP_K_LAG_GAS:
       launch_lagrangian<T>(runs, b->work[1], b->nwork[1], b->parity, b->partials, COMP_GAS, nblocks, b->st);
@@ -690,7 +696,17 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     R.g.h = (cfgs[r].hi[0] - cfgs[r].lo[0]) / cfgs[r].n[0];
     R.g.ncell = (size_t)R.g.nx * R.g.ny * R.g.nz;
     R.g.phi_iso = cfgs[r].poisson == GP_POISSON_ISOLATED ? 1 : 0;
-    R.ph = Phys{cfgs[r].gamma, cfgs[r].G, cfgs[r].cfl, cfgs[r].eta, cfgs[r].fixed_dt, cfgs[r].t_end};
+    R.ph = Phys{cfgs[r].gamma,
+                cfgs[r].G,
+                cfgs[r].cfl,
+                cfgs[r].eta,
+                cfgs[r].fixed_dt,
+                cfgs[r].t_end,
+                cfgs[r].cool_lambda,
+                cfgs[r].cool_alpha,
+                cfgs[r].cool_theta_min,
+                {cfgs[r].gext[0], cfgs[r].gext[1], cfgs[r].gext[2]}};
+    if (R.ph.cool_lambda != 0.0) b->cooling = true;
     R.ntx = (R.g.nx + kTX - 1) / kTX;
     R.nty = (R.g.ny + kTY - 1) / kTY;
     // partial rows: one per item of the longer of the run's two lists (each
@@ -1091,10 +1107,14 @@ double fft_bytes_per_cell(const gp_batch* b, int k) {
       continue;
     }
     const double spec = 2.0 * es * (R.g.nx / 2 + 1) / R.g.nx;
+    // the plane form does x and y in one pass; the line form reads and
+    // writes the spectrum once more between its x and y passes
+    const SizeClass& c = b->classes[R.cls];
+    const double xy = (c.fg.plane && b->fft_form == GP_FFT_AUTO) ? 1.0 : 3.0;
     double v = 0.0;
     switch (k) {
-      case GP_K_FFT_XY_FWD: v = 16.0 + spec; break;  // reads rho and n (FP64)
-      case GP_K_FFT_XY_INV: v = spec + es; break;
+      case GP_K_FFT_XY_FWD: v = 16.0 + xy * spec; break;  // reads rho and n (FP64)
+      case GP_K_FFT_XY_INV: v = xy * spec + es; break;
       case GP_K_FFT_Z: v = 2.0 * spec; break;
     }
     bytes += v * (double)R.g.ncell;

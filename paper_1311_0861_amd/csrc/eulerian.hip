@@ -174,7 +174,18 @@ __device__ __forceinline__ T phi_at(gptr<const T> phi, bool grav, size_t z, uint
   return grav ? ld_at(phi, z, xy) : T(0);
 }
 
+// Cooling rate of the energy equations (Sec. 2: the -q that Sec. 2.1 puts in
+// the Eulerian stage).  The paper tabulates q; the stand-in is the power law
+// q = lambda rho^2 theta^alpha of theta = p / rho above theta_min (0 below).
 template <typename T>
+__device__ __forceinline__ T cooling_rate(const Phys& ph, T rho, T theta) {
+  if (!(theta > (T)ph.cool_theta_min)) return T(0);
+  return (T)ph.cool_lambda * rho * rho * pow(theta, (T)ph.cool_alpha);
+}
+
+// COOL: the cooling source is compiled in (launched when a run of the batch
+// cools; runs with lambda = 0 skip it).
+template <typename T, bool COOL>
 __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict__ runs,
                                                     const WorkItem* __restrict__ work, unsigned nwork, int parity) {
   __shared__ T s_g[kGasPrims][kLY][kLX];
@@ -189,6 +200,8 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
     const Column col = make_column(g, R.ntx, it, false);
     const Column pc = make_phi_column(g, R.ntx, it);
     const bool grav = R.ph.G != 0.0;
+    const T gext[3] = {(T)R.ph.gext[0], (T)R.ph.gext[1], (T)R.ph.gext[2]};
+    const bool cool = COOL && R.ph.cool_lambda != 0.0;
     const size_t nxy = (size_t)g.nx * g.ny;
     const double tau_d = R.sc->dt;
     const T tau = (T)tau_d, r = (T)(tau_d / g.h), r2h = (T)(0.5 / g.h);
@@ -297,15 +310,24 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
           grad[1] = (s_phi[ly + 2][lx + 1] - s_phi[ly][lx + 1]) * r2h;
           grad[2] = (php - phm) * r2h;
         }
+        // a uniform external field adds to the self-gravity (exact when 0)
+#pragma unroll
+        for (int d = 0; d < 3; d++) grad[d] -= gext[d];
         // momentum slots receive v' = m' / rho
         const T irho = rcp(pc_[0]);
         const uint32_t xy = xy_c;
 #pragma unroll
         for (int d = 0; d < 3; d++)
           st_at(as_global((T*)R.tmp[oidx(GP_MX + d)]), zk, xy, (mc[d] - r * dP[d] - tau * pc_[0] * grad[d]) * irho);
-        st_at(as_global((T*)R.tmp[oidx(GP_E)]), zk, xy,
-              E - r * dPV - tau * (mc[0] * grad[0] + mc[1] * grad[1] + mc[2] * grad[2]));
-        st_at(as_global((T*)R.tmp[oidx(GP_EINT)]), zk, xy, ec - r * gm1 * ec * dV);
+        T Enew = E - r * dPV - tau * (mc[0] * grad[0] + mc[1] * grad[1] + mc[2] * grad[2]);
+        T enew = ec - r * gm1 * ec * dV;
+        if (cool) {
+          const T qc = cooling_rate<T>(R.ph, pc_[0], pc_[4] * irho);  // theta = p / rho
+          Enew -= tau * qc;
+          enew -= tau * qc;
+        }
+        st_at(as_global((T*)R.tmp[oidx(GP_E)]), zk, xy, Enew);
+        st_at(as_global((T*)R.tmp[oidx(GP_EINT)]), zk, xy, enew);
       }
       prims(rho_n, m_n, e_n, pc_);
 #pragma unroll
@@ -332,6 +354,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
     const Column col = make_column(g, R.ntx, it, false);
     const Column pc = make_phi_column(g, R.ntx, it);
     const bool grav = R.ph.G != 0.0;
+    const T gext[3] = {(T)R.ph.gext[0], (T)R.ph.gext[1], (T)R.ph.gext[2]};
     const size_t nxy = (size_t)g.nx * g.ny;
     const double tau_d = R.sc->dt;
     const T tau = (T)tau_d, r = (T)(tau_d / g.h), r2h = (T)(0.5 / g.h);
@@ -443,6 +466,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
           grad[1] = (s_phi[ly + 2][lx + 1] - s_phi[ly][lx + 1]) * r2h;
           grad[2] = (php - phm) * r2h;
         }
+        // a uniform external field adds to the self-gravity (exact when 0)
+#pragma unroll
+        for (int d = 0; d < 3; d++) grad[d] -= gext[d];
         // momentum slots receive u' = q' / n
         const T inb = rcp(C.n);
         const uint32_t xy = xy_c;
@@ -470,16 +496,18 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
 
 template <typename T>
 void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, int comp,
-                     unsigned nblocks, hipStream_t st) {
-  if (comp == COMP_GAS)
-    k_eul_gas<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+                     bool cool, unsigned nblocks, hipStream_t st) {
+  if (comp == COMP_GAS && cool)
+    k_eul_gas<T, true><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+  else if (comp == COMP_GAS)
+    k_eul_gas<T, false><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
   else
     k_eul_bme<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
 }
 
-template void launch_eulerian<double>(const RunDev<double>*, const WorkItem*, unsigned, int, int, unsigned,
+template void launch_eulerian<double>(const RunDev<double>*, const WorkItem*, unsigned, int, int, bool, unsigned,
                                       hipStream_t);
-template void launch_eulerian<float>(const RunDev<float>*, const WorkItem*, unsigned, int, int, unsigned,
+template void launch_eulerian<float>(const RunDev<float>*, const WorkItem*, unsigned, int, int, bool, unsigned,
                                      hipStream_t);
 
 }  // namespace gp

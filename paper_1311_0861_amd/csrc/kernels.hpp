@@ -11,7 +11,7 @@ namespace gp {
 // ---- Eulerian stage (comp = COMP_GAS or COMP_BME) --------------------------
 template <typename T>
 void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, int comp,
-                     unsigned nblocks, hipStream_t st);
+                     bool cool, unsigned nblocks, hipStream_t st);
 
 // ---- Lagrangian stage + energy balance + diagnostics partials -------------
 // New state of component comp into cur / dens[parity ^ 1], and that

@@ -45,6 +45,10 @@ class gp_config(ctypes.Structure):
         ("t_end", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("poisson", ctypes.c_int32),
+        ("cool_lambda", ctypes.c_double),
+        ("cool_alpha", ctypes.c_double),
+        ("cool_theta_min", ctypes.c_double),
+        ("gext", ctypes.c_double * 3),
     ]
 
 
@@ -138,7 +142,8 @@ def _check(sim, status, batch=False):
 
 def make_config(cfg):
     """gp_config from the workload dict (keys n, lo, hi, gamma, G, cfl, eta,
-    fixed_dt, t_end, bc, precision, poisson)."""
+    fixed_dt, t_end, bc, precision, poisson, cool_lambda, cool_alpha,
+    cool_theta_min, gext)."""
     c = gp_config()
     for d in range(3):
         c.n[d] = int(cfg["n"][d])
@@ -155,6 +160,11 @@ def make_config(cfg):
     c.precision = GP_FP32 if prec in ("fp32", GP_FP32) else GP_FP64
     pois = cfg.get("poisson", "periodic")
     c.poisson = {"periodic": GP_POISSON_PERIODIC, "isolated": GP_POISSON_ISOLATED}.get(pois, pois)
+    c.cool_lambda = float(cfg.get("cool_lambda", 0.0))
+    c.cool_alpha = float(cfg.get("cool_alpha", 0.0))
+    c.cool_theta_min = float(cfg.get("cool_theta_min", 0.0))
+    for d in range(3):
+        c.gext[d] = float(cfg.get("gext", (0.0, 0.0, 0.0))[d])
     return c
 
 

@@ -44,14 +44,30 @@ def test_status_strings_without_gpu(lib):
     assert b"order" in lib.gp_status_str(-7)
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and the size of gp_config and gp_diag, as a C
+    compiler lays them out from the header, equal the binding's."""
     from paper_1311_0861_amd import gpupegas as gp
-    # gp_config: 6 int32 + 6 double + 6 double + 2 int32 = 24 + 96 + 8
-    assert ctypes.sizeof(gp.gp_config) == 128
-    assert gp.gp_config.lo.offset == 24 and gp.gp_config.precision.offset == 120
-    # gp_diag: int64 + 16 doubles + 2 uint32
-    assert ctypes.sizeof(gp.gp_diag) == 8 + 16 * 8 + 8
-    assert gp.gp_diag.err.offset == 136
+    prog = ['#include <stddef.h>', '#include <stdio.h>', '#include "gpupegas.h"', "int main(void) {"]
+    for st in (gp.gp_config, gp.gp_diag):
+        cname = st.__name__
+        prog.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for name, _ in st._fields_:
+            prog.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, name, cname, name))
+    prog += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for st in (gp.gp_config, gp.gp_diag):
+        cname = st.__name__
+        assert got[(cname, "size")] == ctypes.sizeof(st), cname
+        for name, _ in st._fields_:
+            assert got[(cname, name)] == getattr(st, name).offset, (cname, name)
     src = open(os.path.join(ROOT, "paper_1311_0861_amd", "csrc", "common.hpp")).read()
     assert "kDiagCap = 4096" in src
 
