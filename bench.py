@@ -126,6 +126,17 @@ def recorded_traffic(kernel, workload, path=None):
     return None
 
 
+def launch_table(obj):
+    """The autotuner's pick for each per-cell kernel: tile shape, z-chunk cap
+    (planes) and persistent workgroups."""
+    from paper_1311_0861_amd import gpupegas as gp
+    out = {}
+    for k in gp.CELL_KERNELS:
+        shape, cap = obj.get_tiling(k)
+        out[k] = {"tile": ("64x4", "32x8")[shape], "chunk_cap": cap, "workgroups": obj.get_launch(k)}
+    return out
+
+
 def kernel_table(obj, kt, cells, workload):
     """Per-kernel time, algorithmic GB/s and, where the counter summary for
     this workload and source is committed, the measured HBM bytes per launch
@@ -348,7 +359,7 @@ def batch_form(args):
     out = {"workload": "48 two-disk runs, sizes drawn from 64^3/96^3/128^3, FP32, one launch per stage",
            "cells": cells, "value": round(cells * args.form_steps / sec / 1e6, 2), "unit": "Mcell-updates/s",
            "steps": args.form_steps,
-           "launch": {k: b.get_launch(k) for k in gp.CELL_KERNELS},
+           "launch": launch_table(b),
            "kernels": kernel_table(b, kt, cells, "ensemble48_fp32")}
     b.close()
     torch.cuda.empty_cache()
@@ -419,7 +430,7 @@ def main():
                 "kernel_ms": round(kt[dom], 5), "bytes_per_cell": bpc}
     kernels = kernel_table(sim, kt, ncell, workload)
     step_bytes = sim.bytes_per_cell(-1)
-    launch = {k: sim.get_launch(k) for k in gp.CELL_KERNELS}
+    launch = launch_table(sim)
     sim.close()
 
     # ---- CPU oracle: reference run of the error figures, and the baseline -----

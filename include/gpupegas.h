@@ -236,13 +236,26 @@ gp_status gp_time_kernels(gp_sim *sim, int32_t nsteps, double *ms, int32_t max);
 /* Use a captured HIP graph per step (default on).  Results are identical. */
 gp_status gp_use_graph(gp_sim *sim, int32_t enable);
 
-/* Persistent grid size (workgroups) of a per-cell kernel (GP_K_EUL_GAS,
- * GP_K_EUL_BME, GP_K_LAG_GAS or GP_K_LAG_BME).  By default the first step times a few
- * candidates and keeps the fastest; gp_set_launch fixes the size instead
- * (0 = one workgroup per tile) and disables that tuning.  Results never
- * depend on the grid size. */
+/* Launch configuration of a per-cell kernel (GP_K_EUL_GAS, GP_K_EUL_BME,
+ * GP_K_LAG_GAS or GP_K_LAG_BME): the work is a list of (run, tile column,
+ * chunk of z planes) items walked by a persistent grid of workgroups.  The
+ * autotuner picks, during the first step, the tile shape (0: 64 x 4 cells,
+ * 1: 32 x 8), the z-chunk cap (16, 32 or 64 planes; an item reads the plane
+ * below and above its chunk as its z halo) and the grid size (one workgroup
+ * per item, or 8192 / 4096 / 2048 / 1024), each kernel by its own timing.
+ * With the environment variable GPUPEGAS_TUNE_CACHE naming a file when the
+ * sim is created, the picks are read from it (keyed by device architecture,
+ * precision, cooling and the grid sizes of the batch) instead of tuning, and
+ * written to it after tuning.  gp_set_launch fixes the grid size of the
+ * current tiling (0 = one workgroup per item), gp_set_tiling the tile shape
+ * and chunk cap (GP_E_INVALID for other values; GP_E_STATE between the
+ * stages of gp_debug_stage); either disables the tuning.  The state, the
+ * potential and the step never depend on them; the diagnostics sums are
+ * summed over the items, so they match to rounding across tilings. */
 gp_status gp_set_launch(gp_sim *sim, int32_t kernel, int32_t blocks);
 gp_status gp_get_launch(gp_sim *sim, int32_t kernel, int32_t *blocks);
+gp_status gp_set_tiling(gp_sim *sim, int32_t kernel, int32_t shape, int32_t cap_planes);
+gp_status gp_get_tiling(gp_sim *sim, int32_t kernel, int32_t *shape, int32_t *cap_planes);
 
 /* Form of the x and y transforms of the Poisson solve: GP_FFT_AUTO (one
  * workgroup per z plane and row parity wherever two such half planes of the
@@ -280,6 +293,8 @@ gp_status gp_batch_get_diag(gp_batch *b, int32_t run, gp_diag *out, int32_t max,
 gp_status gp_batch_time_kernels(gp_batch *b, int32_t nsteps, double *ms, int32_t max);
 gp_status gp_batch_set_launch(gp_batch *b, int32_t kernel, int32_t blocks);
 gp_status gp_batch_get_launch(gp_batch *b, int32_t kernel, int32_t *blocks);
+gp_status gp_batch_set_tiling(gp_batch *b, int32_t kernel, int32_t shape, int32_t cap_planes);
+gp_status gp_batch_get_tiling(gp_batch *b, int32_t kernel, int32_t *shape, int32_t *cap_planes);
 gp_status gp_batch_set_fft_form(gp_batch *b, int32_t form);
 double gp_batch_algorithmic_bytes_per_cell(const gp_batch *b, int32_t kernel);
 int64_t gp_batch_cells(const gp_batch *b);  /* total cells over all runs */

@@ -1,19 +1,17 @@
 // Tile-column geometry shared by the Eulerian and Lagrangian kernels.
 //
-// A column work item is a 64 x 4 tile of cells and a chunk of z planes; the
-// workgroup walks the planes in order.  For plane k it keeps the tile of each
-// field it needs, with a one-cell ring of x / y neighbours, in LDS (kLY x kLX
-// values, the tile at rows / columns 1..kTY / 1..kTX); z neighbours are held
-// in registers.  Each lane owns the cell of its (threadIdx.x, threadIdx.y);
-// the first kRing lanes of the workgroup also fetch one ring cell each.
+// A column work item is a TX x TY tile of cells (a TileShape) and a chunk of
+// z planes; the workgroup walks the planes in order.  For plane k it keeps
+// the tile of each field it needs, with a one-cell ring of x / y neighbours,
+// in LDS (LY x LX values, the tile at rows / columns 1..TY / 1..TX); z
+// neighbours are held in registers.  Each lane owns the cell of its
+// (threadIdx.x, threadIdx.y); the first RING lanes of the workgroup also
+// fetch one ring cell each.
 #pragma once
 
 #include "common.hpp"
 
 namespace gp {
-
-constexpr int kLX = kTX + 2, kLY = kTY + 2;  // plane tile with its neighbour ring
-constexpr int kRing = 2 * kLX + 2 * kTY;     // ring cells of a plane tile
 
 // Source cell of tile position x under a boundary rule: the rule itself on
 // the one-cell ring outside the grid (x = -1 or x = n); positions further out
@@ -33,13 +31,13 @@ struct Column {
   uint32_t xy_h;       // its in-plane offset
 };
 
-// Geometry of a work item of a run with ntx tiles along x.  periodic = true
-// takes the periodic rule on x and y (the potential) instead of the
-// hydrodynamic one.
-__device__ __forceinline__ Column make_column(const Grid& g, int ntx, const WorkItem& it, bool periodic) {
+// Geometry of a work item for tile shape S.  periodic = true takes the
+// periodic rule on x and y (the potential) instead of the hydrodynamic one.
+template <class S>
+__device__ __forceinline__ Column make_column(const Grid& g, const WorkItem& it, bool periodic) {
   Column c;
-  c.i0 = (it.col % ntx) * kTX;
-  c.j0 = (it.col / ntx) * kTY;
+  c.i0 = it.i0;
+  c.j0 = it.j0;
   c.k0 = it.k0;
   c.k1 = it.k1;
   c.i = c.i0 + (int)threadIdx.x;
@@ -48,21 +46,21 @@ __device__ __forceinline__ Column make_column(const Grid& g, int ntx, const Work
   const int bx = periodic ? GP_BC_PERIODIC : g.bc[0], by = periodic ? GP_BC_PERIODIC : g.bc[1];
   const uint32_t nx = (uint32_t)g.nx;
   c.xy_c = (uint32_t)ring_src(c.i, g.nx, bx) + nx * (uint32_t)ring_src(c.j, g.ny, by);
-  // ring cells: rows -1 and kTY (kLX each), then columns -1 and kTX
-  const int tid = (int)threadIdx.x + kTX * (int)threadIdx.y;
-  c.ring = tid < kRing;
-  if (tid < kLX) {
+  // ring cells: rows -1 and TY (LX each), then columns -1 and TX
+  const int tid = (int)threadIdx.x + S::TX * (int)threadIdx.y;
+  c.ring = tid < S::RING;
+  if (tid < S::LX) {
     c.hr = 0;
     c.hc = tid;
-  } else if (tid < 2 * kLX) {
-    c.hr = kLY - 1;
-    c.hc = tid - kLX;
-  } else if (tid < 2 * kLX + kTY) {
-    c.hr = 1 + tid - 2 * kLX;
+  } else if (tid < 2 * S::LX) {
+    c.hr = S::LY - 1;
+    c.hc = tid - S::LX;
+  } else if (tid < 2 * S::LX + S::TY) {
+    c.hr = 1 + tid - 2 * S::LX;
     c.hc = 0;
   } else {
-    c.hr = 1 + min(tid - 2 * kLX - kTY, kTY - 1);
-    c.hc = kLX - 1;
+    c.hr = 1 + min(tid - 2 * S::LX - S::TY, S::TY - 1);
+    c.hc = S::LX - 1;
   }
   c.xy_h = (uint32_t)ring_src(c.i0 + c.hc - 1, g.nx, bx) + nx * (uint32_t)ring_src(c.j0 + c.hr - 1, g.ny, by);
   return c;
@@ -72,8 +70,9 @@ __device__ __forceinline__ Column make_column(const Grid& g, int ntx, const Work
 // axis.  Isolated: the grid and its one-cell ring, (nx+2)(ny+2)(nz+2) values
 // with cell i at index i + 1 on each axis; tile positions beyond the ring
 // (ragged edge tiles) are never read and take the ring's last cell.
-__device__ __forceinline__ Column make_phi_column(const Grid& g, int ntx, const WorkItem& it) {
-  Column c = make_column(g, ntx, it, true);
+template <class S>
+__device__ __forceinline__ Column make_phi_column(const Grid& g, const WorkItem& it) {
+  Column c = make_column<S>(g, it, true);
   if (g.phi_iso) {
     const uint32_t ex = (uint32_t)g.nx + 2;
     c.xy_c = (uint32_t)(min(c.i, g.nx) + 1) + ex * (uint32_t)(min(c.j, g.ny) + 1);

@@ -36,15 +36,6 @@ enum : uint32_t {
 // Index of a field other than rho / n inside the "other" array.
 __host__ __device__ constexpr int oidx(int field) { return field < GP_N ? field - 1 : field - 2; }
 
-// State pointer table.  rho and n are always FP64 (exact telescoping of the
-// mass flux in both precisions); the other 20 fields use the working type T.
-template <typename T>
-struct Fields {
-  __attribute__((address_space(1))) double* rho;
-  __attribute__((address_space(1))) double* nb;
-  __attribute__((address_space(1))) T* o[kNO];  // mx my mz E e | qx qy qz | Pxx..Pzz | Wxx..Wzz
-};
-
 struct Grid {
   int nx, ny, nz;
   int bc[3];    // GP_BC_OUTFLOW / GP_BC_PERIODIC
@@ -82,12 +73,23 @@ __device__ __forceinline__ int bc_index(int i, int n, int bc) {
 }
 __device__ __forceinline__ int wrap_index(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Per-cell kernels work on 64 x 4 tiles of an x-y plane (one thread per cell,
-// a wave covers 64 consecutive x cells); a tile index runs x fastest, then y,
-// then z.
-constexpr int kTX = 64;
-constexpr int kTY = 4;
-constexpr int kBlock = kTX * kTY;
+// Per-cell kernels work on TX x TY tiles of an x-y plane, one thread per
+// cell (kBlock threads; a wave covers 64 / TX rows of TX consecutive x
+// cells).  The shape is a template parameter of each per-cell kernel, picked
+// per kernel by the engine's autotuner among kNumShapes candidates.
+constexpr int kBlock = 256;
+template <int TX_, int TY_>
+struct TileShape {
+  static constexpr int TX = TX_, TY = TY_;
+  static constexpr int LX = TX + 2, LY = TY + 2;  // the tile with its one-cell ring
+  static constexpr int RING = 2 * LX + 2 * TY;    // ring cells of a plane tile
+  static_assert(TX * TY == kBlock && RING <= kBlock, "one thread per cell; one ring cell per thread at most");
+};
+constexpr int kNumShapes = 2;
+constexpr int kShapeTX[kNumShapes] = {64, 32};
+constexpr int kShapeTY[kNumShapes] = {4, 8};
+using Shape0 = TileShape<64, 4>;
+using Shape1 = TileShape<32, 8>;
 
 // Device descriptor of one run of a batch (a single simulation is a batch of
 // one).  rho and n alternate between dens[0] and dens[1] each step; "cur"
@@ -102,22 +104,22 @@ struct RunDev {
   T* phi;
   DevScalars* sc;
   unsigned row0;       // first row of this run in the partial-sum table
-  int ntx, nty;        // cell tiles along x and y
 };
 
-// One work item of a per-cell kernel: a 64 x 4 tile column (col = tx + ntx
-// ty) of one run over planes [k0, k1), whose partial sums go to partial row
+// One work item of a per-cell kernel: the tile column with origin (i0, j0)
+// of one run over planes [k0, k1), whose partial sums go to partial row
 // row0 + row of that run.
 struct WorkItem {
-  int run, col, k0, k1, row;
-  int pad[3];
+  int run, i0, j0, k0, k1, row;
+  int pad[2];
 };
 
 // The item of list slot w, with every field in scalar registers.
 __device__ __forceinline__ WorkItem load_item(const WorkItem* work, unsigned w) {
   WorkItem it;
   it.run = __builtin_amdgcn_readfirstlane(work[w].run);
-  it.col = __builtin_amdgcn_readfirstlane(work[w].col);
+  it.i0 = __builtin_amdgcn_readfirstlane(work[w].i0);
+  it.j0 = __builtin_amdgcn_readfirstlane(work[w].j0);
   it.k0 = __builtin_amdgcn_readfirstlane(work[w].k0);
   it.k1 = __builtin_amdgcn_readfirstlane(work[w].k1);
   it.row = __builtin_amdgcn_readfirstlane(work[w].row);
@@ -179,41 +181,6 @@ __device__ __forceinline__ gptr<T> as_global(T* p) {
   return (gptr<T>)p;
 }
 
-// Addresses of a cell's 7-point stencil.  A tile lies in one z plane, so the
-// planes it touches (k-1, k, k+1 under a boundary rule) are the same for the
-// whole wave; each lane keeps 32-bit in-plane element offsets.  A load is a
-// wave-uniform plane base (scalar registers) plus a 32-bit lane byte offset,
-// i.e. one global load with a scalar base and no 64-bit address arithmetic in
-// vector registers.  Point p: 0 centre, 1 / 2 minus / plus x, 3 / 4 minus /
-// plus y, 5 / 6 minus / plus z.
-struct Stencil {
-  size_t z[3];     // element offsets of planes k-1, k, k+1
-  uint32_t xy[5];  // in-plane offsets of the centre, x-1, x+1, y-1, y+1
-};
-
-// wrap = true applies the periodic rule on every axis (the potential),
-// otherwise each axis follows its hydrodynamic boundary condition.
-__device__ __forceinline__ Stencil make_stencil(const Grid& g, int i, int j, int k, bool wrap) {
-  Stencil s;
-  const size_t nxy = (size_t)g.nx * g.ny;
-  const uint32_t nx = (uint32_t)g.nx;
-  const int im = wrap ? wrap_index(i - 1, g.nx) : bc_index(i - 1, g.nx, g.bc[0]);
-  const int ip = wrap ? wrap_index(i + 1, g.nx) : bc_index(i + 1, g.nx, g.bc[0]);
-  const int jm = wrap ? wrap_index(j - 1, g.ny) : bc_index(j - 1, g.ny, g.bc[1]);
-  const int jp = wrap ? wrap_index(j + 1, g.ny) : bc_index(j + 1, g.ny, g.bc[1]);
-  const int km = wrap ? wrap_index(k - 1, g.nz) : bc_index(k - 1, g.nz, g.bc[2]);
-  const int kp = wrap ? wrap_index(k + 1, g.nz) : bc_index(k + 1, g.nz, g.bc[2]);
-  s.z[0] = nxy * (size_t)km;
-  s.z[1] = nxy * (size_t)k;
-  s.z[2] = nxy * (size_t)kp;
-  s.xy[0] = (uint32_t)i + nx * (uint32_t)j;
-  s.xy[1] = (uint32_t)im + nx * (uint32_t)j;
-  s.xy[2] = (uint32_t)ip + nx * (uint32_t)j;
-  s.xy[3] = (uint32_t)i + nx * (uint32_t)jm;
-  s.xy[4] = (uint32_t)i + nx * (uint32_t)jp;
-  return s;
-}
-
 // Element at plane offset z (uniform) and in-plane offset xy (per lane).
 template <typename E>
 __device__ __forceinline__ E ld_at(gptr<const E> base, size_t z, uint32_t xy) {
@@ -227,59 +194,6 @@ template <typename E>
 __device__ __forceinline__ void st_at(gptr<E> base, size_t z, uint32_t xy, E v) {
   const gptr<char> plane = (gptr<char>)(base + z);
   __builtin_nontemporal_store(v, (gptr<E>)(plane + xy * (uint32_t)sizeof(E)));
-}
-// Stencil point P (compile-time) of an array.
-template <int P, typename E>
-__device__ __forceinline__ E ld_pt(gptr<const E> base, const Stencil& s) {
-  if constexpr (P == 0) return ld_at(base, s.z[1], s.xy[0]);
-  if constexpr (P >= 1 && P <= 4) return ld_at(base, s.z[1], s.xy[P]);
-  if constexpr (P == 5) return ld_at(base, s.z[0], s.xy[0]);
-  return ld_at(base, s.z[2], s.xy[0]);
-}
-
-// Tile coordinates of a cell work item: lane (threadIdx.x, threadIdx.y) of
-// tile t covers cell (i, j) of plane k.
-struct TileCell {
-  int i, j, k;
-  bool inside;
-};
-template <typename R>
-__device__ __forceinline__ TileCell tile_cell(const R& run, int tile) {
-  TileCell c;
-  const int ntx = run.ntx, nty = run.nty;
-  c.i = (tile % ntx) * kTX + (int)threadIdx.x;
-  c.j = ((tile / ntx) % nty) * kTY + (int)threadIdx.y;
-  c.k = tile / (ntx * nty);
-  c.inside = c.i < run.g.nx && c.j < run.g.ny;
-  return c;
-}
-
-template <typename T>
-__device__ __forceinline__ Fields<T> fields_state(const RunDev<T>& R, int parity) {
-  Fields<T> f;
-  f.rho = as_global(R.dens[parity][0]);
-  f.nb = as_global(R.dens[parity][1]);
-#pragma unroll
-  for (int o = 0; o < kNO; o++) f.o[o] = as_global(R.cur[o]);
-  return f;
-}
-template <typename T>
-__device__ __forceinline__ Fields<T> fields_eul(const RunDev<T>& R) {
-  Fields<T> f;
-  f.rho = nullptr;
-  f.nb = nullptr;
-#pragma unroll
-  for (int o = 0; o < kNO; o++) f.o[o] = as_global(R.tmp[o]);
-  return f;
-}
-template <typename T>
-__device__ __forceinline__ Fields<T> fields_next(const RunDev<T>& R, int parity) {
-  Fields<T> f;
-  f.rho = as_global(R.dens[parity ^ 1][0]);
-  f.nb = as_global(R.dens[parity ^ 1][1]);
-#pragma unroll
-  for (int o = 0; o < kNO; o++) f.o[o] = as_global(R.cur[o]);
-  return f;
 }
 
 }  // namespace gp

@@ -25,8 +25,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -47,6 +51,19 @@ namespace {
 constexpr long kItemsFp64[2] = {512, 768};
 constexpr long kItemsFp32[2] = {512, 512};
 constexpr int kTunedKernels = 4;  // the per-cell kernels
+// z-chunk caps the autotuner tries (the "halo" shape of a work item): an item
+// of cz planes also reads the plane below and above it, 2 / cz of re-reads;
+// shorter chunks give more items to spread over the chip.
+constexpr int kNumCaps = 3;
+constexpr int kCaps[kNumCaps] = {16, 32, 64};
+constexpr int kDefaultCap = 1;  // 32 planes
+// Per-kernel launch configuration: tile shape (TileShape index), z-chunk cap
+// (index into kCaps) and persistent grid size.
+struct TileCfg {
+  int shape = 0;
+  int cap = kDefaultCap;
+  unsigned blocks = 0;
+};
 // Largest grid axis with isolated Poisson boundaries: a padded line of 2n
 // complex values (and an x row of n packed pairs with its bins) stays within
 // 64 KiB of LDS in FP64.
@@ -64,7 +81,6 @@ struct RunHost {
   DevScalars* sc = nullptr;
   gp_diag* ring = nullptr;
   unsigned row0 = 0, nrows = 0;
-  int ntx = 0, nty = 0;
   int cls = 0, slot = 0;  // size class and position inside it
 };
 
@@ -112,9 +128,10 @@ struct gp_batch {
   std::vector<std::pair<void*, size_t>> allocs;
 
   void* runs_dev = nullptr;  // RunDev<T>[nruns]
-  // work lists: [0] stars / DM kernels, [1] gas kernels
-  WorkItem* work[2] = {nullptr, nullptr};
-  unsigned nwork[2] = {0, 0};
+  // work lists [component list][tile shape][z-chunk cap]: list 0 for the
+  // stars / DM kernels, 1 for the gas kernels (their own item targets)
+  WorkItem* work[2][kNumShapes][kNumCaps] = {};
+  unsigned nwork[2][kNumShapes][kNumCaps] = {};
   double* partials = nullptr;
   RedItem* red_items = nullptr;
   int nred = 0;
@@ -130,9 +147,10 @@ struct gp_batch {
   bool use_graph = true;
   bool graph_ready[2] = {false, false};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  unsigned blocks[GP_NKERNELS] = {};
+  TileCfg kcfg[GP_NKERNELS];  // the per-cell kernels' configurations
   bool tuned = false;
   bool tune = true;
+  std::string cache_path;  // GPUPEGAS_TUNE_CACHE at create time (empty: none)
   int fft_form = GP_FFT_AUTO;
   bool cooling = false;  // some run has a cooling source
   std::string last_error;
@@ -355,115 +373,263 @@ void enqueue_finalize(gp_batch* b, int advanced, Timer* tm) {
   tdone(tm, GP_K_FINALIZE);
 }
 
-// Work lists.  A run's tile columns (64 x 4 tiles along z) are each cut into
-// about target / ncolumns chunks (rounded) of cz planes, cz clamped to 4..32,
-// so the list has about `target` items; list 0 (stars / DM kernels) and list
-// 1 (gas kernels) have their own target.  A workgroup walks its chunk plane by
-// plane, so short chunks re-read more planes at their ends, long ones leave
-// resident workgroup slots idle.  Items go x fastest, then y, then chunk: the
-// columns whose rings overlap run side by side on one XCD.  Item i of a run
-// writes partial row i.
-int chunk_planes(const RunHost& R, int prec, int list) {
+// Work lists.  For tile shape s a run has ntx x nty tile columns; each is
+// cut into about target / ncolumns chunks (rounded) of cz planes, cz clamped
+// to 4..cap, so the list has about `target` items; list 0 (stars / DM
+// kernels) and list 1 (gas kernels) have their own target.  A workgroup walks
+// its chunk plane by plane, so short chunks re-read more planes at their
+// ends, long ones leave resident workgroup slots idle.  Items go x fastest,
+// then y, then chunk: the columns whose rings overlap run side by side on one
+// XCD.  Item i of a run writes partial row i.
+int tiles_x(const RunHost& R, int s) { return (R.g.nx + kShapeTX[s] - 1) / kShapeTX[s]; }
+int tiles_y(const RunHost& R, int s) { return (R.g.ny + kShapeTY[s] - 1) / kShapeTY[s]; }
+int chunk_planes(const RunHost& R, int prec, int list, int s, int cap) {
   const long target = (prec == GP_FP64 ? kItemsFp64 : kItemsFp32)[list];
-  const long ncol = (long)R.ntx * R.nty;
+  const long ncol = (long)tiles_x(R, s) * tiles_y(R, s);
   const long nchunk = std::max(1L, (target + ncol / 2) / ncol);  // chunks per column, rounded
   const long cz = (R.g.nz + nchunk - 1) / nchunk;
-  return (int)std::max<long>(4, std::min<long>(32, cz));
+  return (int)std::max<long>(4, std::min<long>(kCaps[cap], cz));
 }
-unsigned items_per_run(const RunHost& R, int prec, int list) {
-  const int cz = chunk_planes(R, prec, list);
-  return (unsigned)(R.ntx * R.nty * ((R.g.nz + cz - 1) / cz));
+unsigned items_per_run(const RunHost& R, int prec, int list, int s, int cap) {
+  const int cz = chunk_planes(R, prec, list, s, cap);
+  return (unsigned)(tiles_x(R, s) * tiles_y(R, s) * ((R.g.nz + cz - 1) / cz));
 }
-void make_items(const RunHost& R, int run, int prec, int list, std::vector<WorkItem>& out) {
-  const int cz = chunk_planes(R, prec, list);
+void make_items(const RunHost& R, int run, int prec, int list, int s, int cap, std::vector<WorkItem>& out) {
+  const int cz = chunk_planes(R, prec, list, s, cap);
+  const int ntx = tiles_x(R, s), nty = tiles_y(R, s);
   int row = 0;
   for (int k0 = 0; k0 < R.g.nz; k0 += cz)
-    for (int col = 0; col < R.ntx * R.nty; col++) {
-      WorkItem it{};
-      it.run = run;
-      it.col = col;
-      it.k0 = k0;
-      it.k1 = std::min(k0 + cz, R.g.nz);
-      it.row = row++;
-      out.push_back(it);
-    }
+    for (int ty = 0; ty < nty; ty++)
+      for (int tx = 0; tx < ntx; tx++) {
+        WorkItem it{};
+        it.run = run;
+        it.i0 = tx * kShapeTX[s];
+        it.j0 = ty * kShapeTY[s];
+        it.k0 = k0;
+        it.k1 = std::min(k0 + cz, R.g.nz);
+        it.row = row++;
+        out.push_back(it);
+      }
 }
 
+int list_of(int k) { return (k == GP_K_EUL_GAS || k == GP_K_LAG_GAS) ? 1 : 0; }
+
+unsigned work_count(const gp_batch* b, int k, const TileCfg& c) { return b->nwork[list_of(k)][c.shape][c.cap]; }
+
 template <typename T>
-void launch_cell_kernel(gp_batch* b, int k, unsigned nblocks) {
+void launch_cell_kernel(gp_batch* b, int k, const TileCfg& c) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
+  const int l = list_of(k);
+  const WorkItem* w = b->work[l][c.shape][c.cap];
+  const unsigned nw = b->nwork[l][c.shape][c.cap];
   switch (k) {
     case GP_K_EUL_GAS:
-      launch_eulerian<T>(runs, b->work[1], b->nwork[1], b->parity, COMP_GAS, b->cooling, nblocks, b->st);
+      launch_eulerian<T>(runs, w, nw, b->parity, COMP_GAS, b->cooling, c.shape, c.blocks, b->st);
       break;
     case GP_K_EUL_BME:
-      launch_eulerian<T>(runs, b->work[0], b->nwork[0], b->parity, COMP_BME, false, nblocks, b->st);
+      launch_eulerian<T>(runs, w, nw, b->parity, COMP_BME, false, c.shape, c.blocks, b->st);
       break;
     case GP_K_LAG_GAS:
-      launch_lagrangian<T>(runs, b->work[1], b->nwork[1], b->parity, b->partials, COMP_GAS, nblocks, b->st);
+      launch_lagrangian<T>(runs, w, nw, b->parity, b->partials, COMP_GAS, c.shape, c.blocks, b->st);
       break;
     case GP_K_LAG_BME:
-      launch_lagrangian<T>(runs, b->work[0], b->nwork[0], b->parity, b->partials, COMP_BME, nblocks, b->st);
+      launch_lagrangian<T>(runs, w, nw, b->parity, b->partials, COMP_BME, c.shape, c.blocks, b->st);
       break;
   }
 }
 
-unsigned work_count(const gp_batch* b, int k) {
-  return (k == GP_K_EUL_GAS || k == GP_K_LAG_GAS) ? b->nwork[1] : b->nwork[0];
-}
-
-// Time the persistent grid-size candidates of kernel k and keep the fastest.
-// Every per-cell stage is idempotent with respect to its inputs (none of them
+// The autotuner.  Kernel k is timed (one warm launch, then five between HIP
+// events) in its default configuration (64 x 4 tiles, 32-plane chunk cap, a
+// workgroup per item), then for every other tile shape and chunk cap at a
+// workgroup per item, then for the fastest of those at the persistent grid
+// sizes 8192, 4096, 2048 and 1024 below that.  A candidate replaces the best
+// so far only when it is more than kTuneMargin faster: the candidates of a
+// grid differ by a few percent, about the spread of such short timings, and
+// the margin keeps noise from moving the pick off the default.  Every
+// per-cell stage is idempotent with respect to its inputs (none of them
 // writes what it reads), so re-running it during the first step changes
-// nothing but the timing.
+// nothing but the timing -- except the partial rows of the Lagrangian
+// kernels, which the caller clears after tuning them (a candidate list can be
+// longer than the chosen one).
+constexpr float kTuneMargin = 0.02f;
+
 template <typename T>
 void tune_kernel(gp_batch* b, int k) {
-  const unsigned nw = work_count(b, k);
-  std::vector<unsigned> cand = {nw};
-  for (unsigned c : {8192u, 4096u, 2048u, 1024u})
-    if (c < nw) cand.push_back(c);
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  float best = 1e30f;
-  unsigned pick = nw;
-  for (unsigned c : cand) {
+  auto time = [&](const TileCfg& c) {
     launch_cell_kernel<T>(b, k, c);  // warm
     (void)hipEventRecord(e0, b->st);
-    for (int rep = 0; rep < 3; rep++) launch_cell_kernel<T>(b, k, c);
+    for (int rep = 0; rep < 5; rep++) launch_cell_kernel<T>(b, k, c);
     (void)hipEventRecord(e1, b->st);
     (void)hipEventSynchronize(e1);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best) {
+    return ms;
+  };
+  TileCfg pick{};
+  pick.blocks = work_count(b, k, pick);
+  float best = time(pick);
+  auto consider = [&](const TileCfg& c) {
+    const float ms = time(c);
+    if (ms < best * (1.0f - kTuneMargin)) {
       best = ms;
       pick = c;
     }
+  };
+  for (int s = 0; s < kNumShapes; s++)
+    for (int cap = 0; cap < kNumCaps; cap++) {
+      TileCfg c{s, cap, 0};
+      if (s == 0 && cap == kDefaultCap) continue;  // timed first
+      c.blocks = work_count(b, k, c);
+      consider(c);
+    }
+  const unsigned nw = work_count(b, k, pick);
+  for (unsigned blocks : {8192u, 4096u, 2048u, 1024u}) {
+    if (blocks >= nw) continue;
+    TileCfg c = pick;
+    c.blocks = blocks;
+    consider(c);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->blocks[k] = pick;
+  b->kcfg[k] = pick;
+}
+
+// ---- tuning cache --------------------------------------------------------
+// With GPUPEGAS_TUNE_CACHE naming a file, the picked configurations are
+// stored there, one JSON member per kernel: "key": [shape, cap planes,
+// workgroups], the key naming the device architecture, the precision,
+// whether the gas cools, the multiset of grid sizes of the batch and the
+// kernel.  A batch whose four keys are all present takes them instead of
+// tuning.
+const char* kKernelKeys[GP_NKERNELS] = {"eul_gas", "eul_bme", "lag_gas", "lag_bme", "", "", "", ""};
+std::mutex g_cache_mu;
+
+std::string tune_key(const gp_batch* b, int k) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "gpu";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  std::map<std::string, int> sizes;
+  for (const RunHost& R : b->runs)
+    sizes[std::to_string(R.g.nx) + "x" + std::to_string(R.g.ny) + "x" + std::to_string(R.g.nz)]++;
+  std::string key = arch + "|" + (b->prec == GP_FP64 ? "fp64" : "fp32") + (b->cooling ? "|cool" : "") + "|";
+  bool first = true;
+  for (const auto& kv : sizes) {
+    key += (first ? "" : "+") + kv.first + "*" + std::to_string(kv.second);
+    first = false;
+  }
+  return key + "|" + kKernelKeys[k];
+}
+
+// "key": [a, b, c] members of the cache file
+std::map<std::string, std::vector<long>> read_cache(const std::string& path) {
+  std::map<std::string, std::vector<long>> out;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
+    const size_t b0 = line.find('[', q1), b1 = line.find(']', b0);
+    if (q0 == std::string::npos || q1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos)
+      continue;
+    std::string vals = line.substr(b0 + 1, b1 - b0 - 1);
+    for (char& ch : vals)
+      if (ch == ',') ch = ' ';
+    std::istringstream vs(vals);
+    std::vector<long> v;
+    long x;
+    while (vs >> x) v.push_back(x);
+    if (v.size() == 3) out[line.substr(q0 + 1, q1 - q0 - 1)] = v;
+  }
+  return out;
+}
+
+void write_cache(const gp_batch* b) {
+  if (b->cache_path.empty()) return;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto entries = read_cache(b->cache_path);
+  for (int k : kTunedIds) {
+    const TileCfg& c = b->kcfg[k];
+    entries[tune_key(b, k)] = {c.shape, kCaps[c.cap], (long)c.blocks};
+  }
+  const std::string tmp = b->cache_path + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    out << "{\n";
+    size_t i = 0;
+    for (const auto& kv : entries) {
+      out << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", " << kv.second[2] << "]"
+          << (++i < entries.size() ? "," : "") << "\n";
+    }
+    out << "}\n";
+    if (!out) return;
+  }
+  (void)std::rename(tmp.c_str(), b->cache_path.c_str());
+}
+
+// Takes the four kernels' configurations from the cache file when all are
+// there and valid for this batch.
+bool load_cache(gp_batch* b) {
+  if (b->cache_path.empty()) return false;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  const auto entries = read_cache(b->cache_path);
+  TileCfg got[GP_NKERNELS];
+  for (int k : kTunedIds) {
+    const auto it = entries.find(tune_key(b, k));
+    if (it == entries.end()) return false;
+    const std::vector<long>& v = it->second;
+    int cap = -1;
+    for (int q = 0; q < kNumCaps; q++)
+      if (kCaps[q] == v[1]) cap = q;
+    if (v[0] < 0 || v[0] >= kNumShapes || cap < 0 || v[2] < 1) return false;
+    got[k] = TileCfg{(int)v[0], cap, 0};
+    got[k].blocks = std::min<unsigned>((unsigned)v[2], work_count(b, k, got[k]));
+  }
+  for (int k : kTunedIds) b->kcfg[k] = got[k];
+  return true;
+}
+
+// Clears the partial rows: a list shorter than the one that last wrote them
+// would leave stale rows behind (never inside a captured graph).
+void clear_partials(gp_batch* b) {
+  size_t rows = 0;
+  for (const RunHost& R : b->runs) rows += R.nrows;
+  (void)hipMemsetAsync(b->partials, 0, rows * kNP * sizeof(double), b->st);
 }
 
 template <typename T>
 void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
+  const bool tuning = allow_tune && b->tune && !b->tuned;
   auto cell = [&](int k) {
-    if (allow_tune && b->tune && !b->tuned) tune_kernel<T>(b, k);
     const int reps = (tm && tm->on) ? tm->reps : 1;
     tmark(b, tm, k, 0);
-    for (int r = 0; r < reps; r++) launch_cell_kernel<T>(b, k, b->blocks[k]);
+    for (int r = 0; r < reps; r++) launch_cell_kernel<T>(b, k, b->kcfg[k]);
     tmark(b, tm, k, 1);
     tdone(tm, k, reps);
   };
   switch (stage) {
     case GP_STAGE_EUL:
+      if (tuning) {
+        tune_kernel<T>(b, GP_K_EUL_GAS);
+        tune_kernel<T>(b, GP_K_EUL_BME);
+      }
       cell(GP_K_EUL_GAS);
       cell(GP_K_EUL_BME);
       break;
     case GP_STAGE_LAG:
+      if (tuning) {
+        tune_kernel<T>(b, GP_K_LAG_GAS);
+        tune_kernel<T>(b, GP_K_LAG_BME);
+        clear_partials(b);
+      }
       cell(GP_K_LAG_GAS);
       cell(GP_K_LAG_BME);
-      if (allow_tune && b->tune) b->tuned = true;
+      if (tuning) {
+        b->tuned = true;
+        write_cache(b);
+      }
       b->parity ^= 1;
       break;
     case GP_STAGE_POISSON:
@@ -489,10 +655,13 @@ void enqueue_end(gp_batch* b, Timer* tm, int advanced) {
 template <typename T>
 void enqueue_prologue(gp_batch* b) {
   const auto* runs = static_cast<const RunDev<T>*>(b->runs_dev);
-  launch_init_partials<T>(runs, b->work[1], b->nwork[1], b->parity, b->partials, COMP_GAS, b->blocks[GP_K_LAG_GAS],
-                          b->st);
-  launch_init_partials<T>(runs, b->work[0], b->nwork[0], b->parity, b->partials, COMP_BME, b->blocks[GP_K_LAG_BME],
-                          b->st);
+  // the rows of the Lagrangian kernels' lists, in their tile shapes
+  for (int k : {GP_K_LAG_GAS, GP_K_LAG_BME}) {
+    const TileCfg& c = b->kcfg[k];
+    const int l = list_of(k);
+    launch_init_partials<T>(runs, b->work[l][c.shape][c.cap], b->nwork[l][c.shape][c.cap], b->parity, b->partials,
+                            k == GP_K_LAG_GAS ? COMP_GAS : COMP_BME, c.shape, c.blocks, b->st);
+  }
   enqueue_end<T>(b, nullptr, 0);
 }
 
@@ -603,8 +772,6 @@ RunDev<T> make_rundev(const RunHost& r) {
   d.phi = static_cast<T*>(r.phi);
   d.sc = r.sc;
   d.row0 = r.row0;
-  d.ntx = r.ntx;
-  d.nty = r.nty;
   return d;
 }
 
@@ -707,12 +874,14 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
                 cfgs[r].cool_theta_min,
                 {cfgs[r].gext[0], cfgs[r].gext[1], cfgs[r].gext[2]}};
     if (R.ph.cool_lambda != 0.0) b->cooling = true;
-    R.ntx = (R.g.nx + kTX - 1) / kTX;
-    R.nty = (R.g.ny + kTY - 1) / kTY;
     // partial rows: one per item of the longer of the run's two lists (each
     // component writes its own slots of rows 0.. of its list; the slots of
     // rows beyond a list stay zero, which the reductions ignore)
-    R.nrows = std::max(items_per_run(R, b->prec, 0), items_per_run(R, b->prec, 1));
+    R.nrows = 0;
+    for (int l = 0; l < 2; l++)
+      for (int s = 0; s < kNumShapes; s++)
+        for (int cap = 0; cap < kNumCaps; cap++)
+          R.nrows = std::max(R.nrows, items_per_run(R, b->prec, l, s, cap));
     R.row0 = row;
     row += R.nrows;
     const auto key = std::make_tuple(R.g.nx, R.g.ny, R.g.nz, R.g.h, R.ph.G, R.g.phi_iso);
@@ -799,13 +968,15 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   b->epot = static_cast<double*>(dalloc(b, std::max(1u, eoff) * sizeof(double), &st));
 
   // work lists, partial rows, reduction items, finalize descriptors
-  std::vector<WorkItem> lists[2];
+  std::vector<WorkItem> lists[2][kNumShapes][kNumCaps];
   std::vector<RedItem> items;
   std::vector<FinDesc> fins;
   unsigned soff = 0;
   for (int r = 0; r < nruns; r++) {
     RunHost& R = b->runs[r];
-    for (int l = 0; l < 2; l++) make_items(R, r, b->prec, l, lists[l]);
+    for (int l = 0; l < 2; l++)
+      for (int s = 0; s < kNumShapes; s++)
+        for (int cap = 0; cap < kNumCaps; cap++) make_items(R, r, b->prec, l, s, cap, lists[l][s][cap]);
     const unsigned nscr = std::max(1u, std::min(256u, R.nrows / 16));
     const unsigned chunk = (R.nrows + nscr - 1) / nscr;
     for (unsigned c = 0; c < nscr; c++) {
@@ -827,9 +998,14 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     fins.push_back(fd);
     soff += nscr;
   }
-  for (int l = 0; l < 2; l++) b->nwork[l] = (unsigned)lists[l].size();
   b->nred = (int)items.size();
-  for (int l = 0; l < 2; l++) b->work[l] = static_cast<WorkItem*>(dalloc(b, lists[l].size() * sizeof(WorkItem), &st));
+  for (int l = 0; l < 2; l++)
+    for (int s = 0; s < kNumShapes; s++)
+      for (int cap = 0; cap < kNumCaps; cap++) {
+        b->nwork[l][s][cap] = (unsigned)lists[l][s][cap].size();
+        b->work[l][s][cap] =
+            static_cast<WorkItem*>(dalloc(b, lists[l][s][cap].size() * sizeof(WorkItem), &st));
+      }
   b->partials = static_cast<double*>(dalloc(b, (size_t)row * kNP * sizeof(double), &st));
   b->red_items = static_cast<RedItem*>(dalloc(b, items.size() * sizeof(RedItem), &st));
   b->scratch = static_cast<double*>(dalloc(b, (size_t)soff * kNP * sizeof(double), &st));
@@ -844,7 +1020,10 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
   auto put = [&](void* dst, const void* src, size_t bytes) {
     if (e == hipSuccess) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
   };
-  for (int l = 0; l < 2; l++) put(b->work[l], lists[l].data(), lists[l].size() * sizeof(WorkItem));
+  for (int l = 0; l < 2; l++)
+    for (int s = 0; s < kNumShapes; s++)
+      for (int cap = 0; cap < kNumCaps; cap++)
+        put(b->work[l][s][cap], lists[l][s][cap].data(), lists[l][s][cap].size() * sizeof(WorkItem));
   put(b->red_items, items.data(), items.size() * sizeof(RedItem));
   put(b->fin, fins.data(), fins.size() * sizeof(FinDesc));
   if (b->prec == GP_FP64) {
@@ -906,8 +1085,13 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     const gp_status gs = iso_green_spectrum(b, c);
     if (gs != GP_OK) return gs;
   }
-  for (int k = 0; k < GP_NKERNELS; k++) b->blocks[k] = 0;
-  for (int k : kTunedIds) b->blocks[k] = work_count(b, k);
+  // untuned defaults: 64 x 4 tiles, 32-plane chunk cap, a workgroup per item
+  for (int k : kTunedIds) {
+    b->kcfg[k] = TileCfg{};
+    b->kcfg[k].blocks = work_count(b, k, b->kcfg[k]);
+  }
+  if (const char* path = std::getenv("GPUPEGAS_TUNE_CACHE")) b->cache_path = path;
+  if (load_cache(b)) b->tuned = true;
   return GP_OK;
 }
 
@@ -1070,15 +1254,44 @@ gp_status engine_set_fft_form(gp_batch* b, int32_t form) {
   return GP_OK;
 }
 
-gp_status engine_set_launch(gp_batch* b, int32_t kernel, int32_t blocks) {
-  int which = -1;
+bool tuned_kernel(int32_t kernel) {
   for (int q = 0; q < kTunedKernels; q++)
-    if (kTunedIds[q] == kernel) which = q;
-  if (which < 0 || blocks < 0) return GP_E_INVALID;
-  const unsigned nw = work_count(b, kernel);
-  b->blocks[kernel] = blocks == 0 ? nw : std::min<unsigned>((unsigned)blocks, nw);
+    if (kTunedIds[q] == kernel) return true;
+  return false;
+}
+
+gp_status engine_set_launch(gp_batch* b, int32_t kernel, int32_t blocks) {
+  if (!tuned_kernel(kernel) || blocks < 0) return GP_E_INVALID;
+  TileCfg& c = b->kcfg[kernel];
+  const unsigned nw = work_count(b, kernel, c);
+  c.blocks = blocks == 0 ? nw : std::min<unsigned>((unsigned)blocks, nw);
   b->tune = false;
   drop_graphs(b);
+  return GP_OK;
+}
+
+// Tile shape and z-chunk cap of a per-cell kernel (a workgroup per item).
+gp_status engine_set_tiling(gp_batch* b, int32_t kernel, int32_t shape, int32_t cap_planes) {
+  if (!tuned_kernel(kernel) || shape < 0 || shape >= kNumShapes) return GP_E_INVALID;
+  int cap = -1;
+  for (int q = 0; q < kNumCaps; q++)
+    if (kCaps[q] == cap_planes) cap = q;
+  if (cap < 0) return GP_E_INVALID;
+  if (b->next_stage != GP_STAGE_EUL) return GP_E_STATE;
+  TileCfg c{shape, cap, 0};
+  c.blocks = work_count(b, kernel, c);
+  b->kcfg[kernel] = c;
+  b->tune = false;
+  drop_graphs(b);
+  if (kernel == GP_K_LAG_GAS || kernel == GP_K_LAG_BME) clear_partials(b);
+  HIP_TRY(b, hipGetLastError());
+  return GP_OK;
+}
+
+gp_status engine_get_tiling(gp_batch* b, int32_t kernel, int32_t* shape, int32_t* cap_planes) {
+  if (!tuned_kernel(kernel) || !shape || !cap_planes) return GP_E_INVALID;
+  *shape = b->kcfg[kernel].shape;
+  *cap_planes = kCaps[b->kcfg[kernel].cap];
   return GP_OK;
 }
 
@@ -1278,8 +1491,18 @@ gp_status gp_set_fft_form(gp_sim* s, int32_t form) {
 
 gp_status gp_get_launch(gp_sim* s, int32_t kernel, int32_t* blocks) {
   if (!s || !blocks || kernel < 0 || kernel >= GP_NKERNELS) return GP_E_INVALID;
-  *blocks = (int32_t)s->blocks[kernel];
+  *blocks = (int32_t)s->kcfg[kernel].blocks;
   return GP_OK;
+}
+
+gp_status gp_set_tiling(gp_sim* s, int32_t kernel, int32_t shape, int32_t cap_planes) {
+  if (!s) return GP_E_INVALID;
+  return engine_set_tiling(s, kernel, shape, cap_planes);
+}
+
+gp_status gp_get_tiling(gp_sim* s, int32_t kernel, int32_t* shape, int32_t* cap_planes) {
+  if (!s) return GP_E_INVALID;
+  return engine_get_tiling(s, kernel, shape, cap_planes);
 }
 
 double gp_algorithmic_bytes_per_cell(const gp_sim* s, int32_t kernel) {
@@ -1359,8 +1582,18 @@ gp_status gp_batch_set_fft_form(gp_batch* b, int32_t form) {
 
 gp_status gp_batch_get_launch(gp_batch* b, int32_t kernel, int32_t* blocks) {
   if (!b || !blocks || kernel < 0 || kernel >= GP_NKERNELS) return GP_E_INVALID;
-  *blocks = (int32_t)b->blocks[kernel];
+  *blocks = (int32_t)b->kcfg[kernel].blocks;
   return GP_OK;
+}
+
+gp_status gp_batch_set_tiling(gp_batch* b, int32_t kernel, int32_t shape, int32_t cap_planes) {
+  if (!b) return GP_E_INVALID;
+  return engine_set_tiling(b, kernel, shape, cap_planes);
+}
+
+gp_status gp_batch_get_tiling(gp_batch* b, int32_t kernel, int32_t* shape, int32_t* cap_planes) {
+  if (!b) return GP_E_INVALID;
+  return engine_get_tiling(b, kernel, shape, cap_planes);
 }
 
 double gp_batch_algorithmic_bytes_per_cell(const gp_batch* b, int32_t kernel) {

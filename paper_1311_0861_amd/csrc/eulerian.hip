@@ -135,16 +135,16 @@ __device__ __forceinline__ void bme_face_add(const T us[3], const T ps[3], T sg,
 constexpr int kGasPrims = 5;
 constexpr int kBmePrims = 10;
 
-template <int D, typename T>
-__device__ __forceinline__ GasPrim<T> gas_at(const T (&t)[kGasPrims][kLY][kLX], int r, int c) {
+template <int D, typename T, int LY, int LX>
+__device__ __forceinline__ GasPrim<T> gas_at(const T (&t)[kGasPrims][LY][LX], int r, int c) {
   return GasPrim<T>{t[0][r][c], t[1 + D][r][c], t[4][r][c]};
 }
 template <int D, typename T>
 __device__ __forceinline__ GasPrim<T> gas_of(const T (&a)[kGasPrims]) {
   return GasPrim<T>{a[0], a[1 + D], a[4]};
 }
-template <int D, typename T>
-__device__ __forceinline__ BmeSide<T> bme_at(const T (&t)[kBmePrims][kLY][kLX], int r, int c) {
+template <int D, typename T, int LY, int LX>
+__device__ __forceinline__ BmeSide<T> bme_at(const T (&t)[kBmePrims][LY][LX], int r, int c) {
   BmeSide<T> o;
   o.n = t[0][r][c];
 #pragma unroll
@@ -185,11 +185,11 @@ __device__ __forceinline__ T cooling_rate(const Phys& ph, T rho, T theta) {
 
 // COOL: the cooling source is compiled in (launched when a run of the batch
 // cools; runs with lambda = 0 skip it).
-template <typename T, bool COOL>
+template <typename T, bool COOL, class S>
 __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict__ runs,
                                                     const WorkItem* __restrict__ work, unsigned nwork, int parity) {
-  __shared__ T s_g[kGasPrims][kLY][kLX];
-  __shared__ T s_phi[kLY][kLX];
+  __shared__ T s_g[kGasPrims][S::LY][S::LX];
+  __shared__ T s_phi[S::LY][S::LX];
   const int lx = threadIdx.x, ly = threadIdx.y;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
@@ -197,8 +197,8 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
     const int run = it.run;
     const RunDev<T>& R = runs[run];
     const Grid& g = R.g;
-    const Column col = make_column(g, R.ntx, it, false);
-    const Column pc = make_phi_column(g, R.ntx, it);
+    const Column col = make_column<S>(g, it, false);
+    const Column pc = make_phi_column<S>(g, it);
     const bool grav = R.ph.G != 0.0;
     const T gext[3] = {(T)R.ph.gext[0], (T)R.ph.gext[1], (T)R.ph.gext[2]};
     const bool cool = COOL && R.ph.cool_lambda != 0.0;
@@ -339,11 +339,11 @@ __global__ void __launch_bounds__(kBlock) k_eul_gas(const RunDev<T>* __restrict_
   }
 }
 
-template <typename T>
+template <typename T, class S>
 __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restrict__ runs,
                                                     const WorkItem* __restrict__ work, unsigned nwork, int parity) {
-  __shared__ T s_p[kBmePrims][kLY][kLX];
-  __shared__ T s_phi[kLY][kLX];
+  __shared__ T s_p[kBmePrims][S::LY][S::LX];
+  __shared__ T s_phi[S::LY][S::LX];
   const int lx = threadIdx.x, ly = threadIdx.y;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
@@ -351,8 +351,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
     const int run = it.run;
     const RunDev<T>& R = runs[run];
     const Grid& g = R.g;
-    const Column col = make_column(g, R.ntx, it, false);
-    const Column pc = make_phi_column(g, R.ntx, it);
+    const Column col = make_column<S>(g, it, false);
+    const Column pc = make_phi_column<S>(g, it);
     const bool grav = R.ph.G != 0.0;
     const T gext[3] = {(T)R.ph.gext[0], (T)R.ph.gext[1], (T)R.ph.gext[2]};
     const size_t nxy = (size_t)g.nx * g.ny;
@@ -494,20 +494,30 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
   }
 }
 
-template <typename T>
-void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, int comp,
-                     bool cool, unsigned nblocks, hipStream_t st) {
+template <typename T, class S>
+void launch_eulerian_shape(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, int comp,
+                           bool cool, unsigned nblocks, hipStream_t st) {
+  const dim3 blk(S::TX, S::TY, 1);
   if (comp == COMP_GAS && cool)
-    k_eul_gas<T, true><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+    k_eul_gas<T, true, S><<<nblocks, blk, 0, st>>>(runs, work, nwork, parity);
   else if (comp == COMP_GAS)
-    k_eul_gas<T, false><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+    k_eul_gas<T, false, S><<<nblocks, blk, 0, st>>>(runs, work, nwork, parity);
   else
-    k_eul_bme<T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity);
+    k_eul_bme<T, S><<<nblocks, blk, 0, st>>>(runs, work, nwork, parity);
 }
 
-template void launch_eulerian<double>(const RunDev<double>*, const WorkItem*, unsigned, int, int, bool, unsigned,
-                                      hipStream_t);
-template void launch_eulerian<float>(const RunDev<float>*, const WorkItem*, unsigned, int, int, bool, unsigned,
+template <typename T>
+void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, int comp,
+                     bool cool, int shape, unsigned nblocks, hipStream_t st) {
+  if (shape == 1)
+    launch_eulerian_shape<T, Shape1>(runs, work, nwork, parity, comp, cool, nblocks, st);
+  else
+    launch_eulerian_shape<T, Shape0>(runs, work, nwork, parity, comp, cool, nblocks, st);
+}
+
+template void launch_eulerian<double>(const RunDev<double>*, const WorkItem*, unsigned, int, int, bool, int,
+                                      unsigned, hipStream_t);
+template void launch_eulerian<float>(const RunDev<float>*, const WorkItem*, unsigned, int, int, bool, int, unsigned,
                                      hipStream_t);
 
 }  // namespace gp

@@ -6,24 +6,25 @@
 namespace gp {
 
 // All per-cell stages are persistent launches of `nblocks` workgroups over a
-// (run, tile) work list; runs[] are the device descriptors of the batch.
+// (run, tile column) work list made for tile shape `shape` (0: 64 x 4,
+// 1: 32 x 8; see TileShape); runs[] are the device descriptors of the batch.
 
 // ---- Eulerian stage (comp = COMP_GAS or COMP_BME) --------------------------
 template <typename T>
 void launch_eulerian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, int comp,
-                     bool cool, unsigned nblocks, hipStream_t st);
+                     bool cool, int shape, unsigned nblocks, hipStream_t st);
 
 // ---- Lagrangian stage + energy balance + diagnostics partials -------------
 // New state of component comp into cur / dens[parity ^ 1], and that
 // component's kNS slots of the partial row of each tile (row R.row0 + tile).
 template <typename T>
 void launch_lagrangian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, double* partials,
-                       int comp, unsigned nblocks, hipStream_t st);
+                       int comp, int shape, unsigned nblocks, hipStream_t st);
 // One component's partial rows of a state that has not been advanced
 // (prologue), over that component's Lagrangian work list.
 template <typename T>
 void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity,
-                          double* partials, int comp, unsigned nblocks, hipStream_t st);
+                          double* partials, int comp, int shape, unsigned nblocks, hipStream_t st);
 
 // ---- FFT Poisson ---------------------------------------------------------
 // Aligned to its size, so that a value moves in one 16-byte (FP64) or 8-byte

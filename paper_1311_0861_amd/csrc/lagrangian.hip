@@ -36,10 +36,9 @@ __device__ __forceinline__ void acc_init(Acc& a) {
 }
 
 // Fixed-order block reduction of one component's accumulators into its kNS
-// slots of a partial row.
-__device__ __forceinline__ void block_reduce_store(Acc& a, gptr<double> slots) {
+// slots of a partial row (tid = the thread's index in the workgroup).
+__device__ __forceinline__ void block_reduce_store(Acc& a, gptr<double> slots, int tid) {
   __shared__ double red[kBlock / 64][kNS];
-  const int tid = threadIdx.x + kTX * threadIdx.y;
   const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -219,9 +218,14 @@ __device__ __forceinline__ T advect7(const T x[7], const Weights<T>& w) {
 // coalesced rows, instead of 7 times through the cache hierarchy, and the
 // corner velocities never go to memory.
 
-constexpr int kVX = kTX + 1, kVY = kTY + 1;  // vertex tile of a cell tile
-constexpr int kVTile = 3 * kVX * kVY;        // corner values staged per vertex plane
-constexpr int kVPer = (kVTile + kBlock - 1) / kBlock;
+// vertex tile of a cell tile of shape S: corner values staged per vertex
+// plane, and per thread
+template <class S>
+struct Vertex {
+  static constexpr int VX = S::TX + 1, VY = S::TY + 1;
+  static constexpr int TILE = 3 * VX * VY;
+  static constexpr int PER = (TILE + kBlock - 1) / kBlock;
+};
 
 // Advected fields of a component (after the density), its corner velocity
 // components and density slot.
@@ -331,8 +335,8 @@ struct CellFlux {
 
 // Flux update of the field in tile slot t from its 7 post-Eulerian values
 // (x / y ring and centre from the LDS tile, z neighbours from registers).
-template <typename T, int NT>
-__device__ __forceinline__ T field_update(const T (&tile)[NT][kLY][kLX], int t, int lx, int ly, T zm, T zp,
+template <typename T, int NT, int LY, int LX>
+__device__ __forceinline__ T field_update(const T (&tile)[NT][LY][LX], int t, int lx, int ly, T zm, T zp,
                                           const CellFlux<T>& cf) {
   T x[7];
   x[0] = tile[t][ly + 1][lx + 1];
@@ -352,7 +356,7 @@ constexpr int lag_waves() {
   return C == COMP_GAS ? 3 : 2;
 }
 
-template <int C, typename T>
+template <int C, typename T, class S>
 __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const RunDev<T>* __restrict__ runs,
                                                                         const WorkItem* __restrict__ work,
                                                                         unsigned nwork, int parity,
@@ -360,17 +364,19 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
   using K = Comp<C>;
   constexpr int NF = K::kNF;
   constexpr int O0 = K::kFirst < GP_N ? K::kFirst - 1 : K::kFirst - 2;  // first "other" slot
+  constexpr int kLX = S::LX, kLY = S::LY;
+  constexpr int kVX = Vertex<S>::VX, kVY = Vertex<S>::VY, kVTile = Vertex<S>::TILE, kVPer = Vertex<S>::PER;
   __shared__ double s_dn[kLY][kLX];
   __shared__ T s_f[NF - 3][kLY][kLX];  // plane k of the fields after the velocities
   __shared__ T s_u[2][3][kLY][kLX];    // velocity tiles of planes k and k+1, alternating
   __shared__ T s_v[2][kVTile];        // corner velocities of vertex planes k and k+1
-  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + kTX * ly;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + S::TX * ly;
   const WorkRange wr = xcd_range(nwork);
   for (unsigned w = wr.first; w < wr.end; w += wr.stride) {
     const WorkItem it = load_item(work, w);
     const RunDev<T>& R = runs[it.run];
     const Grid& g = R.g;
-    const Column col = make_column(g, R.ntx, it, false);
+    const Column col = make_column<S>(g, it, false);
     const int k0 = col.k0, k1 = col.k1, i = col.i, j = col.j;
     const bool active = col.active, ring = col.ring;
     const int hr = col.hr, hc = col.hc;
@@ -628,7 +634,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
         fp[f] = fpp[f];
       }
     }
-    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + it.row) * kNP + C * kNS);
+    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + it.row) * kNP + C * kNS, tid);
   }
 }
 
@@ -663,7 +669,7 @@ __device__ __forceinline__ void init_cell(Acc& acc, const RunDev<T>& R, int pari
 
 // Partial rows of one component of a state that has not been advanced, over
 // the same items (and rows) as that component's Lagrangian kernel.
-template <int C, typename T>
+template <int C, typename T, class S>
 __global__ void __launch_bounds__(kBlock) k_init_partials(const RunDev<T>* __restrict__ runs,
                                                           const WorkItem* __restrict__ work, unsigned nwork,
                                                           int parity, double* __restrict__ partials) {
@@ -672,35 +678,50 @@ __global__ void __launch_bounds__(kBlock) k_init_partials(const RunDev<T>* __res
     const WorkItem it = load_item(work, w);
     const RunDev<T>& R = runs[it.run];
     const Grid& g = R.g;
-    const Column col = make_column(g, R.ntx, it, false);
+    const Column col = make_column<S>(g, it, false);
     Acc acc;
     acc_init(acc);
     if (col.active)
       for (int k = col.k0; k < col.k1; k++) init_cell<C, T>(acc, R, parity, (size_t)g.nx * g.ny * k, col.xy_c);
-    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + it.row) * kNP + C * kNS);
+    block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + it.row) * kNP + C * kNS,
+                       (int)threadIdx.x + S::TX * (int)threadIdx.y);
   }
+}
+
+template <typename T, class S>
+void launch_lagrangian_shape(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity,
+                             double* partials, int comp, bool init, unsigned nblocks, hipStream_t st) {
+  const dim3 blk(S::TX, S::TY, 1);
+  if (init && comp == COMP_GAS)
+    k_init_partials<COMP_GAS, T, S><<<nblocks, blk, 0, st>>>(runs, work, nwork, parity, partials);
+  else if (init)
+    k_init_partials<COMP_BME, T, S><<<nblocks, blk, 0, st>>>(runs, work, nwork, parity, partials);
+  else if (comp == COMP_GAS)
+    k_lagrangian<COMP_GAS, T, S><<<nblocks, blk, 0, st>>>(runs, work, nwork, parity, partials);
+  else
+    k_lagrangian<COMP_BME, T, S><<<nblocks, blk, 0, st>>>(runs, work, nwork, parity, partials);
 }
 
 template <typename T>
 void launch_lagrangian(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity, double* partials,
-                       int comp, unsigned nblocks, hipStream_t st) {
-  if (comp == COMP_GAS)
-    k_lagrangian<COMP_GAS, T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
+                       int comp, int shape, unsigned nblocks, hipStream_t st) {
+  if (shape == 1)
+    launch_lagrangian_shape<T, Shape1>(runs, work, nwork, parity, partials, comp, false, nblocks, st);
   else
-    k_lagrangian<COMP_BME, T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
+    launch_lagrangian_shape<T, Shape0>(runs, work, nwork, parity, partials, comp, false, nblocks, st);
 }
 template <typename T>
 void launch_init_partials(const RunDev<T>* runs, const WorkItem* work, unsigned nwork, int parity,
-                          double* partials, int comp, unsigned nblocks, hipStream_t st) {
-  if (comp == COMP_GAS)
-    k_init_partials<COMP_GAS, T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
+                          double* partials, int comp, int shape, unsigned nblocks, hipStream_t st) {
+  if (shape == 1)
+    launch_lagrangian_shape<T, Shape1>(runs, work, nwork, parity, partials, comp, true, nblocks, st);
   else
-    k_init_partials<COMP_BME, T><<<nblocks, dim3(kTX, kTY, 1), 0, st>>>(runs, work, nwork, parity, partials);
+    launch_lagrangian_shape<T, Shape0>(runs, work, nwork, parity, partials, comp, true, nblocks, st);
 }
 #define GP_INSTANTIATE(T)                                                                                  \
-  template void launch_lagrangian<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, int,        \
+  template void launch_lagrangian<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, int, int,   \
                                      unsigned, hipStream_t);                                                \
-  template void launch_init_partials<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, int,      \
+  template void launch_init_partials<T>(const RunDev<T>*, const WorkItem*, unsigned, int, double*, int, int, \
                                         unsigned, hipStream_t);
 GP_INSTANTIATE(double)
 GP_INSTANTIATE(float)

@@ -105,6 +105,10 @@ def _load():
         "gp_set_launch": ([vp, i32, i32], i32),
         "gp_get_launch": ([vp, i32, ctypes.POINTER(i32)], i32),
         "gp_set_fft_form": ([vp, i32], i32),
+        "gp_set_tiling": ([vp, i32, i32, i32], i32),
+        "gp_get_tiling": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "gp_batch_set_tiling": ([vp, i32, i32, i32], i32),
+        "gp_batch_get_tiling": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "gp_batch_create": ([ctypes.POINTER(gp_config), i32, vp, ctypes.POINTER(vp)], i32),
         "gp_batch_destroy": ([vp], i32),
         "gp_batch_set_field": ([vp, i32, i32, vp, i32, i32], i32),
@@ -284,6 +288,16 @@ def gp_get_launch(sim, kernel):
     return v.value
 
 
+def gp_set_tiling(sim, kernel, shape, cap_planes):
+    _check(sim, lib.gp_set_tiling(sim, int(kernel), int(shape), int(cap_planes)))
+
+
+def gp_get_tiling(sim, kernel):
+    s, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(sim, lib.gp_get_tiling(sim, int(kernel), ctypes.byref(s), ctypes.byref(c)))
+    return s.value, c.value
+
+
 def _diag_dicts(buf, n):
     out = []
     for r in buf[:n]:
@@ -354,6 +368,16 @@ def gp_batch_get_launch(b, kernel):
     v = ctypes.c_int32()
     _check(b, lib.gp_batch_get_launch(b, int(kernel), ctypes.byref(v)), True)
     return v.value
+
+
+def gp_batch_set_tiling(b, kernel, shape, cap_planes):
+    _check(b, lib.gp_batch_set_tiling(b, int(kernel), int(shape), int(cap_planes)), True)
+
+
+def gp_batch_get_tiling(b, kernel):
+    s, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(b, lib.gp_batch_get_tiling(b, int(kernel), ctypes.byref(s), ctypes.byref(c)), True)
+    return s.value, c.value
 
 
 def gp_batch_algorithmic_bytes_per_cell(b, kernel=-1):
@@ -448,6 +472,13 @@ class Sim:
     def get_launch(self, kernel):
         return gp_get_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel)
 
+    def set_tiling(self, kernel, shape, cap_planes):
+        gp_set_tiling(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel, shape, cap_planes)
+
+    def get_tiling(self, kernel):
+        """(tile shape: 0 = 64 x 4, 1 = 32 x 8; z-chunk cap in planes)"""
+        return gp_get_tiling(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel)
+
 
 class Batch:
     """An ensemble of independent runs advanced together (one precision)."""
@@ -520,6 +551,13 @@ class Batch:
 
     def get_launch(self, kernel):
         return gp_batch_get_launch(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel)
+
+    def set_tiling(self, kernel, shape, cap_planes):
+        gp_batch_set_tiling(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel, shape,
+                            cap_planes)
+
+    def get_tiling(self, kernel):
+        return gp_batch_get_tiling(self._h, KERNEL_NAMES.index(kernel) if isinstance(kernel, str) else kernel)
 
     def bytes_per_cell(self, kernel=-1):
         return gp_batch_algorithmic_bytes_per_cell(self._h, kernel)

@@ -3,11 +3,12 @@
 A batch advances independent runs of uneven grid sizes together (persistent
 per-stage launches over a (run, tile) work list, one FFT launch per grid size,
 graph-replayed steps).  Each member must equal the same run in its own sim
-bitwise, whatever persistent grid sizes are used."""
+bitwise, whatever persistent grid sizes and tilings are used; where whole
+diagnostics records are compared bitwise, both sides run the same tiling."""
 import numpy as np
 import pytest
 
-from gpu_helpers import FP32_SLAB_TOL, assert_close_fields, gpu_state, say
+from gpu_helpers import FP32_SLAB_TOL, assert_close_fields, gpu_state, pin_tiling, say
 
 pytestmark = pytest.mark.gpu
 
@@ -153,12 +154,14 @@ def test_same_size_runs_keep_their_potential_energy(gp, W):
     say("same-size runs, ny = 12")
     members = [W.random_periodic(n=(16, 12, 8), seed=s) for s in (21, 22)]
     b = gp.Batch([c for c, _ in members])
+    pin_tiling(b)
     for r, (_, st) in enumerate(members):
         b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
     b.step(3)
     b.sync()
     for r, (cfg, st) in enumerate(members):
         s = gp.Sim(cfg)
+        pin_tiling(s)
         s.set_state({k: v.to("cuda") for k, v in st.items()})
         s.step(3)
         s.sync()
@@ -182,12 +185,14 @@ def test_batch_mixing_fft_forms(gp, W):
     for cfg, _ in members:
         cfg["precision"] = "fp32"
     b = gp.Batch([c for c, _ in members])
+    pin_tiling(b)
     for r, (_, st) in enumerate(members):
         b.set_state(r, {k: v.to("cuda") for k, v in st.items()})
     b.step(3)
     b.sync()
     for r, (cfg, st) in enumerate(members):
         s = gp.Sim(cfg)
+        pin_tiling(s)
         s.set_state({k: v.to("cuda") for k, v in st.items()})
         s.step(3)
         s.sync()

@@ -8,7 +8,7 @@ forms on the GPU), so per-stage comparisons use 1e-12 and multi-step runs
 import numpy as np
 import pytest
 
-from gpu_helpers import FP32_SLAB_TOL, assert_close_fields, gpu_state, make_pair, rel_l1, say
+from gpu_helpers import FP32_SLAB_TOL, assert_close_fields, gpu_state, make_pair, pin_tiling, rel_l1, say
 
 pytestmark = pytest.mark.gpu
 
@@ -200,6 +200,7 @@ def test_stages_equal_step(gp, W):
     cfg, st = W.random_periodic(n=(16, 12, 8), seed=9)
     a, _ = make_pair(cfg, st)
     b, _ = make_pair(cfg, st)
+    pin_tiling(a)  # stage by stage runs the default tiling
     a.step(3)
     for _ in range(3):
         for stage in range(4):
@@ -226,9 +227,11 @@ def test_time_kernels_advances_like_step(gp, W):
     cfg, st = W.random_periodic(n=(16, 12, 8), seed=13)
     a, _ = make_pair(cfg, st)
     b, _ = make_pair(cfg, st)
+    pin_tiling(a)
+    pin_tiling(b)
     a.step(4)
     a.sync()
-    b.step(1)  # the first step also picks the launch sizes
+    b.step(1)
     kt = b.time_kernels(3)
     b.sync()
     assert set(kt) == set(gp.KERNEL_NAMES) and all(v >= 0.0 for v in kt.values())
