@@ -266,6 +266,11 @@ enum { GP_FFT_AUTO = 0, GP_FFT_LINES = 1 };
 gp_status gp_set_fft_form(gp_sim *sim, int32_t form);
 
 const char *gp_status_str(gp_status s);
+/* Text of the last error a sim recorded (HIP call and message, or the run
+ * whose configuration was refused).  With sim = NULL: why the calling
+ * thread's last failed gp_create or gp_batch_create failed.  The string is
+ * owned by the library and valid until the next call on the same sim (or,
+ * for NULL, the thread's next failed create). */
 const char *gp_last_error(const gp_sim *sim);
 
 /* ---- Ensembles --------------------------------------------------------------
@@ -298,7 +303,7 @@ gp_status gp_batch_get_tiling(gp_batch *b, int32_t kernel, int32_t *shape, int32
 gp_status gp_batch_set_fft_form(gp_batch *b, int32_t form);
 double gp_batch_algorithmic_bytes_per_cell(const gp_batch *b, int32_t kernel);
 int64_t gp_batch_cells(const gp_batch *b);  /* total cells over all runs */
-const char *gp_batch_last_error(const gp_batch *b);
+const char *gp_batch_last_error(const gp_batch *b);  /* b = NULL: as gp_last_error(NULL) */
 
 /* Bytes the kernels move per cell per step by design (reads + writes of the
  * state, potential and spectrum), for the roofline; see the source for the

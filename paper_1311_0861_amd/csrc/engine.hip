@@ -843,7 +843,8 @@ gp_status engine_create(gp_batch* b, const gp_config* cfgs, int nruns, void* hip
     b->st = static_cast<hipStream_t>(hip_stream);
   } else {
     // a blocking stream orders after work on the legacy default stream
-    if (hipStreamCreate(&b->st) != hipSuccess) return GP_E_HIP;
+    const hipError_t se = hipStreamCreate(&b->st);
+    if (se != hipSuccess) return hip_fail(b, se, "stream create");
     b->own_stream = true;
   }
   const size_t es = esize(b->prec);
@@ -1379,7 +1380,15 @@ const char* gp_status_str(gp_status s) {
 
 // ---- single simulation ------------------------------------------------------
 
-const char* gp_last_error(const gp_sim* sim) { return sim ? sim->last_error.c_str() : "null sim"; }
+// Why the calling thread's last gp_create / gp_batch_create failed (the
+// handle it would have returned no longer exists).
+thread_local std::string t_create_error;
+
+void note_create_error(const gp_batch* b, gp_status r) {
+  t_create_error = b->last_error.empty() ? std::string(gp_status_str(r)) : b->last_error;
+}
+
+const char* gp_last_error(const gp_sim* sim) { return sim ? sim->last_error.c_str() : t_create_error.c_str(); }
 
 gp_status gp_create(const gp_config* cfg, void* hip_stream, gp_sim** out) {
   if (!cfg || !out) return GP_E_INVALID;
@@ -1387,6 +1396,7 @@ gp_status gp_create(const gp_config* cfg, void* hip_stream, gp_sim** out) {
   gp_sim* s = new gp_sim();
   const gp_status r = engine_create(s, cfg, 1, hip_stream);
   if (r != GP_OK) {
+    note_create_error(s, r);
     engine_free(s);
     delete s;
     return r;
@@ -1517,6 +1527,7 @@ gp_status gp_batch_create(const gp_config* cfgs, int32_t nruns, void* hip_stream
   gp_batch* b = new gp_batch();
   const gp_status r = engine_create(b, cfgs, nruns, hip_stream);
   if (r != GP_OK) {
+    note_create_error(b, r);
     engine_free(b);
     delete b;
     return r;
@@ -1607,6 +1618,6 @@ int64_t gp_batch_cells(const gp_batch* b) {
   return n;
 }
 
-const char* gp_batch_last_error(const gp_batch* b) { return b ? b->last_error.c_str() : "null batch"; }
+const char* gp_batch_last_error(const gp_batch* b) { return b ? b->last_error.c_str() : t_create_error.c_str(); }
 
 }  // extern "C"

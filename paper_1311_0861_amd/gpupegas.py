@@ -81,6 +81,15 @@ class GpError(RuntimeError):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime under the same soname as ROCm's but
+    # asks for it by another file name.  Loaded first, it satisfies the
+    # library's dependency too, so the process holds one runtime; loaded
+    # after the library it would bring a second one, which then sees no
+    # device for the other.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError("libgpupegas.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
     L = ctypes.CDLL(LIB_PATH)
@@ -136,11 +145,13 @@ def _load():
 lib = _load()
 
 
-def _check(sim, status, batch=False):
+def _check(sim, status, batch=False, create=False):
     if status != GP_OK:
         detail = ""
         if sim:
             detail = (lib.gp_batch_last_error(sim) if batch else lib.gp_last_error(sim)).decode()
+        elif create:
+            detail = lib.gp_last_error(None).decode()
         raise GpError(status, lib.gp_status_str(status).decode() + (" (" + detail + ")" if detail else ""))
 
 
@@ -175,7 +186,7 @@ def make_config(cfg):
 def gp_create(cfg, stream=None):
     c = cfg if isinstance(cfg, gp_config) else make_config(cfg)
     h = ctypes.c_void_p()
-    _check(None, lib.gp_create(ctypes.byref(c), stream, ctypes.byref(h)))
+    _check(None, lib.gp_create(ctypes.byref(c), stream, ctypes.byref(h)), create=True)
     return h
 
 
@@ -310,7 +321,7 @@ def _diag_dicts(buf, n):
 def gp_batch_create(cfgs, stream=None):
     arr = (gp_config * len(cfgs))(*[c if isinstance(c, gp_config) else make_config(c) for c in cfgs])
     h = ctypes.c_void_p()
-    _check(None, lib.gp_batch_create(arr, len(cfgs), stream, ctypes.byref(h)))
+    _check(None, lib.gp_batch_create(arr, len(cfgs), stream, ctypes.byref(h)), create=True)
     return h
 
 

@@ -84,6 +84,33 @@ def test_null_and_bad_arguments_rejected(lib):
     assert lib.gp_destroy(None) == -1
 
 
+def test_create_failure_reason_without_gpu():
+    """A refused configuration is rejected before any HIP call, and
+    gp_last_error(NULL) then says why the calling thread's create failed."""
+    from paper_1311_0861_amd import gpupegas as gp
+    cfg = {"n": (16, 16, 16), "lo": (-1.0,) * 3, "hi": (1.0,) * 3, "gamma": 0.5}
+    with pytest.raises(gp.GpError, match="invalid configuration"):
+        gp.gp_create(cfg)
+    assert b"invalid configuration" in gp.lib.gp_last_error(None)
+    with pytest.raises(gp.GpError, match="run 1: invalid configuration"):
+        gp.gp_batch_create([dict(cfg, gamma=5.0 / 3.0), cfg])
+    assert gp.lib.gp_batch_last_error(None).startswith(b"run 1")
+
+
+def test_binding_shares_one_hip_runtime_with_torch():
+    """Importing the binding before torch still leaves a single HIP runtime
+    mapped in the process (two runtimes each claim the device)."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1311_0861_amd import gpupegas\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().split()\n"
+            "print(sorted({m for m in maps if 'libamdhip64' in m}))\n") % ROOT
+    out = subprocess.run(["python", "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
+
+
 def test_product_package_does_not_touch_oracle():
     """The GPU path never imports or links the oracle."""
     pkg = os.path.join(ROOT, "paper_1311_0861_amd")
