@@ -123,12 +123,16 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __rest
 // (ky and ky + ny/2), which hold E and O: it forms C[ky] = E + W^ky O and
 // C[ky + ny/2] = E - W^ky O before the z transforms, and stores e = C[ky] +
 // C[ky + ny/2] and o = (C[ky] - C[ky + ny/2]) W^-ky after them.
-template <typename T, int MODE>  // MODE 0: forward, 1: inverse, 2: forward * symbol * inverse
+// LC, CBC, NRC > 0 (z pass only): the transform length, the columns per row
+// and the rows per workgroup are compile-time constants (they must equal
+// ax.L, cb and 1 + pair), so that every index is derived from constants.
+template <typename T, int MODE, int LC = 0, int CBC = 0, int NRC = 0>  // MODE 0: forward, 1: inverse, 2: forward * symbol * inverse
 __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t,
-                                                         FftAxis ax, const cplx<T>* __restrict__ twg, int cb,
+                                                         FftAxis ax, const cplx<T>* __restrict__ twg, int cb_rt,
                                                          size_t stride, size_t outer_stride, int outer_div,
                                                          size_t run_stride, double* __restrict__ epot_partials,
                                                          RedJob red, int pair, size_t pair_stride) {
+  static_assert(LC == 0 || (MODE == 2 && CBC > 0 && NRC > 0), "compile-time shapes are for the z pass");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   int bid = (int)blockIdx.x, nblk = (int)gridDim.x;
   if constexpr (MODE == 2) {
@@ -142,12 +146,24 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
     nblk -= red.n;
   }
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int L = ax.L;
-  const int nr = (MODE == 2 && pair) ? 2 : 1;  // spectrum rows per workgroup
-  const int cw = nr * cb;                      // LDS columns: cb per row
+  const int L = LC ? LC : ax.L;
+  const int cb = CBC ? CBC : cb_rt;
+  const int nr = NRC ? NRC : ((MODE == 2 && pair) ? 2 : 1);  // spectrum rows per workgroup
+  const int cw = nr * cb;                                      // LDS columns: cb per row
   // LDS holds the block as L rows of cw columns: element j of column c at
   // j * cw + c, so that lanes on neighbouring columns touch neighbouring words
   cplx<T>* tw = lds + cw * L;
+  // the transforms along the columns of the block
+  auto transform = [&](bool inv) {
+    if constexpr (LC > 0) {
+      if (inv)
+        cfft<T, LC, CBC * NRC, kFftThreads, true>(lds, tw);
+      else
+        cfft<T, LC, CBC * NRC, kFftThreads, false>(lds, tw);
+    } else {
+      col_fft(lds, cw, ax, tw, inv);
+    }
+  };
   const int nchunks = (f.px + cb - 1) / cb;
   const ColBlock cbk = col_block(bid, nchunks, nblk / nchunks);
   const int chunk = cbk.chunk, oline = cbk.oline;
@@ -156,6 +172,25 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
   const int ncols = min(cb, f.px - kx0);
   load_twiddles<kFftThreads>(tw, twg, L);
   const FastDiv dcw(cw), dcb(cb);
+  // index split q -> (q / n, q % n) by a compile-time or a run-time divisor
+  auto split_cb = [&](int q, int& j, int& c) {
+    if constexpr (CBC > 0) {
+      j = q / CBC;
+      c = q % CBC;
+    } else {
+      j = (int)dcb.div(q);
+      c = q - j * cb;
+    }
+  };
+  auto split_cw = [&](int q, int& j, int& c) {
+    if constexpr (CBC > 0) {
+      j = q / (CBC * NRC);
+      c = q % (CBC * NRC);
+    } else {
+      j = (int)dcw.div(q);
+      c = q - j * cw;
+    }
+  };
   // z pass: the symbol's factors D(kz) and D(kx) D(ky) of this block
   double* gz = reinterpret_cast<double*>(tw + L);
   double* gxy = gz + L;
@@ -180,14 +215,16 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
     staged_copy<kFftThreads, 2, Pair>(
         cb * L,
         [&](int q) {
-          const int j = (int)dcb.div(q), cc = q - j * cb;
+          int j, cc;
+          split_cb(q, j, cc);
           const cplx<T>* g = base + (size_t)j * stride + min(cc, ncols - 1);
           Pair v{gload(g), gload(g + pair_stride)};
           if (cc >= ncols) v = Pair{{T(0), T(0)}, {T(0), T(0)}};
           return v;
         },
         [&](int q, Pair v) {
-          const int j = (int)dcb.div(q), cc = q - j * cb;
+          int j, cc;
+          split_cb(q, j, cc);
           const cplx<T> o = cmul(v.o, wk);
           lds[j * cw + cc] = cadd(v.e, o);
           lds[j * cw + cb + cc] = csub(v.e, o);
@@ -196,14 +233,15 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
     staged_copy<kFftThreads, 4, cplx<T>>(
         cw * L,
         [&](int q) {
-          const int j = (int)dcw.div(q), c = q - j * cw;
+          int j, c;
+          split_cw(q, j, c);
           const cplx<T> v = gload(base + (size_t)j * stride + min(c, ncols - 1));
           return (c < ncols) ? v : cplx<T>{T(0), T(0)};
         },
         [&](int q, cplx<T> v) { lds[q] = v; });
   }
   __syncthreads();
-  col_fft(lds, cw, ax, tw, MODE == 1);
+  transform(MODE == 1);
   if constexpr (MODE == 2) {
     // z pass: line position = kz, column = (row h, kx); the potential-energy
     // partial of each row goes to slot (line, chunk), so that a run's
@@ -211,7 +249,9 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
     __shared__ double red_ep[2][kFftThreads / 64];
     double ep[2] = {0.0, 0.0};
     for (int q = threadIdx.x; q < cw * L; q += kFftThreads) {
-      const int kz = (int)dcw.div(q), c = q - kz * cw, h = c >= cb ? 1 : 0, cc = c - h * cb;
+      int kz, c;
+      split_cw(q, kz, c);
+      const int h = c >= cb ? 1 : 0, cc = c - h * cb;
       if (cc >= ncols) continue;
       const int kx = kx0 + cc, ky = outer + h * outer_div;
       cplx<T>& v = lds[q];
@@ -237,12 +277,13 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
       const size_t line = (size_t)run * outer_div * nr + outer + h * outer_div;  // spectrum row of the run
       epot_partials[line * nchunks + chunk] = s;
     }
-    col_fft(lds, cw, ax, tw, true);
+    transform(true);
     if (nr == 2) {
       // e and o of one (z, kx) by one thread, formed on their way out
       const cplx<T> wc = {wk.x, -wk.y};
       for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
-        const int j = (int)dcb.div(q), cc = q - j * cb;
+        int j, cc;
+        split_cb(q, j, cc);
         if (cc >= ncols) continue;
         const cplx<T> c0 = lds[j * cw + cc], c1 = lds[j * cw + cb + cc];
         cplx<T>* g = base + (size_t)j * stride + cc;
@@ -253,7 +294,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
     }
   }
   for (int q = threadIdx.x; q < cw * L; q += kFftThreads) {
-    const int j = (int)dcw.div(q), c = q - j * cw;
+    int j, c;
+    split_cw(q, j, c);
     if (c < ncols) base[(size_t)j * stride + c] = lds[q];
   }
 }
@@ -458,7 +500,9 @@ FftGeom make_fft_geom(int nx, int ny, int nz, int nruns, int prec, bool planes) 
   }
   // the z pass after the plane passes holds the columns of two ky rows, 64
   // bytes of each row per z (4 FP64 or 8 FP32 columns)
-  f.cols_z = f.plane ? even_cols(2 * f.az.L, 32 / (int)es) : even_cols(f.az.L, 8);
+  // (exactly 64 bytes where the LDS allows: the same number of blocks as an
+  // even spread, since px = nx/2 + 1 is one above a multiple of it)
+  f.cols_z = f.plane ? std::max(1, std::min({32 / (int)es, f.px, maxpts / (2 * f.az.L)})) : even_cols(f.az.L, 8);
   f.norm = 2.0 / ((double)f.nx * f.ny * f.nz);
   return f;
 }
@@ -532,6 +576,36 @@ void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool i
                                                     RedJob{}, 0, 0);
 }
 
+// The z pass with its length and block shape fixed at compile time, for the
+// shapes the benchmarked grids use (64 bytes of each of two rows per z after
+// the plane passes; 8 columns of one row after the line passes); false if the
+// shape has no such instance (the run-time form then runs).
+template <typename T, int L, int CB, int NR>
+static void z_fixed(int nblk, size_t lds, hipStream_t st, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
+                    size_t stride, size_t outer, int lines, size_t run, double* ep, const RedJob& red, size_t ps) {
+  k_fft_col<T, 2, L, CB, NR><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, CB, stride, outer, lines,
+                                                             run, ep, red, NR == 2, ps);
+}
+
+template <typename T>
+static bool launch_z_fixed(int nblk, size_t lds, hipStream_t st, cplx<T>* spec, const FftGeom& f,
+                           const FftTables<T>& t, int cb, size_t stride, size_t outer, int lines, size_t run,
+                           double* ep, const RedJob& red, int nr, size_t ps) {
+  constexpr int CP = 32 / (int)sizeof(T);  // columns of 64 bytes
+#define GP_Z_FIXED(LL, CBB, NRR)                                                                 \
+  if (f.az.L == LL && cb == CBB && nr == NRR) {                                                  \
+    z_fixed<T, LL, CBB, NRR>(nblk, lds, st, spec, f, t, stride, outer, lines, run, ep, red, ps); \
+    return true;                                                                                 \
+  }
+  GP_Z_FIXED(64, CP, 2)
+  GP_Z_FIXED(96, CP, 2)
+  GP_Z_FIXED(128, CP, 2)
+  GP_Z_FIXED(256, 8, 1)
+  GP_Z_FIXED(512, 8, 1)
+#undef GP_Z_FIXED
+  return false;
+}
+
 template <typename T>
 void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, double* epot_partials,
                         bool ky_major, const RedJob& red, hipStream_t st) {
@@ -548,8 +622,10 @@ void launch_fft_z_green(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, 
   // C[run][z][ky][kx] (line passes) or C[run][ky][z][kx] (plane passes)
   const size_t stride = ky_major ? (size_t)f.px : (size_t)f.px * f.ny;
   const size_t outer = ky_major ? (size_t)f.px * f.nz : (size_t)f.px;
-  k_fft_col<T, 2><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, cb, stride, outer, lines, run,
-                                                  epot_partials, red, nr == 2, (size_t)lines * outer);
+  const size_t ps = (size_t)lines * outer;
+  if (!launch_z_fixed<T>(nblk, lds, st, spec, f, t, cb, stride, outer, lines, run, epot_partials, red, nr, ps))
+    k_fft_col<T, 2><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.az, t.tw_z, cb, stride, outer, lines, run,
+                                                    epot_partials, red, nr == 2, ps);
 }
 
 template void launch_fft_x_fwd<double>(const SrcSlot*, int, cplx<double>*, const FftGeom&,

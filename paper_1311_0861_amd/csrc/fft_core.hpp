@@ -168,6 +168,102 @@ __device__ void lds_fft(cplx<T>* buf, int lines, int ls, int es, const FftAxis& 
   }
 }
 
+// ---- transforms whose length and line count are known at compile time -----
+// The same Stockham stages as fft_stage (same butterflies, twiddle indexes and
+// order of operations, hence the same bits), with every index derived from
+// compile-time constants: the run-time form spends most of its instructions
+// on 32-bit multiplies and divides of the line count, stride and Ns.
+
+// Radix plan of a length L in make_axis order (8s, then 4s, 2s, 3s).
+struct RadPlan {
+  int nst;
+  int rad[16];
+};
+constexpr RadPlan rad_plan(int L) {
+  RadPlan p{0, {}};
+  int m = L;
+  while (m % 8 == 0 && m > 1) {
+    p.rad[p.nst++] = 8;
+    m /= 8;
+  }
+  while (m % 4 == 0) {
+    p.rad[p.nst++] = 4;
+    m /= 4;
+  }
+  while (m % 2 == 0) {
+    p.rad[p.nst++] = 2;
+    m /= 2;
+  }
+  while (m % 3 == 0) {
+    p.rad[p.nst++] = 3;
+    m /= 3;
+  }
+  return p;
+}
+// Product of the radices before stage s.
+constexpr int rad_ns(int L, int s) {
+  const RadPlan p = rad_plan(L);
+  int n = 1;
+  for (int q = 0; q < s; q++) n *= p.rad[q];
+  return n;
+}
+
+// One stage on LINES columns of an LDS block (element j of column c at
+// j * LINES + c), in place.
+template <typename T, int R, int NS, int L, int LINES, int NT, bool INV>
+__device__ __forceinline__ void cstage(cplx<T>* buf, const cplx<T>* tw) {
+  constexpr int nb = L / R;
+  constexpr int total = LINES * nb;
+  constexpr int tstep = L / (NS * R);
+  constexpr int MAXB = (total + NT - 1) / NT;
+  cplx<T> v[MAXB][R];
+  const int tid = (int)threadIdx.x;
+#pragma unroll
+  for (int b = 0; b < MAXB; b++) {
+    const int q = tid + b * NT;
+    if (total % NT == 0 || q < total) {
+      const int jj = q / LINES, line = q % LINES;
+      const int kk = jj % NS;
+      const cplx<T>* base = buf + line;
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        cplx<T> x = base[(jj + r * nb) * LINES];
+        if (r > 0) {
+          cplx<T> w = tw[kk * r * tstep];
+          if (INV) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[b][r] = x;
+      }
+      dft_small<T, R>(v[b], INV);
+    }
+  }
+  lds_barrier();
+#pragma unroll
+  for (int b = 0; b < MAXB; b++) {
+    const int q = tid + b * NT;
+    if (total % NT == 0 || q < total) {
+      const int jj = q / LINES, line = q % LINES;
+      const int kk = jj % NS;
+      cplx<T>* base = buf + line;
+      const int d0 = (jj / NS) * NS * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; r++) base[(d0 + r * NS) * LINES] = v[b][r];
+    }
+  }
+  lds_barrier();
+}
+
+// Transform of length L along LINES columns of an LDS block: all stages.
+template <typename T, int L, int LINES, int NT, bool INV, int S = 0>
+__device__ __forceinline__ void cfft(cplx<T>* buf, const cplx<T>* tw) {
+  constexpr RadPlan p = rad_plan(L);
+  if constexpr (S < p.nst) {
+    cstage<T, p.rad[S], rad_ns(L, S), L, LINES, NT, INV>(buf, tw);
+    cfft<T, L, LINES, NT, INV, S + 1>(buf, tw);
+  }
+}
+
 // rows (pitch lp, odd) of the line passes
 template <typename T>
 __device__ __forceinline__ void line_fft(cplx<T>* buf, int lines, int lp, const FftAxis& ax, const cplx<T>* tw,
