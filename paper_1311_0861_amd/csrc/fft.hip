@@ -24,20 +24,47 @@
 // held in registers between two barriers, so the stages work in place.
 // Twiddles come from tables computed on the host in FP64.
 #include <algorithm>
+#include <type_traits>
 
 #include "fft_core.hpp"
 #include "reduce.hpp"
 
 namespace gp {
 
+// Division by N, or by a run-time divisor (FastDiv) when N = 0.
+template <int N>
+struct CDiv {
+  __device__ explicit CDiv(uint32_t) {}
+  __device__ __forceinline__ uint32_t div(uint32_t q) const { return q / N; }
+};
+template <>
+struct CDiv<0> : FastDiv {
+  __device__ explicit CDiv(uint32_t d) : FastDiv(d) {}
+};
+
+
 // ---- x forward: rows of s (length nx) -> C rows (nx/2 + 1 bins) -------------
-template <typename T>
+// MC, RBC > 0: the half row length and the rows per block are compile-time
+// constants (equal to f.ax.L and f.rows_per_block); a last block with fewer
+// rows takes the run-time transform.
+template <typename T, int MC, int RBC, bool INV>
+__device__ __forceinline__ void x_rows_fft(cplx<T>* lds, int rows, int xp, const FftAxis& ax, const cplx<T>* tw) {
+  if constexpr (MC > 0) {
+    if (rows == RBC) {
+      cfft<T, MC, RBC, MC | 1, 1, kFftThreads, INV>(lds, tw);
+      return;
+    }
+  }
+  line_fft(lds, rows, xp, ax, tw, INV);
+}
+
+template <typename T, int MC = 0, int RBC = 0>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __restrict__ src, int parity,
                                                            cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int M = f.ax.L, xp = M | 1;  // odd row pitch
-  const int RB = f.rows_per_block;
+  const int M = MC ? MC : f.ax.L, xp = M | 1;  // odd row pitch
+  const int RB = RBC ? RBC : f.rows_per_block;
   cplx<T>* tw = lds + RB * xp;
   cplx<T>* wn = tw + M;
   const int rows_run = f.ny * f.nz;
@@ -46,7 +73,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __rest
   const int rows = min(RB, nrows - row0);
   load_twiddles<kFftThreads>(tw, t.tw_x, M);
   load_twiddles<kFftThreads>(wn, t.wn_x, M + 1);
-  const FastDiv dm(M), dm1(M + 1);
+  const CDiv<MC> dm(M);
+  const CDiv<MC ? MC + 1 : 0> dm1(M + 1);
   // packed (even, odd) pairs of each row of s
   staged_copy<kFftThreads, 4, cplx<T>>(
       rows * M,
@@ -65,7 +93,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __rest
         lds[rq * xp + q - rq * M] = v;
       });
   __syncthreads();
-  line_fft(lds, rows, xp, f.ax, tw, false);
+  x_rows_fft<T, MC, RBC, false>(lds, rows, xp, f.ax, tw);
   // even/odd split: X[k] = E[k] + W_N^k O[k]
   for (int q = threadIdx.x; q < rows * (M + 1); q += kFftThreads) {
     const int rr = (int)dm1.div(q), k = q - rr * (M + 1);
@@ -77,7 +105,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __rest
 
 // ---- x inverse: C rows -> real rows of phi ---------------------------------
 // The first fin.n workgroups finish the step instead (one per run).
-template <typename T>
+template <typename T, int MC = 0, int RBC = 0>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __restrict__ spec, T* __restrict__ phi,
                                                            FftGeom f, FftTables<T> t, FinJob fin) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -87,8 +115,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __rest
   }
   const int bid = (int)blockIdx.x - fin.n;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int M = f.ax.L, xp = M | 1;  // odd row pitch
-  const int RB = f.rows_per_block;
+  const int M = MC ? MC : f.ax.L, xp = M | 1;  // odd row pitch
+  const int RB = RBC ? RBC : f.rows_per_block;
   cplx<T>* xin = lds + RB * xp;         // RB rows of M + 1 bins
   cplx<T>* tw = xin + RB * (M + 1);
   cplx<T>* wn = tw + M;
@@ -97,7 +125,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __rest
   const int rows = min(RB, nrows - row0);
   load_twiddles<kFftThreads>(tw, t.tw_x, M);
   load_twiddles<kFftThreads>(wn, t.wn_x, M + 1);
-  const FastDiv dm(M);
+  const CDiv<MC> dm(M);
   staged_copy<kFftThreads, 4, cplx<T>>(
       rows * (M + 1), [&](int q) { return gload(spec + (size_t)row0 * f.px + q); },
       [&](int q, cplx<T> v) { xin[q] = v; });
@@ -107,7 +135,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __rest
     lds[rr * xp + k] = split_inv(xin[rr * (M + 1) + k], xin[rr * (M + 1) + M - k], wn[k]);
   }
   __syncthreads();
-  line_fft(lds, rows, xp, f.ax, tw, true);
+  x_rows_fft<T, MC, RBC, true>(lds, rows, xp, f.ax, tw);
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(phi) + (size_t)row0 * M;
   for (int q = threadIdx.x; q < rows * M; q += kFftThreads) {
     const int rq = (int)dm.div(q);
@@ -123,16 +151,16 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_x_inv(const cplx<T>* __rest
 // (ky and ky + ny/2), which hold E and O: it forms C[ky] = E + W^ky O and
 // C[ky + ny/2] = E - W^ky O before the z transforms, and stores e = C[ky] +
 // C[ky + ny/2] and o = (C[ky] - C[ky + ny/2]) W^-ky after them.
-// LC, CBC, NRC > 0 (z pass only): the transform length, the columns per row
-// and the rows per workgroup are compile-time constants (they must equal
-// ax.L, cb and 1 + pair), so that every index is derived from constants.
+// LC, CBC, NRC > 0: the transform length, the columns per row and the rows
+// per workgroup are compile-time constants (they must equal ax.L, cb and
+// 1 + pair), so that every index is derived from constants.
 template <typename T, int MODE, int LC = 0, int CBC = 0, int NRC = 0>  // MODE 0: forward, 1: inverse, 2: forward * symbol * inverse
 __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t,
                                                          FftAxis ax, const cplx<T>* __restrict__ twg, int cb_rt,
                                                          size_t stride, size_t outer_stride, int outer_div,
                                                          size_t run_stride, double* __restrict__ epot_partials,
                                                          RedJob red, int pair, size_t pair_stride) {
-  static_assert(LC == 0 || (MODE == 2 && CBC > 0 && NRC > 0), "compile-time shapes are for the z pass");
+  static_assert(LC == 0 || (CBC > 0 && (NRC == 1 || (MODE == 2 && NRC == 2))), "compile-time block shape");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   int bid = (int)blockIdx.x, nblk = (int)gridDim.x;
   if constexpr (MODE == 2) {
@@ -156,10 +184,11 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
   // the transforms along the columns of the block
   auto transform = [&](bool inv) {
     if constexpr (LC > 0) {
+      constexpr int CW = CBC * NRC;
       if (inv)
-        cfft<T, LC, CBC * NRC, kFftThreads, true>(lds, tw);
+        cfft<T, LC, CW, 1, CW, kFftThreads, true>(lds, tw);
       else
-        cfft<T, LC, CBC * NRC, kFftThreads, false>(lds, tw);
+        cfft<T, LC, CW, 1, CW, kFftThreads, false>(lds, tw);
     } else {
       col_fft(lds, cw, ax, tw, inv);
     }
@@ -313,6 +342,23 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_col(cplx<T>* __restrict__ s
 // them, so that the inverse plane pass again takes one row parity: row 2j + p
 // of the inverse y transform is the length-ny/2 inverse transform of e or o.
 // Two workgroups per plane, each with half the LDS of a whole plane.
+// Transform of a half plane: compile-time form when L > 0, else run-time.
+template <typename T, int L, int LINES, int LS, int ES, bool INV>
+__device__ __forceinline__ void plane_fft(cplx<T>* buf, int lines, int ls, int es, const FftAxis& ax,
+                                          const cplx<T>* tw) {
+  if constexpr (L > 0)
+    cfft<T, L, LINES, LS, ES, kPlaneThreads, INV>(buf, tw);
+  else
+    lds_fft<T, kPlaneThreads, plane_points<T>()>(buf, lines, ls, es, ax, tw, INV);
+}
+
+// Compile-time plane geometry of an NX x NY plane (all zero for run-time).
+template <int NX, int NY>
+struct PlaneShape {
+  static constexpr int M = NX / 2, HY = NY / 2, HP = NX ? ((NX / 2 + 1) | 1) : 0;
+  static constexpr int M1 = NX ? M + 1 : 0, H = NX ? M / 2 + 1 : 0;
+};
+
 template <typename T>
 struct PlaneLds {
   cplx<T>* pl;   // ny/2 x hp half plane
@@ -336,13 +382,18 @@ __device__ __forceinline__ PlaneLds<T> plane_lds(const FftGeom& f, const FftTabl
   return s;
 }
 
-template <typename T>
+// NX, NY > 0: the plane size is a compile-time constant (it must equal
+// f.nx, f.ny), so that every index is derived from constants.
+template <typename T, int NX = 0, int NY = 0>
 __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __restrict__ src, int parity,
                                                              cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t) {
-  constexpr int NT = kPlaneThreads, PM = plane_points<T>();
+  constexpr int NT = kPlaneThreads;
+  using PS = PlaneShape<NX, NY>;
   const PlaneLds<T> s = plane_lds(f, t);
-  const int M = f.ax.L, hy = f.ny / 2, hp = f.hp;
-  const FastDiv dm(M), dm1(M + 1), dh(M / 2 + 1);
+  const int M = NX ? PS::M : f.ax.L, hy = NY ? PS::HY : f.ny / 2, hp = NX ? PS::HP : f.hp;
+  const CDiv<PS::M> dm(M);
+  const CDiv<PS::M1> dm1(M + 1);
+  const CDiv<PS::H> dh(M / 2 + 1);
   const int plane = (int)blockIdx.x >> 1, p = (int)blockIdx.x & 1;  // run * nz + z, row parity
   const int slot = plane / f.nz, z = plane - slot * f.nz;
   const SrcSlot& S = src[slot];
@@ -363,7 +414,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
         s.pl[j * hp + m] = v;
       });
   lds_barrier();
-  lds_fft<T, NT, PM>(s.pl, hy, hp, 1, f.ax, s.twx, false);
+  plane_fft<T, PS::M, PS::HY, PS::HP, 1, false>(s.pl, hy, hp, 1, f.ax, s.twx);
   // split of each row into its M + 1 bins, pairs (k, M - k) by one thread
   const int H = M / 2 + 1;
   for (int q = threadIdx.x; q < hy * H; q += NT) {
@@ -380,7 +431,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
     }
   }
   lds_barrier();
-  lds_fft<T, NT, PM>(s.pl, M + 1, 1, hp, f.ayh, s.twy, false);
+  plane_fft<T, PS::HY, PS::M1, 1, PS::HP, false>(s.pl, M + 1, 1, hp, f.ayh, s.twy);
   // E or O into spectrum rows p ny/2 + k, ky-major: C[run][ky][z][kx], so
   // that the z pass reads contiguous blocks
   cplx<T>* out = spec + (((size_t)slot * f.ny + (size_t)p * hy) * f.nz + z) * f.px;
@@ -392,18 +443,21 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
 }
 
 // The first fin.n workgroups finish the step instead (one per run).
-template <typename T>
+template <typename T, int NX = 0, int NY = 0>
 __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_inv(const cplx<T>* __restrict__ spec, T* __restrict__ phi,
                                                              FftGeom f, FftTables<T> t, FinJob fin) {
-  constexpr int NT = kPlaneThreads, PM = plane_points<T>();
+  constexpr int NT = kPlaneThreads;
+  using PS = PlaneShape<NX, NY>;
   if ((int)blockIdx.x < fin.n) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     finalize_run(fin, (int)blockIdx.x, reinterpret_cast<double*>(smem_raw));
     return;
   }
   const PlaneLds<T> s = plane_lds(f, t);
-  const int M = f.ax.L, hy = f.ny / 2, hp = f.hp;
-  const FastDiv dm(M), dm1(M + 1), dh(M / 2 + 1);
+  const int M = NX ? PS::M : f.ax.L, hy = NY ? PS::HY : f.ny / 2, hp = NX ? PS::HP : f.hp;
+  const CDiv<PS::M> dm(M);
+  const CDiv<PS::M1> dm1(M + 1);
+  const CDiv<PS::H> dh(M / 2 + 1);
   const int b = (int)blockIdx.x - fin.n;
   const int plane = b >> 1, p = b & 1;  // run * nz + z, row parity
   const int slot = plane / f.nz, z = plane - slot * f.nz;
@@ -421,7 +475,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_inv(const cplx<T>* __r
         s.pl[ky * hp + kx] = v;
       });
   lds_barrier();
-  lds_fft<T, NT, PM>(s.pl, M + 1, 1, hp, f.ayh, s.twy, true);
+  plane_fft<T, PS::HY, PS::M1, 1, PS::HP, true>(s.pl, M + 1, 1, hp, f.ayh, s.twy);
   // complex-to-real split of each row: M + 1 bins -> M packed pairs
   const int H = M / 2 + 1;
   for (int q = threadIdx.x; q < hy * H; q += NT) {
@@ -437,7 +491,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_inv(const cplx<T>* __r
     }
   }
   lds_barrier();
-  lds_fft<T, NT, PM>(s.pl, hy, hp, 1, f.ax, s.twx, true);
+  plane_fft<T, PS::M, PS::HY, PS::HP, 1, true>(s.pl, hy, hp, 1, f.ax, s.twx);
   // rows 2j + p of phi, M packed pairs each
   cplx<T>* dst = reinterpret_cast<cplx<T>*>(phi) + ((size_t)plane * f.ny + p) * M;
   for (int q = threadIdx.x; q < hy * M; q += NT) {
@@ -512,21 +566,48 @@ size_t plane_lds_bytes(const FftGeom& f, size_t csz) {
   return csz * ((size_t)(f.ny / 2) * f.hp + M + M + 1 + f.ny / 2);
 }
 
-template <typename T>
-hipError_t fft_plane_prepare(int bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy_fwd<T>),
+// The plane passes are instantiated with compile-time shapes for square
+// planes of 64, 96 and 128 cells (the benchmarked grids); other sizes run the
+// run-time form.
+template <typename T, int NX>
+static hipError_t plane_prepare_one(int bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy_fwd<T, NX, NX>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy_inv<T>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy_inv<T, NX, NX>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return e;
 }
 
 template <typename T>
+hipError_t fft_plane_prepare(int bytes) {
+  hipError_t e = plane_prepare_one<T, 0>(bytes);
+  if (e == hipSuccess) e = plane_prepare_one<T, 64>(bytes);
+  if (e == hipSuccess) e = plane_prepare_one<T, 96>(bytes);
+  if (e == hipSuccess) e = plane_prepare_one<T, 128>(bytes);
+  return e;
+}
+
+// Calls fn(std::integral_constant<int, N>) with N the plane size when the
+// plane passes have a compile-time instance for f, else with N = 0.
+template <typename Fn>
+static void with_plane_shape(const FftGeom& f, Fn fn) {
+  if (f.nx == f.ny) {
+    if (f.nx == 64) return fn(std::integral_constant<int, 64>{});
+    if (f.nx == 96) return fn(std::integral_constant<int, 96>{});
+    if (f.nx == 128) return fn(std::integral_constant<int, 128>{});
+  }
+  fn(std::integral_constant<int, 0>{});
+}
+
+template <typename T>
 void launch_fft_xy_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
                        hipStream_t st) {
-  k_fft_xy_fwd<T><<<2 * f.nz * f.nruns, kPlaneThreads, plane_lds_bytes(f, sizeof(cplx<T>)), st>>>(src, parity,
-                                                                                                  spec, f, t);
+  with_plane_shape(f, [&](auto n) {
+    constexpr int N = decltype(n)::value;
+    k_fft_xy_fwd<T, N, N><<<2 * f.nz * f.nruns, kPlaneThreads, plane_lds_bytes(f, sizeof(cplx<T>)), st>>>(
+        src, parity, spec, f, t);
+  });
 }
 
 template <typename T>
@@ -534,7 +615,10 @@ void launch_fft_xy_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftT
                        hipStream_t st) {
   size_t lds = plane_lds_bytes(f, sizeof(cplx<T>));
   if (fin.n > 0) lds = std::max(lds, sizeof(double) * kFinLds);
-  k_fft_xy_inv<T><<<2 * f.nz * f.nruns + fin.n, kPlaneThreads, lds, st>>>(spec, phi, f, t, fin);
+  with_plane_shape(f, [&](auto n) {
+    constexpr int N = decltype(n)::value;
+    k_fft_xy_inv<T, N, N><<<2 * f.nz * f.nruns + fin.n, kPlaneThreads, lds, st>>>(spec, phi, f, t, fin);
+  });
 }
 
 static size_t x_lds_bytes(const FftGeom& f, size_t csz, bool inv) {
@@ -544,12 +628,28 @@ static size_t x_lds_bytes(const FftGeom& f, size_t csz, bool inv) {
 
 int fft_blocks_z(const FftGeom& f) { return ((f.px + f.cols_z - 1) / f.cols_z) * f.ny * f.nruns; }
 
+// Calls fn(std::integral_constant<int, N>) with N = nx / 2 when the line
+// passes have a compile-time instance for f (rows of 256 and 512 cells, the
+// benchmarked line-form grids), else with N = 0.
+template <typename T, typename Fn>
+static void with_line_shape(const FftGeom& f, Fn fn) {
+  constexpr int P = max_points<T>();
+  if (f.ax.L == 128 && f.rows_per_block == std::max(1, P / 256)) return fn(std::integral_constant<int, 128>{});
+  if (f.ax.L == 256 && f.rows_per_block == std::max(1, P / 512)) return fn(std::integral_constant<int, 256>{});
+  fn(std::integral_constant<int, 0>{});
+}
+
 template <typename T>
 void launch_fft_x_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const FftGeom& f, const FftTables<T>& t,
                       hipStream_t st) {
   const int nrows = f.ny * f.nz * f.nruns;
   const int nblk = (nrows + f.rows_per_block - 1) / f.rows_per_block;
-  k_fft_x_fwd<T><<<nblk, kFftThreads, x_lds_bytes(f, sizeof(cplx<T>), false), st>>>(src, parity, spec, f, t);
+  with_line_shape<T>(f, [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    constexpr int RB = M ? std::max(1, max_points<T>() / (2 * M)) : 0;
+    k_fft_x_fwd<T, M, RB><<<nblk, kFftThreads, x_lds_bytes(f, sizeof(cplx<T>), false), st>>>(src, parity, spec, f,
+                                                                                             t);
+  });
 }
 
 template <typename T>
@@ -559,7 +659,11 @@ void launch_fft_x_inv(const cplx<T>* spec, T* phi, const FftGeom& f, const FftTa
   const int nblk = (nrows + f.rows_per_block - 1) / f.rows_per_block + fin.n;
   size_t lds = x_lds_bytes(f, sizeof(cplx<T>), true);
   if (fin.n > 0) lds = std::max(lds, sizeof(double) * kFinLds);
-  k_fft_x_inv<T><<<nblk, kFftThreads, lds, st>>>(spec, phi, f, t, fin);
+  with_line_shape<T>(f, [&](auto m) {
+    constexpr int M = decltype(m)::value;
+    constexpr int RB = M ? std::max(1, max_points<T>() / (2 * M)) : 0;
+    k_fft_x_inv<T, M, RB><<<nblk, kFftThreads, lds, st>>>(spec, phi, f, t, fin);
+  });
 }
 
 template <typename T>
@@ -568,12 +672,20 @@ void launch_fft_y(cplx<T>* spec, const FftGeom& f, const FftTables<T>& t, bool i
   const int nblk = ((f.px + cb - 1) / cb) * f.nz * f.nruns;
   const size_t lds = sizeof(cplx<T>) * ((size_t)cb * f.ay.L + f.ay.L);
   const size_t stride = f.px, outer = (size_t)f.px * f.ny, run = outer * f.nz;
+  auto go = [&](auto mode, auto len) {
+    constexpr int MODE = decltype(mode)::value, L = decltype(len)::value;
+    k_fft_col<T, MODE, L, L ? 8 : 0, L ? 1 : 0><<<nblk, kFftThreads, lds, st>>>(
+        spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr, RedJob{}, 0, 0);
+  };
+  auto with_len = [&](auto mode) {
+    if (cb == 8 && f.ay.L == 256) return go(mode, std::integral_constant<int, 256>{});
+    if (cb == 8 && f.ay.L == 512) return go(mode, std::integral_constant<int, 512>{});
+    go(mode, std::integral_constant<int, 0>{});
+  };
   if (inverse)
-    k_fft_col<T, 1><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr,
-                                                    RedJob{}, 0, 0);
+    with_len(std::integral_constant<int, 1>{});
   else
-    k_fft_col<T, 0><<<nblk, kFftThreads, lds, st>>>(spec, f, t, f.ay, t.tw_y, cb, stride, outer, f.nz, run, nullptr,
-                                                    RedJob{}, 0, 0);
+    with_len(std::integral_constant<int, 0>{});
 }
 
 // The z pass with its length and block shape fixed at compile time, for the

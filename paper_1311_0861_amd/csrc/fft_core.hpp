@@ -208,9 +208,9 @@ constexpr int rad_ns(int L, int s) {
   return n;
 }
 
-// One stage on LINES columns of an LDS block (element j of column c at
-// j * LINES + c), in place.
-template <typename T, int R, int NS, int L, int LINES, int NT, bool INV>
+// One stage on LINES lines of length L, element j of line l at
+// buf[l * LS + j * ES], in place.
+template <typename T, int R, int NS, int L, int LINES, int LS, int ES, int NT, bool INV>
 __device__ __forceinline__ void cstage(cplx<T>* buf, const cplx<T>* tw) {
   constexpr int nb = L / R;
   constexpr int total = LINES * nb;
@@ -224,10 +224,10 @@ __device__ __forceinline__ void cstage(cplx<T>* buf, const cplx<T>* tw) {
     if (total % NT == 0 || q < total) {
       const int jj = q / LINES, line = q % LINES;
       const int kk = jj % NS;
-      const cplx<T>* base = buf + line;
+      const cplx<T>* base = buf + line * LS;
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        cplx<T> x = base[(jj + r * nb) * LINES];
+        cplx<T> x = base[(jj + r * nb) * ES];
         if (r > 0) {
           cplx<T> w = tw[kk * r * tstep];
           if (INV) w.y = -w.y;
@@ -245,22 +245,22 @@ __device__ __forceinline__ void cstage(cplx<T>* buf, const cplx<T>* tw) {
     if (total % NT == 0 || q < total) {
       const int jj = q / LINES, line = q % LINES;
       const int kk = jj % NS;
-      cplx<T>* base = buf + line;
+      cplx<T>* base = buf + line * LS;
       const int d0 = (jj / NS) * NS * R + kk;
 #pragma unroll
-      for (int r = 0; r < R; r++) base[(d0 + r * NS) * LINES] = v[b][r];
+      for (int r = 0; r < R; r++) base[(d0 + r * NS) * ES] = v[b][r];
     }
   }
   lds_barrier();
 }
 
-// Transform of length L along LINES columns of an LDS block: all stages.
-template <typename T, int L, int LINES, int NT, bool INV, int S = 0>
+// Transform of length L along LINES lines (strides LS, ES): all stages.
+template <typename T, int L, int LINES, int LS, int ES, int NT, bool INV, int S = 0>
 __device__ __forceinline__ void cfft(cplx<T>* buf, const cplx<T>* tw) {
   constexpr RadPlan p = rad_plan(L);
   if constexpr (S < p.nst) {
-    cstage<T, p.rad[S], rad_ns(L, S), L, LINES, NT, INV>(buf, tw);
-    cfft<T, L, LINES, NT, INV, S + 1>(buf, tw);
+    cstage<T, p.rad[S], rad_ns(L, S), L, LINES, LS, ES, NT, INV>(buf, tw);
+    cfft<T, L, LINES, LS, ES, NT, INV, S + 1>(buf, tw);
   }
 }
 
