@@ -33,13 +33,20 @@ struct GasPrim {
 
 // Sec. 2.1: V and P at a face between left and right states; z is the
 // acoustic impedance sqrt(gamma (pL + pR) rhoL rhoR / (rhoL + rhoR)).
+// The face solvers fuse multiply-adds only where written (fma): a face is
+// solved in more than one place (a chunk's first z face in the column
+// prologue, every other one in the plane loop and carried to the next
+// plane), and fusing left to the compiler is decided per inlined copy, which
+// would give those copies different bits, so results would depend on where
+// the tiling puts chunk boundaries.
 template <typename T>
 __device__ __forceinline__ void gas_face(const GasPrim<T>& L, const GasPrim<T>& R, T gamma, T& V, T& P) {
+#pragma clang fp contract(off)
   const T pl = L.p, pr = R.p;
   const T z = sqrt(gamma * (pl + pr) * L.rho * R.rho * rcp(L.rho + R.rho));
   const T rz = rcp(z);
-  V = T(0.5) * (L.vd + R.vd) + T(0.5) * (pl - pr) * rz;
-  P = T(0.5) * (pl + pr) + T(0.5) * (L.vd - R.vd) * z;
+  V = fma(T(0.5) * (pl - pr), rz, T(0.5) * (L.vd + R.vd));
+  P = fma(T(0.5) * (L.vd - R.vd), z, T(0.5) * (pl + pr));
 }
 
 // ------------------------------------------------- stars / dark matter ----
@@ -73,8 +80,10 @@ __device__ __forceinline__ BmeSide<T> centre_side(const BmeCentre<T>& C) {
 // (the printed x-normal formulas with the transverse axes a, b in place of
 // y, z).  Bracketed coefficients use the arithmetic means of n, Pi_DD, Pi_Da,
 // Pi_Db.  us[i] = u*_i, ps[i] = Pi*_{D i} in lab components.
+// (Multiply-adds fused only where written, as in gas_face.)
 template <typename T, int D>
 __device__ __forceinline__ void bme_face(const BmeSide<T>& L, const BmeSide<T>& R, T us[3], T ps[3]) {
+#pragma clang fp contract(off)
   constexpr int A_ = (D + 1) % 3, B_ = (D + 2) % 3;
   const T sqrt3 = T(1.7320508075688772935);
   const T nbar = T(0.5) * (L.n + R.n);
@@ -94,12 +103,12 @@ __device__ __forceinline__ void bme_face(const BmeSide<T>& L, const BmeSide<T>& 
   const T dub = T(0.5) * (L.u[B_] - R.u[B_]);
   const T cross_u = dpdd * (T(1) - sqrt3) * rA * rZ1;  // coupling of the fast wave into u_a, u_b
   const T cross_p = dud * nbar * (sqrt3 - T(1)) * rZ2;  // and into Pi_Da, Pi_Db
-  us[D] = T(0.5) * (L.u[D] + R.u[D]) + dpdd * rZ1;
-  us[A_] = T(0.5) * (L.u[A_] + R.u[A_]) + dpda * rZ2 + B * cross_u;
-  us[B_] = T(0.5) * (L.u[B_] + R.u[B_]) + dpdb * rZ2 + C * cross_u;
-  ps[D] = A + dud * Z1;
-  ps[A_] = B + dua * Z2 + B * cross_p;
-  ps[B_] = C + dub * Z2 + C * cross_p;
+  us[D] = fma(dpdd, rZ1, T(0.5) * (L.u[D] + R.u[D]));
+  us[A_] = fma(B, cross_u, fma(dpda, rZ2, T(0.5) * (L.u[A_] + R.u[A_])));
+  us[B_] = fma(C, cross_u, fma(dpdb, rZ2, T(0.5) * (L.u[B_] + R.u[B_])));
+  ps[D] = fma(dud, Z1, A);
+  ps[A_] = fma(B, cross_p, fma(dua, Z2, B));
+  ps[B_] = fma(C, cross_p, fma(dub, Z2, C));
 }
 
 // Adds the contribution of one face normal to axis D, with sign sg (+1 for

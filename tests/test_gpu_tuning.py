@@ -81,6 +81,26 @@ def test_every_tiling_gives_the_same_state(gp, W, precision):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_tilings_with_different_chunk_boundaries(gp, W, precision):
+    """96^3 is ragged in x for 64-wide tiles and its two tile shapes cut the
+    columns into chunks of different lengths (9 and 7 planes for the stars /
+    DM list, 6 and 5 for the FP64 gas list), so a chunk's first z face falls
+    on different planes.  The face solved in a column's prologue must carry
+    the same bits as the one solved in the plane loop of another tiling (a
+    regression test: with multiply-adds fused per inlined copy of the face
+    solvers, the Eulerian results depended on the tile shape here)."""
+    import torch
+    cfg, st = W.ensemble_member(W.ensemble_sizes(48).index(96))
+    cfgs = [dict(cfg, precision=precision)]
+    say("tiling invariance, 96^3 chunk boundaries", precision)
+    ref = _run(gp, cfgs, [st], None, steps=3)
+    _same(ref, _run(gp, cfgs, [st], {k: (1, 32) for k in CELL}, steps=3), "32x8")
+    mixed = {"eul_gas": (1, 16), "eul_bme": (1, 64), "lag_gas": (0, 16), "lag_bme": (1, 32)}
+    _same(ref, _run(gp, cfgs, [st], mixed, steps=3), "mixed")
+    torch.cuda.synchronize()
+
+
 def test_tuned_sim_equals_fixed_tiling(gp, W):
     """A sim left to the autotuner ends in the same state as one with the
     default tiling fixed, and reports valid picks."""
