@@ -350,14 +350,15 @@ __device__ __forceinline__ T field_update(const T (&tile)[NT][LY][LX], int t, in
 }
 
 // Waves per SIMD the register budget aims at (the stars / DM tiles take
-// 67 KB of LDS per workgroup in FP64, which allows two workgroups per CU).
-template <int C>
+// 67-76 KB of LDS per workgroup in FP64, which allows two workgroups per CU;
+// in FP32 half that, and three fit).
+template <int C, typename T>
 constexpr int lag_waves() {
-  return C == COMP_GAS ? 3 : 2;
+  return C == COMP_GAS ? 3 : (sizeof(T) == 8 ? 2 : 3);
 }
 
 template <int C, typename T, class S>
-__global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const RunDev<T>* __restrict__ runs,
+__global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(const RunDev<T>* __restrict__ runs,
                                                                         const WorkItem* __restrict__ work,
                                                                         unsigned nwork, int parity,
                                                                         double* __restrict__ partials) {
@@ -426,23 +427,27 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
     };
 
     const uint32_t xy_c = col.xy_c, xy_h = col.xy_h;
-    // prologue: plane k0 - 1 goes to the LDS centre slots (each plane's z-
-    // neighbours are read back from there) and to the velocity tile
-    // s_u[(k0 + 1) & 1]; plane k0 goes to registers and to s_u[k0 & 1]; the
-    // two give the corner velocities of vertex plane k0.  Plane k0 + 1 comes
-    // into registers too: the loop fetches each plane's centres two planes
-    // ahead, so they arrive while earlier planes are computed.
-    double dc, dp;
-    T fc[NF], fp[NF];
+    // Every line of a plane is fetched by its owner (as centres) and by the
+    // neighbouring tiles (as their ring).  Both fetches are issued in the
+    // same plane step of the sweep, so whichever comes second finds the line
+    // in the XCD's L2.  In the step of plane k the loop fetches
+    //   - the density and the fields after the velocities of plane k + 1,
+    //     centres and ring: the centres are this step's z+ neighbours and
+    //     next step's centres, the ring is staged next step;
+    //   - the velocities of plane k + 2, centres and ring: staged next step
+    //     as the velocity tile the corners of vertex plane k + 2 need.
+    // The z- neighbours are read back from the LDS centres of the previous
+    // plane and the z+ velocities from the velocity tile of plane k + 1.
+    // prologue: plane k0 - 1 goes to the LDS centre slots and to the
+    // velocity tile s_u[(k0 + 1) & 1], the velocities of plane k0 to
+    // s_u[k0 & 1] (the two give the corners of vertex plane k0); the rest of
+    // plane k0 (centres and ring) and the velocities of plane k0 + 1 come
+    // into registers.
+    double dc, rdn, dn1;
+    T fc[NF], rf[NF], uc[3], ur[3];  // fc, rf: slots 3..NF-1
     {
-      const size_t z1 = plane(k0 + 1);
-      dp = ld_at(din, z1, xy_c);
-#pragma unroll
-      for (int f = 0; f < NF; f++) fp[f] = ld_at(fin(f), z1, xy_c);
-    }
-    {
-      const size_t zm = plane(k0 - 1), z0 = nxy * (size_t)k0;
-      T um[3];
+      const size_t zm = plane(k0 - 1), z0 = nxy * (size_t)k0, z1 = plane(k0 + 1);
+      T um[3], u0[3];
       s_dn[ly + 1][lx + 1] = ld_at(din, zm, xy_c);
 #pragma unroll
       for (int f = 0; f < 3; f++) um[f] = ld_at(fin(f), zm, xy_c);
@@ -451,24 +456,21 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
       stage_velocity(zm, xy_h, s_u[(k0 + 1) & 1], um);
       dc = ld_at(din, z0, xy_c);
 #pragma unroll
-      for (int f = 0; f < NF; f++) fc[f] = ld_at(fin(f), z0, xy_c);
-      stage_velocity(z0, xy_h, s_u[k0 & 1], fc);
+      for (int f = 0; f < 3; f++) u0[f] = ld_at(fin(f), z0, xy_c);
+#pragma unroll
+      for (int f = 3; f < NF; f++) fc[f] = ld_at(fin(f), z0, xy_c);
+      stage_velocity(z0, xy_h, s_u[k0 & 1], u0);
+      rdn = ld_at(din, z0, xy_h);
+#pragma unroll
+      for (int f = 3; f < NF; f++) rf[f] = ld_at(fin(f), z0, xy_h);
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        uc[d] = ld_at(fin(d), z1, xy_c);
+        ur[d] = ld_at(fin(d), z1, xy_h);
+      }
+      dn1 = ld_at(din, z1, xy_c);
       lds_barrier();
       corner_plane(s_u[(k0 + 1) & 1], s_u[k0 & 1], s_v[k0 & 1]);
-    }
-    // The gas kernel fetches each plane's ring one plane ahead too (the
-    // stars / DM kernel has no registers left for it): the ring of plane k
-    // and the velocity ring of plane k + 1, held for the next plane.
-    constexpr bool kRingAhead = C == COMP_GAS;
-    double rd_n = 0.0;
-    T rf_n[NF], ru_n[3];
-    if constexpr (kRingAhead) {
-      const size_t z0 = nxy * (size_t)k0, z1 = plane(k0 + 1);
-      rd_n = ld_at(din, z0, xy_h);
-#pragma unroll
-      for (int f = 3; f < NF; f++) rf_n[f] = ld_at(fin(f), z0, xy_h);
-#pragma unroll
-      for (int f = 0; f < 3; f++) ru_n[f] = ld_at(fin(f), z1, xy_h);
     }
 
     Acc acc;
@@ -481,10 +483,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
       const int cu = k & 1, nu = cu ^ 1;  // velocity tiles of planes k and k+1
       const uint32_t xy_c = fresh(col.xy_c), xy_h = fresh(col.xy_h);
       // the previous centres become the z- neighbours (each thread reads back
-      // its own slot; the velocities from the tile of plane k-1); this
-      // plane's ring and centres go into LDS; the next plane's centres (z+
-      // neighbours, already in registers) and velocity ring go into the other
-      // velocity tile; plane k+2's centres are fetched for later
+      // its own slot; the velocities from the tile of plane k - 1)
       const double dm = s_dn[ly + 1][lx + 1];
       T fm[NF];
 #pragma unroll
@@ -492,50 +491,38 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
 #pragma unroll
       for (int f = 3; f < NF; f++) fm[f] = s_f[f - 3][ly + 1][lx + 1];
       lds_barrier();  // every thread is done with the previous plane's tiles
-      // ring of this plane (and velocity ring of the next) into LDS, from
-      // registers where it was fetched a plane ahead, else loaded now (every
-      // lane has a valid ring address; only ring lanes store); then the
-      // plane k+2 centre prefetch
-      auto stage_ring = [&](double rd, const T (&rf)[NF], const T (&ru)[3]) {
-        if (ring) {
-          s_dn[hr][hc] = rd;
+      // plane k (ring and centres) and the velocity tile of plane k + 1
+      // (every lane has a valid ring address; only ring lanes store)
+      if (ring) {
+        s_dn[hr][hc] = rdn;
 #pragma unroll
-          for (int f = 3; f < NF; f++) s_f[f - 3][hr][hc] = rf[f];
+        for (int f = 3; f < NF; f++) s_f[f - 3][hr][hc] = rf[f];
 #pragma unroll
-          for (int f = 0; f < 3; f++) s_u[nu][f][hr][hc] = ru[f];
-        }
-      };
-      auto load_ring = [&](size_t zf, size_t zu, double& rd, T (&rf)[NF], T (&ru)[3]) {
-        rd = ld_at(din, zf, xy_h);
-#pragma unroll
-        for (int f = 3; f < NF; f++) rf[f] = ld_at(fin(f), zf, xy_h);
-#pragma unroll
-        for (int f = 0; f < 3; f++) ru[f] = ld_at(fin(f), zu, xy_h);
-      };
-      double dpp;
-      T fpp[NF];
-      if constexpr (kRingAhead) {
-        stage_ring(rd_n, rf_n, ru_n);
-        load_ring(zp, zpp, rd_n, rf_n, ru_n);
-        issue_order();
-        dpp = ld_at(din, zpp, xy_c);
-#pragma unroll
-        for (int f = 0; f < NF; f++) fpp[f] = ld_at(fin(f), zpp, xy_c);
-      } else {
-        double rd_h;
-        T rf_h[NF], ru_h[3];
-        load_ring(zk, zp, rd_h, rf_h, ru_h);
-        issue_order();
-        dpp = ld_at(din, zpp, xy_c);
-#pragma unroll
-        for (int f = 0; f < NF; f++) fpp[f] = ld_at(fin(f), zpp, xy_c);
-        stage_ring(rd_h, rf_h, ru_h);
+        for (int d = 0; d < 3; d++) s_u[nu][d][hr][hc] = ur[d];
       }
       s_dn[ly + 1][lx + 1] = dc;
 #pragma unroll
       for (int f = 3; f < NF; f++) s_f[f - 3][ly + 1][lx + 1] = fc[f];
 #pragma unroll
-      for (int f = 0; f < 3; f++) s_u[nu][f][ly + 1][lx + 1] = fp[f];
+      for (int d = 0; d < 3; d++) s_u[nu][d][ly + 1][lx + 1] = uc[d];
+      // this step's fetches (the z+ centres first: they are needed first;
+      // the z+ density, needed before them, was fetched a step earlier)
+      const double dp = dn1;
+      T fp[NF];
+#pragma unroll
+      for (int f = 3; f < NF; f++) fp[f] = ld_at(fin(f), zp, xy_c);
+      if (k + 1 < k1) {
+        issue_order();
+        dn1 = ld_at(din, zpp, xy_c);
+        rdn = ld_at(din, zp, xy_h);
+#pragma unroll
+        for (int f = 3; f < NF; f++) rf[f] = ld_at(fin(f), zp, xy_h);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+          uc[d] = ld_at(fin(d), zpp, xy_c);
+          ur[d] = ld_at(fin(d), zpp, xy_h);
+        }
+      }
       lds_barrier();
       corner_plane(s_u[cu], s_u[nu], s_v[(k + 1) & 1]);
       lds_barrier();
@@ -602,7 +589,7 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
           x[3] = s_u[cu][d][ly][lx + 1];
           x[4] = s_u[cu][d][ly + 2][lx + 1];
           x[5] = fm[d];
-          x[6] = fp[d];
+          x[6] = s_u[nu][d][ly + 1][lx + 1];
 #pragma unroll
           for (int p = 0; p < 7; p++) x[p] *= (T)cf.dn[p];
           return advect7(x, cf.w);
@@ -627,12 +614,8 @@ __global__ void __launch_bounds__(kBlock, lag_waves<C>()) k_lagrangian(const Run
         }
       }
       dc = dp;
-      dp = dpp;
 #pragma unroll
-      for (int f = 0; f < NF; f++) {
-        fc[f] = fp[f];
-        fp[f] = fpp[f];
-      }
+      for (int f = 3; f < NF; f++) fc[f] = fp[f];
     }
     block_reduce_store(acc, as_global(partials) + ((size_t)R.row0 + it.row) * kNP + C * kNS, tid);
   }
