@@ -227,10 +227,9 @@ gp_status gp_debug_stage(gp_sim *sim, int32_t stage);
 
 /* Run nsteps steps kernel by kernel with HIP events around every launch and
  * return the mean duration in milliseconds of each GP_K_* kernel in ms[0..]
- * (max entries).  Each per-cell kernel (GP_K_EUL_*, GP_K_LAG_*) runs three
- * times back to back between its events (it recomputes the same outputs), so
- * the events' own latency is spread over three launches.  The state advances
- * as with gp_step. */
+ * (max entries).  Every kernel runs once, in the order of a step, so that it
+ * finds its inputs where a step leaves them; the host waits for each event,
+ * so the kernels do not overlap.  The state advances as with gp_step. */
 gp_status gp_time_kernels(gp_sim *sim, int32_t nsteps, double *ms, int32_t max);
 
 /* Use a captured HIP graph per step (default on).  Results are identical. */

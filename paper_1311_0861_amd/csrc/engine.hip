@@ -106,14 +106,13 @@ struct SizeClass {
   unsigned nep_run = 0;
 };
 
-// HIP events around each kernel (or pass) of a step.  A per-cell kernel is
-// launched `reps` times back to back between its two events (each launch
-// recomputes the same outputs from the same inputs), which spreads the
-// events' own launch and completion latency over the repeats.
+// HIP events around each kernel (or pass) of a step, launched once, in the
+// order of a step, so that each finds its inputs where a step leaves them
+// (launched several times back to back, the later launches read inputs the
+// earlier ones left in the last-level cache and read faster than in a step).
 struct Timer {
   hipEvent_t ev[2 * GP_NKERNELS];
   double acc[GP_NKERNELS];
-  int reps = 1;
   bool on = false;
 };
 
@@ -277,12 +276,12 @@ IsoGeom make_iso_geom(int nx, int ny, int nz, int nruns, size_t es) {
 void tmark(gp_batch* b, Timer* tm, int k, int side) {
   if (tm && tm->on) (void)hipEventRecord(tm->ev[2 * k + side], b->st);
 }
-void tdone(Timer* tm, int k, int reps = 1) {
+void tdone(Timer* tm, int k) {
   if (tm && tm->on) {
     (void)hipEventSynchronize(tm->ev[2 * k + 1]);
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, tm->ev[2 * k], tm->ev[2 * k + 1]);
-    tm->acc[k] += ms / reps;
+    tm->acc[k] += ms;
   }
 }
 
@@ -438,8 +437,8 @@ void launch_cell_kernel(gp_batch* b, int k, const TileCfg& c) {
   }
 }
 
-// The autotuner.  Kernel k is timed (one warm launch, then five between HIP
-// events) in its default configuration (64 x 4 tiles, 32-plane chunk cap, a
+// The autotuner.  Kernel k is timed (one warm launch, then the median of
+// kTuneReps launches, each between HIP events) in its default configuration (64 x 4 tiles, 32-plane chunk cap, a
 // workgroup per item), then for every other tile shape and chunk cap at a
 // workgroup per item, then for the fastest of those at the persistent grid
 // sizes 8192, 4096, 2048 and 1024 below that.  A candidate replaces the best
@@ -451,7 +450,8 @@ void launch_cell_kernel(gp_batch* b, int k, const TileCfg& c) {
 // nothing but the timing -- except the partial rows of the Lagrangian
 // kernels, which the caller clears after tuning them (a candidate list can be
 // longer than the chosen one).
-constexpr float kTuneMargin = 0.02f;
+constexpr float kTuneMargin = 0.03f;
+constexpr int kTuneReps = 7;
 
 template <typename T>
 void tune_kernel(gp_batch* b, int k) {
@@ -467,20 +467,21 @@ void tune_kernel(gp_batch* b, int k) {
   const int other = k == GP_K_EUL_GAS ? GP_K_EUL_BME
                   : k == GP_K_EUL_BME ? GP_K_EUL_GAS
                   : k == GP_K_LAG_GAS ? GP_K_LAG_BME : GP_K_LAG_GAS;
+  // The median of kTuneReps such launches is the candidate's time.
   auto time = [&](const TileCfg& c) {
     launch_cell_kernel<T>(b, k, c);  // warm
-    float total = 0.f;
-    for (int rep = 0; rep < 5; rep++) {
+    float t[kTuneReps];
+    for (int rep = 0; rep < kTuneReps; rep++) {
       launch_cell_kernel<T>(b, other, b->kcfg[other]);
       (void)hipEventRecord(e0, b->st);
       launch_cell_kernel<T>(b, k, c);
       (void)hipEventRecord(e1, b->st);
       (void)hipEventSynchronize(e1);
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      total += ms;
+      t[rep] = 0.f;
+      (void)hipEventElapsedTime(&t[rep], e0, e1);
     }
-    return total;
+    std::sort(t, t + kTuneReps);
+    return t[kTuneReps / 2];
   };
   TileCfg pick{};
   pick.blocks = work_count(b, k, pick);
@@ -617,11 +618,10 @@ template <typename T>
 void enqueue_stage(gp_batch* b, int stage, Timer* tm, bool allow_tune) {
   const bool tuning = allow_tune && b->tune && !b->tuned;
   auto cell = [&](int k) {
-    const int reps = (tm && tm->on) ? tm->reps : 1;
     tmark(b, tm, k, 0);
-    for (int r = 0; r < reps; r++) launch_cell_kernel<T>(b, k, b->kcfg[k]);
+    launch_cell_kernel<T>(b, k, b->kcfg[k]);
     tmark(b, tm, k, 1);
-    tdone(tm, k, reps);
+    tdone(tm, k);
   };
   switch (stage) {
     case GP_STAGE_EUL:
@@ -1247,7 +1247,6 @@ gp_status engine_time_kernels(gp_batch* b, int32_t nsteps, double* ms, int32_t m
   if (b->need_prologue) run_prologue(b);
   Timer tm;
   tm.on = true;
-  tm.reps = 3;
   for (int k = 0; k < 2 * GP_NKERNELS; k++) HIP_TRY(b, hipEventCreate(&tm.ev[k]));
   for (int k = 0; k < GP_NKERNELS; k++) tm.acc[k] = 0.0;
   // An untuned sim picks its launch sizes during the first timed step: the

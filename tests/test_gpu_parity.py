@@ -220,9 +220,9 @@ def test_stages_equal_step(gp, W):
 
 
 def test_time_kernels_advances_like_step(gp, W):
-    """gp_time_kernels runs each per-cell kernel three times back to back
-    between its events; each launch recomputes the same outputs, so the state
-    and diagnostics after it equal those after the same steps of gp_step."""
+    """gp_time_kernels runs the kernels of each step one by one between HIP
+    events; the state and diagnostics after it equal those after the same
+    steps of gp_step."""
     say("time_kernels vs step")
     cfg, st = W.random_periodic(n=(16, 12, 8), seed=13)
     a, _ = make_pair(cfg, st)
