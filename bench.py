@@ -228,9 +228,24 @@ def oracle_baseline(cfg, st, ncell, err_steps):
     return base, orc
 
 
+def warm_clocks(obj, seconds=0.25):
+    """The first step (in it the autotuner picks each per-cell kernel's
+    launch configuration), then graph-replayed steps for about `seconds`, so
+    that the timed steps run at the GPU's working clocks (a pass that waits
+    on the host between kernels leaves the GPU idle between them and does
+    not bring it there)."""
+    obj.step(1)
+    obj.sync()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        obj.step(10)
+        obj.sync()
+
+
 def timed_steps(obj, steps, warmup):
     """Warm up, then time exactly `steps` graph-replayed steps of a Sim/Batch."""
     import torch
+    warm_clocks(obj)
     obj.step(warmup)
     obj.sync()
     torch.cuda.synchronize()
@@ -398,10 +413,8 @@ def main():
         return s
 
     sim = fresh_sim()
-    # a kernel-by-kernel pass first: it picks the launch sizes and brings the
-    # GPU to its working clocks before the timed steps (its timings are
-    # discarded; the roofline is taken again after the timed run)
-    sim.time_kernels(args.profile_steps)
+    # the tuning step, then steps until the GPU runs at its working clocks
+    warm_clocks(sim)
 
     # ---- timed run: warmup, then exactly K graph-replayed steps ------------
     sim.step(args.warmup)
