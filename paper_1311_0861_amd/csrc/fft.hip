@@ -31,33 +31,10 @@
 
 namespace gp {
 
-// Division by N, or by a run-time divisor (FastDiv) when N = 0.
-template <int N>
-struct CDiv {
-  __device__ explicit CDiv(uint32_t) {}
-  __device__ __forceinline__ uint32_t div(uint32_t q) const { return q / N; }
-};
-template <>
-struct CDiv<0> : FastDiv {
-  __device__ explicit CDiv(uint32_t d) : FastDiv(d) {}
-};
-
 
 // ---- x forward: rows of s (length nx) -> C rows (nx/2 + 1 bins) -------------
 // MC, RBC > 0: the half row length and the rows per block are compile-time
-// constants (equal to f.ax.L and f.rows_per_block); a last block with fewer
-// rows takes the run-time transform.
-template <typename T, int MC, int RBC, bool INV>
-__device__ __forceinline__ void x_rows_fft(cplx<T>* lds, int rows, int xp, const FftAxis& ax, const cplx<T>* tw) {
-  if constexpr (MC > 0) {
-    if (rows == RBC) {
-      cfft<T, MC, RBC, MC | 1, 1, kFftThreads, INV>(lds, tw);
-      return;
-    }
-  }
-  line_fft(lds, rows, xp, ax, tw, INV);
-}
-
+// constants (equal to f.ax.L and f.rows_per_block).
 template <typename T, int MC = 0, int RBC = 0>
 __global__ void __launch_bounds__(kFftThreads) k_fft_x_fwd(const SrcSlot* __restrict__ src, int parity,
                                                            cplx<T>* __restrict__ spec, FftGeom f, FftTables<T> t) {

@@ -277,6 +277,32 @@ __device__ __forceinline__ void col_fft(cplx<T>* buf, int cols, const FftAxis& a
   lds_fft<T, kFftThreads, max_points<T>()>(buf, cols, 1, cols, ax, tw, inv);
 }
 
+// Division by N, or by a run-time divisor (FastDiv) when N = 0.
+template <int N>
+struct CDiv {
+  __device__ explicit CDiv(uint32_t) {}
+  __device__ __forceinline__ uint32_t div(uint32_t q) const { return q / N; }
+};
+template <>
+struct CDiv<0> : FastDiv {
+  __device__ explicit CDiv(uint32_t d) : FastDiv(d) {}
+};
+
+// Rows of a line pass: the compile-time transform when MC, RBC > 0 (the row
+// length and the rows per block, which must equal ax.L and the block's row
+// count when it is full); a last block with fewer rows, or MC = 0, takes the
+// run-time transform.
+template <typename T, int MC, int RBC, bool INV>
+__device__ __forceinline__ void x_rows_fft(cplx<T>* lds, int rows, int xp, const FftAxis& ax, const cplx<T>* tw) {
+  if constexpr (MC > 0) {
+    if (rows == RBC) {
+      cfft<T, MC, RBC, MC | 1, 1, kFftThreads, INV>(lds, tw);
+      return;
+    }
+  }
+  line_fft(lds, rows, xp, ax, tw, INV);
+}
+
 template <int NT, typename T>
 __device__ __forceinline__ void load_twiddles(cplx<T>* dst, const cplx<T>* src, int n) {
   for (int t = threadIdx.x; t < n; t += NT) dst[t] = src[t];

@@ -29,6 +29,7 @@
 //   x inverse : those rows; the real outputs at x = -1, 0 .. nx, stored as the
 //               potential on the grid and its ring.
 // Every pass works in place on lines its own workgroup loaded whole.
+#include <algorithm>
 #include <cmath>
 
 #include "fft_core.hpp"
@@ -36,29 +37,47 @@
 
 namespace gp {
 
+// Compile-time shape of a cubic N^3 grid (N = 0: every size from IsoGeom at
+// run time).  With N > 0 the kernels below derive every index from constants;
+// the host launches such an instance only for a geometry that matches it
+// (iso_fixed), and the arithmetic is the same, hence the same bits.
+template <typename T, int N>
+struct IsoShape {
+  static constexpr int M = N;                                            // packed pairs of a padded row
+  static constexpr int RB = N ? std::max(1, max_points<T>() / (2 * N)) : 0;  // rows per x block
+  static constexpr int L = 2 * N;                                        // padded column length
+  static constexpr int CB = N ? 8 : 0;                                   // columns per column block
+};
+
 // ---- x forward -----------------------------------------------------------
 // GREEN = false: rows y < ny, z < nz of s (run after run), the padded half of
 // each row zero.  GREEN = true: every row of the padded lattice (py pz of one
 // run), the sampled Green function g; gscale = -G h^2, g0 = g(0).
-template <typename T, bool GREEN>
+template <typename T, bool GREEN, int N = 0>
 __global__ void __launch_bounds__(kFftThreads) k_iso_x_fwd(const SrcSlot* __restrict__ src, int parity,
                                                            cplx<T>* __restrict__ spec, IsoGeom f, IsoTables<T> t,
                                                            double gscale, double g0) {
+  static_assert(N == 0 || !GREEN, "compile-time shapes are for the source rows");
+  using S = IsoShape<T, N>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int M = f.ax.L, xp = M | 1;     // M = nx packed pairs per padded row; odd pitch
-  const int nload = GREEN ? M : M / 2;  // pairs that carry data
-  const int RB = f.rows_per_block;
+  // grid and padded sizes: constants for a compile-time shape
+  const int nx = N ? N : f.nx, ny = N ? N : f.ny, nz = N ? N : f.nz;
+  const int px = N ? N + 1 : f.px, py = N ? 2 * N : f.py, pz = N ? 2 * N : f.pz;
+  const int M = N ? S::M : f.ax.L, xp = M | 1;  // M = nx packed pairs per padded row; odd pitch
+  const int nload = GREEN ? M : M / 2;          // pairs that carry data
+  const int RB = N ? S::RB : f.rows_per_block;
   cplx<T>* tw = lds + RB * xp;
   cplx<T>* wn = tw + M;
-  const int ry = GREEN ? f.py : f.ny;  // rows per plane
-  const int rows_run = ry * (GREEN ? f.pz : f.nz);
+  const int ry = GREEN ? py : ny;  // rows per plane
+  const int rows_run = ry * (GREEN ? pz : nz);
   const int nrows = rows_run * f.nruns;
   const int row0 = blockIdx.x * RB;
   const int rows = min(RB, nrows - row0);
   load_twiddles<kFftThreads>(tw, t.tw_x, M);
   load_twiddles<kFftThreads>(wn, t.wn_x, M + 1);
-  const FastDiv dl(nload), dm1(M + 1);
+  const CDiv<N ? S::M / 2 : 0> dl(nload);
+  const CDiv<N ? S::M + 1 : 0> dm1(M + 1);
   staged_copy<kFftThreads, 4, cplx<T>>(
       rows * nload,
       [&](int q) {
@@ -67,19 +86,19 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_x_fwd(const SrcSlot* __rest
         if constexpr (GREEN) {
           // one run: row = y + py z
           const int z = row / ry, y = row - z * ry;
-          const double dy = y <= f.ny ? y : y - f.py, dz = z <= f.nz ? z : z - f.pz;
+          const double dy = y <= ny ? y : y - py, dz = z <= nz ? z : z - pz;
           double v[2];
 #pragma unroll
           for (int u = 0; u < 2; u++) {
             const int x = 2 * m + u;
-            const double dx = x <= f.nx ? x : x - 2 * f.nx;
+            const double dx = x <= nx ? x : x - 2 * nx;
             const double r = sqrt(dx * dx + dy * dy + dz * dz);
             v[u] = r == 0.0 ? g0 : gscale / r;
           }
           return cplx<T>{(T)v[0], (T)v[1]};
         } else {
           const int slot = row / rows_run;  // may exceed the range of FastDiv
-          const size_t c = (size_t)(row - slot * rows_run) * f.nx + 2 * m;
+          const size_t c = (size_t)(row - slot * rows_run) * nx + 2 * m;
           const SrcSlot& S = src[slot];
           const dpair a = gload(reinterpret_cast<const dpair*>(S.rho[parity] + c));
           const dpair b = gload(reinterpret_cast<const dpair*>(S.nb[parity] + c));
@@ -98,7 +117,7 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_x_fwd(const SrcSlot* __rest
     }
   }
   __syncthreads();
-  line_fft(lds, rows, xp, f.ax, tw, false);
+  x_rows_fft<T, S::M, S::RB, false>(lds, rows, xp, f.ax, tw);
   // even/odd split into nx + 1 bins; spectrum row y + py z of the run
   for (int q = threadIdx.x; q < rows * (M + 1); q += kFftThreads) {
     const int rq = (int)dm1.div(q), k = q - rq * (M + 1);
@@ -107,7 +126,7 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_x_fwd(const SrcSlot* __rest
     const int z = rr / ry, y = rr - z * ry;
     const cplx<T> zk = lds[rq * xp + (k == M ? 0 : k)];
     const cplx<T> zc = lds[rq * xp + (k == 0 ? 0 : M - k)];
-    spec[(size_t)slot * f.run_stride + ((size_t)z * f.py + y) * f.px + k] = split_fwd(zk, zc, wn[k]);
+    spec[(size_t)slot * f.run_stride + ((size_t)z * py + y) * px + k] = split_fwd(zk, zc, wn[k]);
   }
 }
 
@@ -120,12 +139,27 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_x_fwd(const SrcSlot* __rest
 // 0 .. n and -1 of a padded axis.
 // MODE 0: forward, 1: inverse, 2: forward * Green spectrum * inverse (z pass,
 // whose first red.n workgroups reduce partial rows instead).
-template <typename T, int MODE>
+// Column transform of a column block: the compile-time one for N > 0.
+template <typename T, int N, bool INV>
+__device__ __forceinline__ void iso_col_fft(cplx<T>* lds, int cb, const FftAxis& ax, const cplx<T>* tw) {
+  using S = IsoShape<T, N>;
+  if constexpr (N > 0)
+    cfft<T, S::L, S::CB, 1, S::CB, kFftThreads, INV>(lds, tw);
+  else
+    col_fft(lds, cb, ax, tw, INV);
+}
+
+template <typename T, int MODE, int N = 0>
 __global__ void __launch_bounds__(kFftThreads) k_iso_col(cplx<T>* __restrict__ spec, IsoGeom f, IsoTables<T> t,
-                                                         FftAxis ax, const cplx<T>* __restrict__ twg, int cb,
+                                                         FftAxis ax, const cplx<T>* __restrict__ twg, int cb_rt,
                                                          size_t stride, size_t outer_stride, int outer_div, int nin,
                                                          int nout, double* __restrict__ epot_partials, RedJob red) {
+  using S = IsoShape<T, N>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  // grid and padded sizes: constants for a compile-time shape
+  const int nx = N ? N : f.nx, ny = N ? N : f.ny, nz = N ? N : f.nz;
+  const int px = N ? N + 1 : f.px, py = N ? 2 * N : f.py, pz = N ? 2 * N : f.pz;
+  const int cb = N ? S::CB : cb_rt;
   int bid = (int)blockIdx.x, nblk = (int)gridDim.x;
   if constexpr (MODE == 2) {
     if (bid < red.n) {
@@ -138,16 +172,16 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_col(cplx<T>* __restrict__ s
     nblk -= red.n;
   }
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);  // L rows of cb columns
-  const int L = ax.L;
+  const int L = N ? S::L : ax.L;
   cplx<T>* tw = lds + cb * L;
-  const int nchunks = (f.px + cb - 1) / cb;
+  const int nchunks = (px + cb - 1) / cb;
   const ColBlock cbk = col_block(bid, nchunks, nblk / nchunks);
   const int chunk = cbk.chunk, oline = cbk.oline;
   const int run = oline / outer_div, outer = oline - run * outer_div;
   const int kx0 = chunk * cb;
-  const int ncols = min(cb, f.px - kx0);
+  const int ncols = min(cb, px - kx0);
   load_twiddles<kFftThreads>(tw, twg, L);
-  const FastDiv dcb(cb);
+  const CDiv<S::CB> dcb(cb);
   cplx<T>* base = spec + (size_t)run * f.run_stride + (size_t)outer * outer_stride + kx0;
   staged_copy<kFftThreads, 4, cplx<T>>(
       cb * nin,
@@ -159,20 +193,20 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_col(cplx<T>* __restrict__ s
       [&](int q, cplx<T> v) { lds[q] = v; });
   for (int q = cb * nin + (int)threadIdx.x; q < cb * L; q += kFftThreads) lds[q] = cplx<T>{T(0), T(0)};
   __syncthreads();
-  col_fft(lds, cb, ax, tw, MODE == 1);
+  iso_col_fft<T, N, MODE == 1>(lds, cb, ax, tw);
   if constexpr (MODE == 2) {
     // line position = kz, outer = ky; the Green spectrum is even in ky and kz
     __shared__ double red_ep[kFftThreads / 64];
-    const int kyr = min(outer, f.py - outer);
-    const double* grow = t.green + (size_t)kyr * f.px + kx0;
-    const size_t gplane = (size_t)(f.ny + 1) * f.px;
+    const int kyr = min(outer, py - outer);
+    const double* grow = t.green + (size_t)kyr * px + kx0;
+    const size_t gplane = (size_t)(ny + 1) * px;
     double ep = 0.0;
     for (int q = threadIdx.x; q < cb * L; q += kFftThreads) {
       const int kz = (int)dcb.div(q), c = q - kz * cb;
       if (c >= ncols) continue;
-      const int kx = kx0 + c, kzr = min(kz, f.pz - kz);
+      const int kx = kx0 + c, kzr = min(kz, pz - kz);
       const double gk = gload(grow + (size_t)kzr * gplane + c);
-      const double w = (kx == 0 || kx == f.nx) ? 1.0 : 2.0;  // Hermitian half spectrum of the padded x axis
+      const double w = (kx == 0 || kx == nx) ? 1.0 : 2.0;  // Hermitian half spectrum of the padded x axis
       cplx<T>& v = lds[q];
       ep += w * gk * ((double)v.x * (double)v.x + (double)v.y * (double)v.y);
       const T gs = (T)(gk * f.norm);
@@ -188,7 +222,7 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_col(cplx<T>* __restrict__ s
       for (int w = 0; w < kFftThreads / 64; w++) s += red_ep[w];
       epot_partials[(size_t)oline * nchunks + chunk] = s;
     }
-    col_fft(lds, cb, ax, tw, true);
+    iso_col_fft<T, N, true>(lds, cb, ax, tw);
   }
   for (int q = threadIdx.x; q < cb * nout; q += kFftThreads) {
     const int j = (int)dcb.div(q), c = q - j * cb;
@@ -200,29 +234,35 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_col(cplx<T>* __restrict__ s
 
 // ---- x inverse: rows of the kept planes -> potential with its ring ---------
 // The first fin.n workgroups finish the step instead (one per run).
-template <typename T>
+template <typename T, int N = 0>
 __global__ void __launch_bounds__(kFftThreads) k_iso_x_inv(const cplx<T>* __restrict__ spec, T* __restrict__ phi,
                                                            IsoGeom f, IsoTables<T> t, FinJob fin) {
+  using S = IsoShape<T, N>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   if ((int)blockIdx.x < fin.n) {
     finalize_run(fin, (int)blockIdx.x, reinterpret_cast<double*>(smem_raw));
     return;
   }
+  // grid and padded sizes: constants for a compile-time shape
+  const int nx = N ? N : f.nx, ny = N ? N : f.ny, nz = N ? N : f.nz;
+  const int px = N ? N + 1 : f.px, py = N ? 2 * N : f.py, pz = N ? 2 * N : f.pz;
   const int bid = (int)blockIdx.x - fin.n;
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int M = f.ax.L, xp = M | 1;
-  const int RB = f.rows_per_block;
+  const int M = N ? S::M : f.ax.L, xp = M | 1;
+  const int RB = N ? S::RB : f.rows_per_block;
   cplx<T>* xin = lds + RB * xp;  // RB rows of M + 1 bins
   cplx<T>* tw = xin + RB * (M + 1);
   cplx<T>* wn = tw + M;
-  const int ex = f.nx + 2, ey = f.ny + 2, ez = f.nz + 2;
+  const int ex = nx + 2, ey = ny + 2, ez = nz + 2;
   const int rows_run = ey * ez;
   const int nrows = rows_run * f.nruns;
   const int row0 = bid * RB;
   const int rows = min(RB, nrows - row0);
   load_twiddles<kFftThreads>(tw, t.tw_x, M);
   load_twiddles<kFftThreads>(wn, t.wn_x, M + 1);
-  const FastDiv dm(M), dm1(M + 1), dex(ex);
+  const CDiv<S::M> dm(M);
+  const CDiv<N ? S::M + 1 : 0> dm1(M + 1);
+  const CDiv<N ? N + 2 : 0> dex(ex);
   // kept row yo of kept plane zo sits at spectrum row yo + py zo
   staged_copy<kFftThreads, 4, cplx<T>>(
       rows * (M + 1),
@@ -231,7 +271,7 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_x_inv(const cplx<T>* __rest
         const int row = row0 + rq;
         const int slot = row / rows_run, rr = row - slot * rows_run;
         const int zo = rr / ey, yo = rr - zo * ey;
-        return gload(spec + (size_t)slot * f.run_stride + ((size_t)zo * f.py + yo) * f.px + k);
+        return gload(spec + (size_t)slot * f.run_stride + ((size_t)zo * py + yo) * px + k);
       },
       [&](int q, cplx<T> v) { xin[q] = v; });
   __syncthreads();
@@ -240,7 +280,7 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_x_inv(const cplx<T>* __rest
     lds[rr * xp + k] = split_inv(xin[rr * (M + 1) + k], xin[rr * (M + 1) + M - k], wn[k]);
   }
   __syncthreads();
-  line_fft(lds, rows, xp, f.ax, tw, true);
+  x_rows_fft<T, S::M, S::RB, true>(lds, rows, xp, f.ax, tw);
   // real value at position p of the padded row is component p & 1 of pair
   // p / 2; ring position 0 holds p = 2nx - 1, positions 1 .. nx + 1 hold p = 0 .. nx
   for (int q = threadIdx.x; q < rows * ex; q += kFftThreads) {
@@ -248,9 +288,9 @@ __global__ void __launch_bounds__(kFftThreads) k_iso_x_inv(const cplx<T>* __rest
     const int row = row0 + rq;
     const int slot = row / rows_run, rr = row - slot * rows_run;
     const int zo = rr / ey, yo = rr - zo * ey;
-    const int p = xo == 0 ? 2 * f.nx - 1 : xo - 1;
+    const int p = xo == 0 ? 2 * nx - 1 : xo - 1;
     const cplx<T> v = lds[rq * xp + (p >> 1)];
-    const int zi = zo == f.nz + 1 ? 0 : zo + 1, yi = yo == f.ny + 1 ? 0 : yo + 1;
+    const int zi = zo == nz + 1 ? 0 : zo + 1, yi = yo == ny + 1 ? 0 : yo + 1;
     phi[(size_t)slot * f.ext_cells + ((size_t)zi * ey + yi) * ex + xo] = (p & 1) ? v.y : v.x;
   }
 }
@@ -284,17 +324,33 @@ size_t x_lds(const IsoGeom& f, size_t csz, bool inv) {
 
 size_t col_lds(int cb, int L, size_t csz) { return csz * ((size_t)cb * L + L); }
 
+// Grid size N of the compile-time kernels f runs on (the 128^3 runs of the
+// benchmark), or 0: cubic, blocks of 8 columns, full x blocks of the
+// compile-time row count.
+template <typename T>
+int iso_fixed(const IsoGeom& f) {
+  constexpr int N = 128;
+  if (f.nx == N && f.ny == N && f.nz == N && f.cols_y == IsoShape<T, N>::CB && f.cols_z == IsoShape<T, N>::CB &&
+      f.rows_per_block == IsoShape<T, N>::RB)
+    return N;
+  return 0;
+}
+
 // column pass over `nouter` outer lines per run
 template <typename T, int MODE>
 void col_pass(cplx<T>* spec, const IsoGeom& f, const IsoTables<T>& t, const FftAxis& ax, const cplx<T>* tw, int cb,
               size_t stride, size_t outer_stride, int nouter, int nruns, int nin, int nout, double* epot,
-              const RedJob& red, hipStream_t st) {
+              const RedJob& red, hipStream_t st, int fixed) {
   const int nchunks = (f.px + cb - 1) / cb;
   const int nblk = nchunks * nouter * nruns + (MODE == 2 ? red.n : 0);
   size_t lds = col_lds(cb, ax.L, sizeof(cplx<T>));
   if (MODE == 2 && red.n > 0) lds = std::max(lds, sizeof(double) * kRedThreads);
-  k_iso_col<T, MODE><<<nblk, kFftThreads, lds, st>>>(spec, f, t, ax, tw, cb, stride, outer_stride, nouter, nin, nout,
-                                                     epot, red);
+  if (fixed == 128)
+    k_iso_col<T, MODE, 128><<<nblk, kFftThreads, lds, st>>>(spec, f, t, ax, tw, cb, stride, outer_stride, nouter,
+                                                            nin, nout, epot, red);
+  else
+    k_iso_col<T, MODE><<<nblk, kFftThreads, lds, st>>>(spec, f, t, ax, tw, cb, stride, outer_stride, nouter, nin,
+                                                       nout, epot, red);
 }
 
 }  // namespace
@@ -306,11 +362,16 @@ void launch_iso_fwd(const SrcSlot* src, int parity, cplx<T>* spec, const IsoGeom
                     hipStream_t st) {
   const int nrows = f.ny * f.nz * f.nruns;
   const int nblk = (nrows + f.rows_per_block - 1) / f.rows_per_block;
-  k_iso_x_fwd<T, false><<<nblk, kFftThreads, x_lds(f, sizeof(cplx<T>), false), st>>>(src, parity, spec, f, t, 0.0,
-                                                                                     0.0);
+  const int fixed = iso_fixed<T>(f);
+  const size_t xl = x_lds(f, sizeof(cplx<T>), false);
+  if (fixed == 128)
+    k_iso_x_fwd<T, false, 128><<<nblk, kFftThreads, xl, st>>>(src, parity, spec, f, t, 0.0, 0.0);
+  else
+    k_iso_x_fwd<T, false><<<nblk, kFftThreads, xl, st>>>(src, parity, spec, f, t, 0.0, 0.0);
   // y: planes z < nz, lines y < ny read, all 2ny stored
   const size_t row = f.px, plane = (size_t)f.px * f.py;
-  col_pass<T, 0>(spec, f, t, f.ay, t.tw_y, f.cols_y, row, plane, f.nz, f.nruns, f.ny, f.py, nullptr, RedJob{}, st);
+  col_pass<T, 0>(spec, f, t, f.ay, t.tw_y, f.cols_y, row, plane, f.nz, f.nruns, f.ny, f.py, nullptr, RedJob{}, st,
+                 fixed);
 }
 
 template <typename T>
@@ -319,7 +380,7 @@ void launch_iso_z(cplx<T>* spec, const IsoGeom& f, const IsoTables<T>& t, double
   // lines z < nz read; z = 0 .. nz and 2nz - 1 stored
   const size_t row = f.px, plane = (size_t)f.px * f.py;
   col_pass<T, 2>(spec, f, t, f.az, t.tw_z, f.cols_z, plane, row, f.py, f.nruns, f.nz, f.nz + 2, epot_partials, red,
-                 st);
+                 st, iso_fixed<T>(f));
 }
 
 template <typename T>
@@ -327,13 +388,17 @@ void launch_iso_inv(cplx<T>* spec, T* phi_ext, const IsoGeom& f, const IsoTables
                     hipStream_t st) {
   const size_t row = f.px, plane = (size_t)f.px * f.py;
   // y: the nz + 2 kept planes, all 2ny lines read, y = 0 .. ny and 2ny - 1 stored
+  const int fixed = iso_fixed<T>(f);
   col_pass<T, 1>(spec, f, t, f.ay, t.tw_y, f.cols_y, row, plane, f.nz + 2, f.nruns, f.py, f.ny + 2, nullptr,
-                 RedJob{}, st);
+                 RedJob{}, st, fixed);
   const int nrows = (f.ny + 2) * (f.nz + 2) * f.nruns;
   const int nblk = (nrows + f.rows_per_block - 1) / f.rows_per_block + fin.n;
   size_t lds = x_lds(f, sizeof(cplx<T>), true);
   if (fin.n > 0) lds = std::max(lds, sizeof(double) * kFinLds);
-  k_iso_x_inv<T><<<nblk, kFftThreads, lds, st>>>(spec, phi_ext, f, t, fin);
+  if (fixed == 128)
+    k_iso_x_inv<T, 128><<<nblk, kFftThreads, lds, st>>>(spec, phi_ext, f, t, fin);
+  else
+    k_iso_x_inv<T><<<nblk, kFftThreads, lds, st>>>(spec, phi_ext, f, t, fin);
 }
 
 void launch_iso_green(cplx<double>* work, const IsoGeom& f, const IsoTables<double>& t, double* green, double h,
@@ -345,8 +410,8 @@ void launch_iso_green(cplx<double>* work, const IsoGeom& f, const IsoTables<doub
   k_iso_x_fwd<double, true><<<nblk, kFftThreads, x_lds(f, sizeof(cplx<double>), false), st>>>(
       nullptr, 0, work, f, t, gscale, gscale * c0);
   const size_t row = f.px, plane = (size_t)f.px * f.py;
-  col_pass<double, 0>(work, f, t, f.ay, t.tw_y, f.cols_y, row, plane, f.pz, 1, f.py, f.py, nullptr, RedJob{}, st);
-  col_pass<double, 0>(work, f, t, f.az, t.tw_z, f.cols_z, plane, row, f.py, 1, f.pz, f.pz, nullptr, RedJob{}, st);
+  col_pass<double, 0>(work, f, t, f.ay, t.tw_y, f.cols_y, row, plane, f.pz, 1, f.py, f.py, nullptr, RedJob{}, st, 0);
+  col_pass<double, 0>(work, f, t, f.az, t.tw_z, f.cols_z, plane, row, f.py, 1, f.pz, f.pz, nullptr, RedJob{}, st, 0);
   k_iso_green_extract<<<1024, 256, 0, st>>>(work, green, f);
 }
 
