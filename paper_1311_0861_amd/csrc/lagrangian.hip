@@ -72,23 +72,23 @@ __device__ __forceinline__ void block_reduce_store(Acc& a, gptr<double> slots, i
 
 // ---- end-of-step cell terms -------------------------------------------------
 
-// Gas: kappa integrand |E - e - |m|^2/(2 rho)| (Sec. 2.4) and kinetic energy.
+// Gas: kappa integrand |E - e - |m|^2/(2 rho)| (Sec. 2.4) and kinetic energy
+// (ir = 1 / rho: every division of a cell's end-of-step terms is by its
+// density, so one reciprocal serves them all).
 template <typename T>
-__device__ __forceinline__ T gas_kappa(double rho, const T m[3], T E, T e, T& ekin) {
-  const T rr = T(rho);
-  ekin = (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / (T(2) * rr);
+__device__ __forceinline__ T gas_kappa(T ir, const T m[3], T E, T e, T& ekin) {
+  ekin = T(0.5) * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) * ir;
   return fabs(E - e - ekin);
 }
 
 // Gas diagnostics of a finished cell: signal speed, sums, error bits.
 template <typename T>
-__device__ __forceinline__ void gas_terms(Acc& a, double rho, const T m[3], T E, T e, T gamma) {
-  const T rr = T(rho);
+__device__ __forceinline__ void gas_terms(Acc& a, double rho, T ir, const T m[3], T E, T e, T gamma) {
   const T p = (gamma - T(1)) * e;
-  const T cs = sqrt(fmax(gamma * p / rr, T(0)));
+  const T cs = sqrt(fmax(gamma * p * ir, T(0)));
   T sp = T(0);
 #pragma unroll
-  for (int d = 0; d < 3; d++) sp = fmax(sp, fabs(m[d] / rr) + cs);
+  for (int d = 0; d < 3; d++) sp = fmax(sp, fabs(m[d]) * ir + cs);
   a.v[S_SPEED] = fmax(a.v[S_SPEED], (double)sp);
   a.v[S_MASS] += rho;
 #pragma unroll
@@ -107,26 +107,24 @@ __device__ __forceinline__ void gas_terms(Acc& a, double rho, const T m[3], T E,
 // Stars / dark matter: thermal tensor T = W - q q / n and the kappa integrand
 // sum_ij |T_ij - Pi_ij| (Sec. 2.4).
 template <typename T>
-__device__ __forceinline__ T bme_kappa(double n, const T q[3], const T P[6], const T W[6], T Tt[6]) {
-  const T rn = T(n);
+__device__ __forceinline__ T bme_kappa(T iv, const T q[3], const T P[6], const T W[6], T Tt[6]) {
   T kb = T(0);
 #pragma unroll
   for (int a = 0; a < 3; a++)
 #pragma unroll
     for (int b = a; b < 3; b++) {
       const int s = sym(a, b);
-      Tt[s] = W[s] - q[a] * q[b] / rn;
+      Tt[s] = W[s] - q[a] * q[b] * iv;
       kb += fabs(Tt[s] - P[s]);
     }
   return kb;
 }
 
 template <typename T>
-__device__ __forceinline__ void bme_terms(Acc& a, double n, const T q[3], const T P[6], const T W[6]) {
-  const T rn = T(n);
+__device__ __forceinline__ void bme_terms(Acc& a, double n, T iv, const T q[3], const T P[6], const T W[6]) {
   T sp = T(0);
 #pragma unroll
-  for (int d = 0; d < 3; d++) sp = fmax(sp, fabs(q[d] / rn) + sqrt(fmax(T(3) * P[sym(d, d)] / rn, T(0))));
+  for (int d = 0; d < 3; d++) sp = fmax(sp, fabs(q[d]) * iv + sqrt(fmax(T(3) * P[sym(d, d)] * iv, T(0))));
   a.v[S_SPEED] = fmax(a.v[S_SPEED], (double)sp);
   a.v[S_MASS] += n;
 #pragma unroll
@@ -254,7 +252,8 @@ __device__ __forceinline__ void gas_finish(Acc& acc, const RunDev<T>& R, int par
   const T E = nv[3];
   T e = nv[4];
   T ekin;
-  acc.v[S_KAPPA] += (double)gas_kappa(rho, m, E, e, ekin);
+  const T ir = rcp(T(rho));
+  acc.v[S_KAPPA] += (double)gas_kappa(ir, m, E, e, ekin);
   if (R.ph.eta >= 0.0) {
     const T et = E - ekin;
     if (et > (T)R.ph.eta * E) {
@@ -268,7 +267,7 @@ __device__ __forceinline__ void gas_finish(Acc& acc, const RunDev<T>& R, int par
   for (int d = 0; d < 3; d++) st_at(as_global(R.cur[oidx(GP_MX + d)]), z, xy, m[d]);
   st_at(as_global(R.cur[oidx(GP_E)]), z, xy, E);
   st_at(as_global(R.cur[oidx(GP_EINT)]), z, xy, e);
-  gas_terms(acc, rho, m, E, e, (T)R.ph.gamma);
+  gas_terms(acc, rho, ir, m, E, e, (T)R.ph.gamma);
 }
 
 // Stars / dark matter epilogue, streamed over the six stress / energy pairs
@@ -277,7 +276,7 @@ __device__ __forceinline__ void gas_finish(Acc& acc, const RunDev<T>& R, int par
 template <typename T, typename Next>
 __device__ __forceinline__ void bme_stream(Acc& acc, const RunDev<T>& R, int parity, size_t z, uint32_t xy,
                                            double n, const T q[3], double out, Next next) {
-  const T rn = T(n);
+  const T iv = rcp(T(n));
   const T eta = (T)R.ph.eta;
   const bool balance = R.ph.eta >= 0.0;
   T kb = T(0), sp = T(0), wtr = T(0);
@@ -291,14 +290,14 @@ __device__ __forceinline__ void bme_stream(Acc& acc, const RunDev<T>& R, int par
       const int m = sym(a, b);
       T P, W;
       next(m, P, W);
-      const T Tt = W - q[a] * q[b] / rn;
+      const T Tt = W - q[a] * q[b] * iv;
       kb += fabs(Tt - P);
       if (a == b) {
         if (balance && Tt > eta * W) {
           P = Tt;
           any = true;
         }
-        sp = fmax(sp, fabs(q[a] / rn) + sqrt(fmax(T(3) * P / rn, T(0))));
+        sp = fmax(sp, fabs(q[a]) * iv + sqrt(fmax(T(3) * P * iv, T(0))));
         stress_ok = stress_ok && (P > T(0));
         wtr += W;
       }
@@ -633,8 +632,9 @@ __device__ __forceinline__ void init_cell(Acc& acc, const RunDev<T>& R, int pari
     for (int d = 0; d < 3; d++) m[d] = f(GP_MX + d);
     const T E = f(GP_E), e = f(GP_EINT);
     T ekin;
-    acc.v[S_KAPPA] += (double)gas_kappa(rho, m, E, e, ekin);
-    gas_terms(acc, rho, m, E, e, (T)R.ph.gamma);
+    const T ir = rcp(T(rho));
+    acc.v[S_KAPPA] += (double)gas_kappa(ir, m, E, e, ekin);
+    gas_terms(acc, rho, ir, m, E, e, (T)R.ph.gamma);
   } else {
     const double n = ld_at(as_global((const double*)R.dens[parity][1]), z, xy);
     T q[3], P[6], W[6], Tt[6];
@@ -645,8 +645,9 @@ __device__ __forceinline__ void init_cell(Acc& acc, const RunDev<T>& R, int pari
       P[a] = f(GP_PXX + a);
       W[a] = f(GP_WXX + a);
     }
-    acc.v[S_KAPPA] += (double)bme_kappa(n, q, P, W, Tt);
-    bme_terms(acc, n, q, P, W);
+    const T iv = rcp(T(n));
+    acc.v[S_KAPPA] += (double)bme_kappa(iv, q, P, W, Tt);
+    bme_terms(acc, n, iv, q, P, W);
   }
 }
 
