@@ -378,20 +378,43 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fft_xy_fwd(const SrcSlot* __r
   const size_t off = ((size_t)z * f.ny + p) * f.nx;
   const dpair* rho = reinterpret_cast<const dpair*>(S.rho[parity] + off);
   const dpair* nb = reinterpret_cast<const dpair*>(S.nb[parity] + off);
-  staged_copy<NT, 8, cplx<T>>(
-      hy * M,
-      [&](int q) {
-        const int j = (int)dm.div(q);
-        const size_t e = (size_t)q + (size_t)j * M;  // pair m of row 2j + p: 2 j M + m
-        const dpair a = gload(rho + e), c = gload(nb + e);
-        return cplx<T>{(T)(a.x + c.x), (T)(a.y + c.y)};
-      },
-      [&](int q, cplx<T> v) {
+  auto source = [&](int q) {
+    const int j = (int)dm.div(q);
+    const size_t e = (size_t)q + (size_t)j * M;  // pair m of row 2j + p: 2 j M + m
+    const dpair a = gload(rho + e), c = gload(nb + e);
+    return cplx<T>{(T)(a.x + c.x), (T)(a.y + c.y)};
+  };
+  constexpr int HALF = PS::HY / 2 * PS::M;  // pairs in half the rows
+  if constexpr (NX > 0 && HALF % NT == 0) {
+    // Every load of the half plane goes out first; the first half of the
+    // rows is staged and transformed while the second half is still
+    // arriving, then the second half (the same row transforms, the same bits).
+    constexpr int PER = HALF / NT;
+    cplx<T> v[2][PER];
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int i = 0; i < PER; i++) v[h][i] = source(h * HALF + (int)threadIdx.x + i * NT);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+#pragma unroll
+      for (int i = 0; i < PER; i++) {
+        const int q = h * HALF + (int)threadIdx.x + i * NT;
         const int j = (int)dm.div(q), m = q - j * M;
-        s.pl[j * hp + m] = v;
-      });
-  lds_barrier();
-  plane_fft<T, PS::M, PS::HY, PS::HP, 1, false>(s.pl, hy, hp, 1, f.ax, s.twx);
+        s.pl[j * hp + m] = v[h][i];
+      }
+      lds_barrier();
+      plane_fft<T, PS::M, PS::HY / 2, PS::HP, 1, false>(s.pl + h * (PS::HY / 2) * PS::HP, hy / 2, hp, 1, f.ax,
+                                                        s.twx);
+    }
+  } else {
+    staged_copy<NT, 8, cplx<T>>(hy * M, source, [&](int q, cplx<T> v) {
+      const int j = (int)dm.div(q), m = q - j * M;
+      s.pl[j * hp + m] = v;
+    });
+    lds_barrier();
+    plane_fft<T, PS::M, PS::HY, PS::HP, 1, false>(s.pl, hy, hp, 1, f.ax, s.twx);
+  }
   // split of each row into its M + 1 bins, pairs (k, M - k) by one thread
   const int H = M / 2 + 1;
   for (int q = threadIdx.x; q < hy * H; q += NT) {

@@ -45,8 +45,13 @@ def test_stage_by_stage_parity(gp, W, case):
     else:
         cfg, st = W.random_periodic(n=(16, 12, 8), seed=3)
     sim, orc = make_pair(cfg, st)
-    # prologue: Phi^0 and tau^0
-    assert _phi_rel(sim, orc) < 1e-12  # FFT rounding grows with log N
+    # prologue: Phi^0 and tau^0.  Phi's bar is 1e-12, not the 1e-13 of the
+    # cell stages: the two FFTs' relative rounding grows with log2 of the
+    # transform lengths, and the GPU and the oracle factor the lengths
+    # differently (radix 8/4/3/2 against radix 2/3), so their rounding paths
+    # differ in every stage.
+    phi_errs = [_phi_rel(sim, orc)]
+    assert phi_errs[-1] < 1e-12
     assert sim.time()[1] == pytest.approx(orc.dt(), rel=1e-13)
     for step in range(2):
         sim.stage(gp.GP_STAGE_EUL)
@@ -57,7 +62,8 @@ def test_stage_by_stage_parity(gp, W, case):
         assert_close_fields(gpu_state(sim), orc.get_state(), 1e-13, "lagrangian step %d" % step, cfg)
         sim.stage(gp.GP_STAGE_POISSON)
         orc.stage(2)
-        assert _phi_rel(sim, orc) < 1e-12  # FFT rounding grows with log N
+        phi_errs.append(_phi_rel(sim, orc))
+        assert phi_errs[-1] < 1e-12
         sim.stage(gp.GP_STAGE_FINALIZE)
         orc.stage(3)
         dg, do = sim.diag()[-1], orc.diag()[-1]
@@ -67,6 +73,7 @@ def test_stage_by_stage_parity(gp, W, case):
         for k in ("mom_x", "mom_y", "mom_z", "outflow_gas", "outflow_bme"):
             assert dg[k] == pytest.approx(do[k], rel=1e-9, abs=1e-14 * (do["mass_gas"] + do["mass_bme"])), k
         assert dg["step"] == do["step"] and dg["err"] == 0
+    say("stage parity", case, "largest Phi relative L1 %.2e" % max(phi_errs))
 
 
 def test_full_step_parity_blob_100_steps(gp, W):
