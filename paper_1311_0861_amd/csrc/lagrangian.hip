@@ -415,6 +415,28 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
         if (tid + q * kBlock < kVTile) dst[tid + q * kBlock] = v * T(0.125);
       }
     };
+    // The gas kernel (with registers to spare) forms a vertex as the sum of
+    // its lower and its upper 2 x 2 cell sums, each summed y-major then x,
+    // and carries the upper sums to the next vertex plane, where they are
+    // the lower ones: half the LDS reads of corner_plane.
+    T hs[kVPer];
+    auto xy_sum = [&](const T (&u)[3][kLY][kLX], int q) {
+      const T* a = &u[0][0][0];
+      const int o = vo[q];
+      T v = a[o];
+      v += a[o + 1];
+      v += a[o + kLX];
+      v += a[o + kLX + 1];
+      return v;
+    };
+    auto corner_plane_carried = [&](const T (&hi)[3][kLY][kLX], T* dst) {
+#pragma unroll
+      for (int q = 0; q < kVPer; q++) {
+        const T h = xy_sum(hi, q);
+        if (tid + q * kBlock < kVTile) dst[tid + q * kBlock] = (hs[q] + h) * T(0.125);
+        hs[q] = h;
+      }
+    };
     // centre and ring of plane z of the three velocities into tile u
     auto stage_velocity = [&](size_t z, uint32_t xy_h, T (&u)[3][kLY][kLX], const T ctr[3]) {
 #pragma unroll
@@ -469,7 +491,13 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
       }
       dn1 = ld_at(din, z1, xy_c);
       lds_barrier();
-      corner_plane(s_u[(k0 + 1) & 1], s_u[k0 & 1], s_v[k0 & 1]);
+      if constexpr (C == COMP_GAS) {
+#pragma unroll
+        for (int q = 0; q < kVPer; q++) hs[q] = xy_sum(s_u[(k0 + 1) & 1], q);
+        corner_plane_carried(s_u[k0 & 1], s_v[k0 & 1]);
+      } else {
+        corner_plane(s_u[(k0 + 1) & 1], s_u[k0 & 1], s_v[k0 & 1]);
+      }
     }
 
     Acc acc;
@@ -523,7 +551,10 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
         }
       }
       lds_barrier();
-      corner_plane(s_u[cu], s_u[nu], s_v[(k + 1) & 1]);
+      if constexpr (C == COMP_GAS)
+        corner_plane_carried(s_u[nu], s_v[(k + 1) & 1]);
+      else
+        corner_plane(s_u[cu], s_u[nu], s_v[(k + 1) & 1]);
       lds_barrier();
 
       if (active) {
