@@ -232,11 +232,7 @@ gp_status gp_debug_stage(gp_sim *sim, int32_t stage);
  * so the kernels do not overlap.  The state advances as with gp_step. */
 gp_status gp_time_kernels(gp_sim *sim, int32_t nsteps, double *ms, int32_t max);
 
-/* Use a captured HIP graph per step (default on).  Results are identical.
- * The graph runs the gas kernels of a step on a branch beside the stars / DM
- * kernels: the library creates one more stream of its own (default priority,
- * non-blocking) when it first captures, used only inside the graph, whose
- * launch on the sim's stream still orders the whole step there. */
+/* Use a captured HIP graph per step (default on).  Results are identical. */
 gp_status gp_use_graph(gp_sim *sim, int32_t enable);
 
 /* Launch configuration of a per-cell kernel (GP_K_EUL_GAS, GP_K_EUL_BME,

@@ -122,10 +122,6 @@ struct gp_batch {
   int prec = GP_FP64;
   hipStream_t st = nullptr;
   bool own_stream = false;
-  // second stream and fork / join events of the captured step (the gas
-  // kernels run on a branch of their own)
-  hipStream_t st2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<RunHost> runs;
   std::vector<SizeClass> classes;
   std::vector<std::pair<void*, size_t>> allocs;
@@ -708,42 +704,12 @@ void run_step_direct(gp_batch* b, Timer* tm, bool allow_tune) {
     enqueue_end<float>(b, tm, 1);
 }
 
-// The captured step: the gas chain (Eulerian, Lagrangian kernels) on a graph
-// branch of its own beside the stars / DM chain.  The two chains share no
-// arrays until the Poisson source is formed from rho and n, so each can start
-// on the chip as the other's workgroups drain (the same kernels and inputs as
-// run_step_direct, hence the same bits).
-template <typename T>
-void enqueue_step_forked(gp_batch* b) {
-  hipStream_t main = b->st;
-  (void)hipEventRecord(b->ev_fork, main);
-  (void)hipStreamWaitEvent(b->st2, b->ev_fork, 0);
-  b->st = b->st2;
-  launch_cell_kernel<T>(b, GP_K_EUL_GAS, b->kcfg[GP_K_EUL_GAS]);
-  launch_cell_kernel<T>(b, GP_K_LAG_GAS, b->kcfg[GP_K_LAG_GAS]);
-  (void)hipEventRecord(b->ev_join, b->st2);
-  b->st = main;
-  launch_cell_kernel<T>(b, GP_K_EUL_BME, b->kcfg[GP_K_EUL_BME]);
-  launch_cell_kernel<T>(b, GP_K_LAG_BME, b->kcfg[GP_K_LAG_BME]);
-  (void)hipStreamWaitEvent(main, b->ev_join, 0);
-  b->parity ^= 1;
-  enqueue_end<T>(b, nullptr, 1);
-}
-
 gp_status build_graph(gp_batch* b, int parity) {
-  if (!b->st2) {
-    HIP_TRY(b, hipStreamCreateWithFlags(&b->st2, hipStreamNonBlocking));
-    HIP_TRY(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-    HIP_TRY(b, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
-  }
   HIP_TRY(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
   const int saved = b->parity;
   b->parity = parity;
   hipGraph_t graph = nullptr;
-  if (b->prec == GP_FP64)
-    enqueue_step_forked<double>(b);
-  else
-    enqueue_step_forked<float>(b);
+  run_step_direct(b, nullptr, false);
   hipError_t e = hipStreamEndCapture(b->st, &graph);
   b->parity = saved;
   if (e != hipSuccess) return hip_fail(b, e, "hipStreamEndCapture");
@@ -1150,9 +1116,6 @@ void engine_free(gp_batch* b) {
   for (auto& a : b->allocs) (void)hipFree(a.first);
   b->allocs.clear();
   if (b->own_stream && b->st) (void)hipStreamDestroy(b->st);
-  if (b->st2) (void)hipStreamDestroy(b->st2);
-  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
 }
 
 gp_status engine_set_field(gp_batch* b, int r, int32_t field, const void* src, int32_t dtype, int32_t on_device) {

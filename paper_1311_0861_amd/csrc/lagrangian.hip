@@ -386,11 +386,11 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
     auto plane = [&](int k) -> size_t { return plane_at(g, k, g.bc[2]); };
 
     // Corner velocities.  Vertex (I, J, K) is the mean of the 8 cells I-1..I,
-    // J-1..J, K-1..K (boundary rule outside the grid), summed z-major, then y,
-    // then x; the cells come from the velocity tiles (with their rings) of
-    // planes K-1 and K.  Entry e of the vertex tile (component e / (kVX kVY),
-    // vertex row and column within it) is formed by thread e mod kBlock; vo[]
-    // is the tile offset of its lower-left cell.
+    // J-1..J, K-1..K (boundary rule outside the grid); the cells come from
+    // the velocity tiles (with their rings) of planes K-1 and K.  Entry e of
+    // the vertex tile (component e / (kVX kVY), vertex row and column within
+    // it) is formed by thread e mod kBlock; vo[] is the tile offset of its
+    // lower-left cell.
     int vo[kVPer];
 #pragma unroll
     for (int q = 0; q < kVPer; q++) {
@@ -398,27 +398,10 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
       const int d = e / (kVX * kVY), rem = e % (kVX * kVY);
       vo[q] = (d * kLY + rem / kVX) * kLX + rem % kVX;
     }
-    auto corner_plane = [&](const T (&lo)[3][kLY][kLX], const T (&hi)[3][kLY][kLX], T* dst) {
-      const T* a = &lo[0][0][0];
-      const T* b = &hi[0][0][0];
-#pragma unroll
-      for (int q = 0; q < kVPer; q++) {
-        const int o = vo[q];
-        T v = a[o];
-        v += a[o + 1];
-        v += a[o + kLX];
-        v += a[o + kLX + 1];
-        v += b[o];
-        v += b[o + 1];
-        v += b[o + kLX];
-        v += b[o + kLX + 1];
-        if (tid + q * kBlock < kVTile) dst[tid + q * kBlock] = v * T(0.125);
-      }
-    };
-    // The gas kernel (with registers to spare) forms a vertex as the sum of
-    // its lower and its upper 2 x 2 cell sums, each summed y-major then x,
-    // and carries the upper sums to the next vertex plane, where they are
-    // the lower ones: half the LDS reads of corner_plane.
+    // The 8-cell sum is the plane K-1 sum plus the plane K sum of the 2 x 2
+    // cells, each summed y-major then x.  The plane K sums stay in registers
+    // as the plane K-1 sums of the next vertex plane (half the LDS reads of
+    // summing all eight cells per vertex plane).
     T hs[kVPer];
     auto xy_sum = [&](const T (&u)[3][kLY][kLX], int q) {
       const T* a = &u[0][0][0];
@@ -429,7 +412,7 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
       v += a[o + kLX + 1];
       return v;
     };
-    auto corner_plane_carried = [&](const T (&hi)[3][kLY][kLX], T* dst) {
+    auto corner_plane = [&](const T (&hi)[3][kLY][kLX], T* dst) {
 #pragma unroll
       for (int q = 0; q < kVPer; q++) {
         const T h = xy_sum(hi, q);
@@ -491,13 +474,9 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
       }
       dn1 = ld_at(din, z1, xy_c);
       lds_barrier();
-      if constexpr (C == COMP_GAS) {
 #pragma unroll
-        for (int q = 0; q < kVPer; q++) hs[q] = xy_sum(s_u[(k0 + 1) & 1], q);
-        corner_plane_carried(s_u[k0 & 1], s_v[k0 & 1]);
-      } else {
-        corner_plane(s_u[(k0 + 1) & 1], s_u[k0 & 1], s_v[k0 & 1]);
-      }
+      for (int q = 0; q < kVPer; q++) hs[q] = xy_sum(s_u[(k0 + 1) & 1], q);
+      corner_plane(s_u[k0 & 1], s_v[k0 & 1]);
     }
 
     Acc acc;
@@ -551,10 +530,7 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
         }
       }
       lds_barrier();
-      if constexpr (C == COMP_GAS)
-        corner_plane_carried(s_u[nu], s_v[(k + 1) & 1]);
-      else
-        corner_plane(s_u[cu], s_u[nu], s_v[(k + 1) & 1]);
+      corner_plane(s_u[nu], s_v[(k + 1) & 1]);
       lds_barrier();
 
       if (active) {
