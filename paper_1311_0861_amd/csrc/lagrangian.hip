@@ -535,22 +535,27 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
 
       if (active) {
         CellFlux<T> cf;
-        // A+ / A- of the six faces from the corners in vertex planes k, k+1
+        // A+ / A- of the six faces from the corners in vertex planes k, k+1:
+        // a quarter of the sums of max(v, 0) and of min(v, 0) over a face's
+        // four corners, formed as (S + |S|') / 8 and (S - |S|') / 8 from the
+        // sum S of the corner values and the sum |S|' of their magnitudes
+        // (exactly 0 where all four corners share a sign); both cells of a
+        // face sum its corners in the same order.
 #pragma unroll
         for (int d = 0; d < 2; d++) {
-          T pos[2] = {T(0), T(0)}, neg[2] = {T(0), T(0)};
+          T sum[2] = {T(0), T(0)}, mag[2] = {T(0), T(0)};
 #pragma unroll
           for (int s = 0; s < 8; s++) {
             const int sx = s & 1, sy = (s >> 1) & 1, sz = (s >> 2) & 1;
             const T v = s_v[(k + sz) & 1][d * kVX * kVY + (ly + sy) * kVX + lx + sx];
             const int side = d == 0 ? sx : sy;
-            pos[side] += fmax(v, T(0));
-            neg[side] += fmin(v, T(0));
+            sum[side] += v;
+            mag[side] += fabs(v);
           }
 #pragma unroll
           for (int side = 0; side < 2; side++) {
-            cf.ap[d][side] = pos[side] * T(0.25);
-            cf.am[d][side] = neg[side] * T(0.25);
+            cf.ap[d][side] = (sum[side] + mag[side]) * T(0.125);
+            cf.am[d][side] = (sum[side] - mag[side]) * T(0.125);
           }
         }
         // z faces: the four corners of vertex plane K in the same order.  In
@@ -559,15 +564,15 @@ __global__ void __launch_bounds__(kBlock, (lag_waves<C, T>())) k_lagrangian(cons
         // item; the stars / DM kernel, at its register limit, recomputes it
         // (carrying measured 1% slower there, 2% faster for the gas).
         auto z_side = [&](int kv, T& ap, T& am) {
-          T pos = T(0), neg = T(0);
+          T sum = T(0), mag = T(0);
 #pragma unroll
           for (int s = 0; s < 4; s++) {
             const T v = s_v[kv & 1][2 * kVX * kVY + (ly + (s >> 1)) * kVX + lx + (s & 1)];
-            pos += fmax(v, T(0));
-            neg += fmin(v, T(0));
+            sum += v;
+            mag += fabs(v);
           }
-          ap = pos * T(0.25);
-          am = neg * T(0.25);
+          ap = (sum + mag) * T(0.125);
+          am = (sum - mag) * T(0.125);
         };
         if (C != COMP_GAS || k == k0) z_side(k, apz, amz);
         cf.ap[2][0] = apz;
