@@ -111,23 +111,28 @@ __device__ __forceinline__ void bme_face(const BmeSide<T>& L, const BmeSide<T>& 
   ps[B_] = fma(C, cross_p, fma(dub, Z2, C));
 }
 
-// Adds the contribution of one face normal to axis D, with sign sg (+1 for
-// the plus face, -1 for the minus face), to the divergences of the centre
-// cell: d_D of Pi*_{iD}, of Pi*_{jD} u*_i + Pi*_{iD} u*_j, and the Pi_{jD} u*_i
-// + Pi_{iD} u*_j terms.  Faces are folded in one at a time, so only one face
-// state is live.
+// Adds the contributions of the two faces normal to axis D (interface states
+// usm, psm of the minus face and usp, psp of the plus face) to the
+// divergences of the centre cell: d_D of Pi*_{iD}, of Pi*_{jD} u*_i +
+// Pi*_{iD} u*_j, and the Pi_{jD} u*_i + Pi_{iD} u*_j terms.  The last take
+// the centre's own Pi, so the two faces combine into Pi_{jD} (u*+_i - u*-_i)
+// + Pi_{iD} (u*+_j - u*-_j).
 template <int D, typename T>
-__device__ __forceinline__ void bme_face_add(const T us[3], const T ps[3], T sg, const BmeCentre<T>& C, T dq[3],
-                                             T dW[6], T dPi[6]) {
+__device__ __forceinline__ void bme_face_pair(const T usm[3], const T psm[3], const T usp[3], const T psp[3],
+                                              const BmeCentre<T>& C, T dq[3], T dW[6], T dPi[6]) {
+  T du[3];
 #pragma unroll
-  for (int i = 0; i < 3; i++) dq[i] += sg * ps[i];
+  for (int i = 0; i < 3; i++) {
+    dq[i] += psp[i] - psm[i];
+    du[i] = usp[i] - usm[i];
+  }
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
     for (int j = i; j < 3; j++) {
       const int m = sym(i, j);
-      dW[m] += sg * (ps[j] * us[i] + ps[i] * us[j]);
-      dPi[m] += sg * (C.P[sym(j, D)] * us[i] + C.P[sym(i, D)] * us[j]);
+      dW[m] += (psp[j] * usp[i] + psp[i] * usp[j]) - (psm[j] * usm[i] + psm[i] * usm[j]);
+      dPi[m] += C.P[sym(j, D)] * du[i] + C.P[sym(i, D)] * du[j];
     }
 }
 
@@ -455,20 +460,22 @@ __global__ void __launch_bounds__(kBlock, 2) k_eul_bme(const RunDev<T>* __restri
         T dq[3] = {T(0), T(0), T(0)};
         T dW[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         T dPi[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        T us[3], ps[3];
-        bme_face<T, 0>(bme_at<0>(s_p, ly + 1, lx), centre_side<0>(C), us, ps);
-        bme_face_add<0>(us, ps, T(-1), C, dq, dW, dPi);
-        bme_face<T, 0>(centre_side<0>(C), bme_at<0>(s_p, ly + 1, lx + 2), us, ps);
-        bme_face_add<0>(us, ps, T(1), C, dq, dW, dPi);
-        bme_face<T, 1>(bme_at<1>(s_p, ly, lx + 1), centre_side<1>(C), us, ps);
-        bme_face_add<1>(us, ps, T(-1), C, dq, dW, dPi);
-        bme_face<T, 1>(centre_side<1>(C), bme_at<1>(s_p, ly + 2, lx + 1), us, ps);
-        bme_face_add<1>(us, ps, T(1), C, dq, dW, dPi);
-        bme_face_add<2>(usz, psz, T(-1), C, dq, dW, dPi);
+        T usm[3], psm[3], usp[3], psp[3];
+        bme_face<T, 0>(bme_at<0>(s_p, ly + 1, lx), centre_side<0>(C), usm, psm);
+        bme_face<T, 0>(centre_side<0>(C), bme_at<0>(s_p, ly + 1, lx + 2), usp, psp);
+        bme_face_pair<0>(usm, psm, usp, psp, C, dq, dW, dPi);
+        bme_face<T, 1>(bme_at<1>(s_p, ly, lx + 1), centre_side<1>(C), usm, psm);
+        bme_face<T, 1>(centre_side<1>(C), bme_at<1>(s_p, ly + 2, lx + 1), usp, psp);
+        bme_face_pair<1>(usm, psm, usp, psp, C, dq, dW, dPi);
         T pn[kBmePrims];
         prims(n_n, q_n, P_n, pn);
-        bme_face<T, 2>(centre_side<2>(C), bme_of<2>(pn), usz, psz);
-        bme_face_add<2>(usz, psz, T(1), C, dq, dW, dPi);
+        bme_face<T, 2>(centre_side<2>(C), bme_of<2>(pn), usp, psp);
+        bme_face_pair<2>(usz, psz, usp, psp, C, dq, dW, dPi);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+          usz[i] = usp[i];
+          psz[i] = psp[i];
+        }
         T grad[3] = {T(0), T(0), T(0)};
         if (grav) {
           grad[0] = (s_phi[ly + 1][lx + 2] - s_phi[ly + 1][lx]) * r2h;
