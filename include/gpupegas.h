@@ -239,7 +239,7 @@ gp_status gp_use_graph(gp_sim *sim, int32_t enable);
  * GP_K_LAG_GAS or GP_K_LAG_BME): the work is a list of (run, tile column,
  * chunk of z planes) items walked by a persistent grid of workgroups.  The
  * autotuner picks, during the first step, the tile shape (0: 64 x 4 cells,
- * 1: 32 x 8), the z-chunk cap (16, 32 or 64 planes; an item reads the plane
+ * 1: 32 x 8), the z-chunk cap (8, 16, 32 or 64 planes; an item reads the plane
  * below and above its chunk as its z halo) and the grid size (one workgroup
  * per item, or 8192 / 4096 / 2048 / 1024), each kernel by its own timing.
  * With the environment variable GPUPEGAS_TUNE_CACHE naming a file when the

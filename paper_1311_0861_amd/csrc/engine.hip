@@ -54,9 +54,9 @@ constexpr int kTunedKernels = 4;  // the per-cell kernels
 // z-chunk caps the autotuner tries (the "halo" shape of a work item): an item
 // of cz planes also reads the plane below and above it, 2 / cz of re-reads;
 // shorter chunks give more items to spread over the chip.
-constexpr int kNumCaps = 3;
-constexpr int kCaps[kNumCaps] = {16, 32, 64};
-constexpr int kDefaultCap = 1;  // 32 planes
+constexpr int kNumCaps = 4;
+constexpr int kCaps[kNumCaps] = {8, 16, 32, 64};
+constexpr int kDefaultCap = 2;  // 32 planes
 // Per-kernel launch configuration: tile shape (TileShape index), z-chunk cap
 // (index into kCaps) and persistent grid size.
 struct TileCfg {
