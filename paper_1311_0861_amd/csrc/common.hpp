@@ -176,6 +176,23 @@ __device__ __forceinline__ float rcp(float x) {
   const float e = __builtin_fmaf(-x, r, 1.0f);
   return __builtin_fmaf(r, e, r);
 }
+// Reciprocal square root by Newton's iteration y <- y + (y / 2)(1 - x y^2)
+// from the hardware estimate (two steps in FP64, one in FP32), for positive
+// x: an impedance sqrt(x) and its reciprocal then cost one estimate, its
+// refinement and a product x y instead of an IEEE square root and a
+// reciprocal of it.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = __builtin_fma(-x * y, y, 1.0);
+  y = __builtin_fma(0.5 * y, e, y);
+  e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float e = __builtin_fmaf(-x * y, y, 1.0f);
+  return __builtin_fmaf(0.5f * y, e, y);
+}
 template <typename T>
 __device__ __forceinline__ gptr<T> as_global(T* p) {
   return (gptr<T>)p;

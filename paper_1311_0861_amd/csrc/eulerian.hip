@@ -43,8 +43,9 @@ template <typename T>
 __device__ __forceinline__ void gas_face(const GasPrim<T>& L, const GasPrim<T>& R, T gamma, T& V, T& P) {
 #pragma clang fp contract(off)
   const T pl = L.p, pr = R.p;
-  const T z = sqrt(gamma * (pl + pr) * L.rho * R.rho * rcp(L.rho + R.rho));
-  const T rz = rcp(z);
+  const T zz = gamma * (pl + pr) * L.rho * R.rho * rcp(L.rho + R.rho);
+  const T rz = rsqrt_nr(zz);
+  const T z = zz * rz;
   V = fma(T(0.5) * (pl - pr), rz, T(0.5) * (L.vd + R.vd));
   P = fma(T(0.5) * (L.vd - R.vd), z, T(0.5) * (pl + pr));
 }
@@ -90,8 +91,9 @@ __device__ __forceinline__ void bme_face(const BmeSide<T>& L, const BmeSide<T>& 
   const T A = T(0.5) * (L.pdd + R.pdd);
   const T B = T(0.5) * (L.pda + R.pda);
   const T C = T(0.5) * (L.pdb + R.pdb);
-  const T Z1 = sqrt(T(3) * nbar * A);  // sqrt(3 n Pi_DD): fast wave impedance
-  const T rZ1 = rcp(Z1);
+  const T Z1sq = T(3) * nbar * A;
+  const T rZ1 = rsqrt_nr(Z1sq);
+  const T Z1 = Z1sq * rZ1;  // sqrt(3 n Pi_DD): fast wave impedance
   const T Z2 = Z1 * T(0.57735026918962576451);   // sqrt(n Pi_DD): slow (shear) impedance
   const T rZ2 = rZ1 * T(1.7320508075688772935);
   const T rA = rcp(A);
