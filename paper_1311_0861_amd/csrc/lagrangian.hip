@@ -17,6 +17,8 @@
 // precisions.  The gas and the stars / dark matter advect with their own
 // corner velocities and share nothing else in this stage, so each has its own
 // kernel (6 and 16 fields), which halves the live state of a joint one.
+#include <limits>
+
 #include "column.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -72,6 +74,16 @@ __device__ __forceinline__ void block_reduce_store(Acc& a, gptr<double> slots, i
 
 // ---- end-of-step cell terms -------------------------------------------------
 
+// sqrt(max(x, 0)) for the signal speeds, from the Newton-refined reciprocal
+// square root, without a branch: 0 where x is not positive (NaN included, as
+// fmax gives); a subnormal x gives x / sqrt(smallest normal), as negligible
+// beside the velocity it is added to as its square root would be.
+template <typename T>
+__device__ __forceinline__ T sqrt_pos(T x) {
+  const T y = x * rsqrt_nr(fmax(x, std::numeric_limits<T>::min()));
+  return x > T(0) ? y : T(0);
+}
+
 // Gas: kappa integrand |E - e - |m|^2/(2 rho)| (Sec. 2.4) and kinetic energy
 // (ir = 1 / rho: every division of a cell's end-of-step terms is by its
 // density, so one reciprocal serves them all).
@@ -85,7 +97,7 @@ __device__ __forceinline__ T gas_kappa(T ir, const T m[3], T E, T e, T& ekin) {
 template <typename T>
 __device__ __forceinline__ void gas_terms(Acc& a, double rho, T ir, const T m[3], T E, T e, T gamma) {
   const T p = (gamma - T(1)) * e;
-  const T cs = sqrt(fmax(gamma * p * ir, T(0)));
+  const T cs = sqrt_pos(gamma * p * ir);
   T sp = T(0);
 #pragma unroll
   for (int d = 0; d < 3; d++) sp = fmax(sp, fabs(m[d]) * ir + cs);
@@ -124,7 +136,7 @@ template <typename T>
 __device__ __forceinline__ void bme_terms(Acc& a, double n, T iv, const T q[3], const T P[6], const T W[6]) {
   T sp = T(0);
 #pragma unroll
-  for (int d = 0; d < 3; d++) sp = fmax(sp, fabs(q[d]) * iv + sqrt(fmax(T(3) * P[sym(d, d)] * iv, T(0))));
+  for (int d = 0; d < 3; d++) sp = fmax(sp, fabs(q[d]) * iv + sqrt_pos(T(3) * P[sym(d, d)] * iv));
   a.v[S_SPEED] = fmax(a.v[S_SPEED], (double)sp);
   a.v[S_MASS] += n;
 #pragma unroll
@@ -297,7 +309,7 @@ __device__ __forceinline__ void bme_stream(Acc& acc, const RunDev<T>& R, int par
           P = Tt;
           any = true;
         }
-        sp = fmax(sp, fabs(q[a]) * iv + sqrt(fmax(T(3) * P * iv, T(0))));
+        sp = fmax(sp, fabs(q[a]) * iv + sqrt_pos(T(3) * P * iv));
         stress_ok = stress_ok && (P > T(0));
         wtr += W;
       }
