@@ -96,7 +96,7 @@ __device__ __forceinline__ void bme_face(const BmeSide<T>& L, const BmeSide<T>& 
   const T Z1 = Z1sq * rZ1;  // sqrt(3 n Pi_DD): fast wave impedance
   const T Z2 = Z1 * T(0.57735026918962576451);   // sqrt(n Pi_DD): slow (shear) impedance
   const T rZ2 = rZ1 * T(1.7320508075688772935);
-  const T rA = rcp(A);
+  const T rA = T(3) * nbar * (rZ1 * rZ1);  // 1 / A, as rZ1^2 = 1 / (3 n A)
   const T dpdd = T(0.5) * (L.pdd - R.pdd);
   const T dpda = T(0.5) * (L.pda - R.pda);
   const T dpdb = T(0.5) * (L.pdb - R.pdb);
